@@ -1,0 +1,289 @@
+/*
+ * nasch.h -- C ABI of libnasch, the MI355X (gfx950) implementation of the
+ * Nagel-Schreckenberg (NaSch) traffic model on a circular road.
+ *
+ * The operation (van Zon & Ponce, "Parallelizing a 1-Dim Nagel-Schreckenberg
+ * Traffic Model", Handout section "The Nagel-Schreckenberg traffic model",
+ * rules 1-4 and their summary system): every time step, every car
+ *   1. speeds up by one if below vmax,
+ *   2. slows to d-1 if the car in front is d cells ahead and v >= d,
+ *   3. if v > 0, slows by one with probability p (a uniform r < p accepts),
+ *   4. moves v cells forward on the ring of L cells (periodic boundary,
+ *      Handout section "Starter Code").
+ * All cars update synchronously from the state at the start of the step.
+ *
+ * Randomness.  The uniform r of rule 3 for the car that starts step t in cell
+ * x is a 32-bit integer R(seed, replica, t, x), compared as R < thr with
+ * thr = floor(p * 2^32).  R is built from Philox4x32-10 (Salmon et al., SC'11)
+ * with key (seed mod 2^32, seed >> 32):
+ *   bits 31..28 = bit (x mod 32) of output words 0..3 (word 0 on top) of
+ *                 Philox(counter = (x div 32, t, replica, 1));
+ *   bits 27..0  = output word 0 of Philox(counter = (x, t, replica, 2)) >> 4.
+ * Results therefore do not depend on thread count, launch shape, temporal
+ * block depth, representation or batch composition (the reproducibility the
+ * paper demands in "Concepts Covered" and assignment item 1).
+ *
+ * Initial state (the paper only says "random positions", Handout "Starter
+ * Code"): car i < N starts in cell pi(i), where pi is a 4-round balanced
+ * Feistel permutation on b bits (b = ceil(log2 L) rounded up to even, >= 2),
+ * round function word 0 of Philox((half, round, replica, 3)) masked to b/2
+ * bits, restricted to [0, L) by cycle-walking.  Initial velocity: 0, or
+ * floor(w * (vmax+1) / 2^32) with w = word 0 of Philox((x, 0, replica, 4)).
+ *
+ * Grid representation ("Concepts Covered"): one uint8 per cell, 0xFF = empty,
+ * else the velocity of the car in the cell.  Agent representation: int32
+ * positions x[N] in road order (cyclically sorted) and uint8 velocities v[N].
+ * F(t) = sum of the velocities after step t (the flux of step t).
+ *
+ * Conventions for every entry point:
+ *   - Return 0 on success or a negative NASCH_E* code; no exception crosses
+ *     the ABI.  After NASCH_EDEVICE the HIP error code is kept in the handle
+ *     (nasch_last_device_error).
+ *   - Handles are owned by the library and released by the matching *_free /
+ *     *_destroy call.  Every output pointer is caller-owned host memory of the
+ *     stated size unless the name says "device".
+ *   - Stepping calls are asynchronous on the handle's stream; calls that hand
+ *     results to the host synchronise that stream first.
+ *   - A handle must not be used from two threads at once; separate handles
+ *     may be used concurrently.
+ *   - The library uses the HIP device that is current when the handle is
+ *     created.
+ */
+#ifndef NASCH_H
+#define NASCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define NASCH_OK        0
+#define NASCH_EINVAL   (-1)  /* an argument is out of range or inconsistent   */
+#define NASCH_ENOMEM   (-2)  /* device or host allocation failed             */
+#define NASCH_EDEVICE  (-3)  /* a HIP call failed; see nasch_last_device_error */
+#define NASCH_ERANGE   (-4)  /* the step counter would reach 2^32            */
+#define NASCH_ESTATE   (-5)  /* the handle is not in a state for this call    */
+#define NASCH_EBUSY    (-6)  /* the request cannot be admitted right now      */
+#define NASCH_ENOTFOUND (-7) /* no such replica / request                    */
+
+/* ---- limits ------------------------------------------------------------ */
+#define NASCH_MAX_VMAX  8u            /* kernels are specialised for vmax <= 8 */
+#define NASCH_MAX_L     0x7FFFFFFFull /* L < 2^31: positions are int32         */
+
+/* ---- option values ----------------------------------------------------- */
+#define NASCH_REP_GRID   0u  /* uint8 per cell                            */
+#define NASCH_REP_AGENT  1u  /* int32 x[N], uint8 v[N]                    */
+#define NASCH_INIT_V_ZERO    0u
+#define NASCH_INIT_V_UNIFORM 1u
+#define NASCH_KERNEL_AUTO    0u /* autotuned: the temporal-blocked kernel, (k, q) chosen by timing */
+#define NASCH_KERNEL_ONESTEP 1u /* grid: one byte-wise step per launch (k = 1, no blocking) */
+#define NASCH_KERNEL_KSTEP   2u /* grid: k steps per launch, bit-sliced, k*vmax halo; agent: k steps per launch */
+
+typedef struct nasch_sim nasch_sim;
+
+typedef struct {
+    uint32_t replica;  /* Philox stream id (counter word 2); default 0; never a batch slot */
+    uint32_t rep;      /* NASCH_REP_GRID or NASCH_REP_AGENT                                */
+    uint32_t init_v;   /* NASCH_INIT_V_ZERO or NASCH_INIT_V_UNIFORM                         */
+    uint32_t kernel;   /* NASCH_KERNEL_*                                                    */
+    uint32_t k;        /* steps per launch for NASCH_KERNEL_KSTEP; 0 = default             */
+    uint32_t q;        /* 32-cell words per lane for the bit-sliced kernel (1, 2 or 4); 0 = default */
+    uint32_t use_graph;/* 1: replay nasch_step_n launch sequences from a captured hipGraph */
+    uint32_t reserved;
+    void*    stream;   /* hipStream_t to run on; NULL = a stream owned by the handle        */
+} nasch_opts;
+
+typedef struct {
+    uint64_t L, N, t;
+    uint32_t vmax, thr, replica, rep, init_v, kernel, k, q;
+    uint64_t seed;
+    uint64_t device_bytes; /* device memory held by the handle */
+} nasch_info;
+
+/* Fills *opts with the defaults (grid representation, v0 = 0, autotuned kernel). */
+void nasch_default_opts(nasch_opts* opts);
+
+/*
+ * Create a simulation of N cars on a ring of L cells, initialised as described
+ * above (t = 0).  Requires 1 <= L < 2^31, N <= L, vmax <= 8, 0 <= p < 1 (the
+ * range the paper gives for p, Handout bullet list on drawing r), p not NaN.
+ * opts may be NULL (defaults).  On success *out is a new handle; on failure
+ * *out is NULL and nothing is leaked.
+ */
+int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
+               uint64_t seed, const nasch_opts* opts);
+
+/* Advance T >= 0 steps (rules 1-4, synchronous update), asynchronously on the
+ * handle's stream.  F(t) for each step is kept on the device.  NASCH_ERANGE if
+ * t + T would exceed 2^32 - 1 (nothing is enqueued then). */
+int nasch_step_n(nasch_sim* h, uint64_t T);
+
+/* As nasch_step_n, then waits; *ms receives the device time between two HIP
+ * events recorded on the handle's stream around the enqueued launches. */
+int nasch_timed_step_n(nasch_sim* h, uint64_t T, double* ms);
+
+/* Copy F(t0), ..., F(t0 + count - 1) to out[count] (uint64).  Requires
+ * t0 + count <= t.  Synchronises. */
+int nasch_flux(nasch_sim* h, uint64_t t0, uint64_t count, uint64_t* out);
+
+/* Copy the whole road in grid form (L bytes, 0xFF = empty, else v) to out and
+ * the current step count to *t_out (either may be NULL).  The agent
+ * representation is scattered to a grid on the device first.  Synchronises. */
+int nasch_snapshot(nasch_sim* h, uint8_t* out, uint64_t* t_out);
+
+/* Copy cells [start, start + len) mod L of the grid form to out[len].  Synchronises. */
+int nasch_snapshot_range(nasch_sim* h, uint64_t start, uint64_t len, uint8_t* out);
+
+/* Agent representation only: copy x[N] (int32, road order, cyclically
+ * sorted) and v[N] (uint8).  Either may be NULL.  Synchronises. */
+int nasch_agent_state(nasch_sim* h, int32_t* x, uint8_t* v);
+
+/* Checkpoint restore: replace the state by grid[L] (host, 0xFF or a velocity
+ * <= vmax per cell, exactly N cars) at step count t.  The flux of steps before
+ * t is forgotten (nasch_flux then accepts t0 >= t only).  Continuing from a
+ * restored snapshot gives the same results as the uninterrupted run, because
+ * R depends only on (seed, replica, t, x).  Synchronises. */
+int nasch_restore(nasch_sim* h, const uint8_t* grid, uint64_t t);
+
+/* Choose the kernel and its tuning explicitly (values as in nasch_opts).
+ * k = 0 or q = 0 keeps the current value.  Takes effect at the next step call. */
+int nasch_set_tuning(nasch_sim* h, uint32_t kernel, uint32_t k, uint32_t q);
+
+/* Time the candidate (k, q) settings on a scratch copy of the state (the
+ * simulation itself does not advance) and keep the fastest.  Synchronises. */
+int nasch_autotune(nasch_sim* h);
+
+int nasch_get_info(const nasch_sim* h, nasch_info* info);
+
+/* The HIP error (hipError_t value) behind the last NASCH_EDEVICE, or 0. */
+int nasch_last_device_error(const nasch_sim* h);
+
+/* The last HIP error any entry point met on the calling thread (also when no
+ * handle was created, e.g. a failed nasch_init), or 0. */
+int nasch_thread_last_device_error(void);
+
+/* Release the handle and its device memory; NULL is accepted. */
+void nasch_free(nasch_sim* h);
+
+/* Static text for a status code. */
+const char* nasch_strerror(int status);
+
+/* ======================================================================= */
+/* Batched ensemble: many independent rings ("replicas") advanced together.  */
+/* The paper suggests running parameter-study cases as embarrassingly       */
+/* parallel jobs (section "Variations"); here every replica keeps its own   */
+/* (L, N, vmax, p, seed, replica) and its results are identical to the same  */
+/* simulation run alone through nasch_init / nasch_step_n.                   */
+/* ======================================================================= */
+typedef struct nasch_batch nasch_batch;
+
+typedef struct {
+    uint64_t L, N;
+    uint32_t vmax;
+    uint32_t init_v;   /* NASCH_INIT_V_* */
+    double   p;
+    uint64_t seed;
+    uint32_t replica;  /* Philox stream id of this replica */
+    uint32_t reserved;
+    uint64_t warmup;   /* F(t) is summed for t >= warmup */
+} nasch_replica;
+
+typedef struct {
+    void*    stream;    /* NULL = owned stream */
+    uint32_t k;         /* steps per launch; 0 = default (autotune with nasch_batch_autotune) */
+    uint32_t q;         /* words per lane; 0 = default */
+    uint32_t use_graph; /* capture each nasch_batch_step_n launch sequence in a hipGraph */
+    uint32_t keep_log;  /* also keep F(t) of every replica and step (R x T uint64 on device) */
+    uint64_t log_steps; /* capacity of that log in steps (required if keep_log) */
+} nasch_batch_opts;
+
+void nasch_batch_default_opts(nasch_batch_opts* opts);
+
+/* Create R >= 1 replicas (each validated as in nasch_init) in one device
+ * arena, all at t = 0. */
+int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
+                     const nasch_batch_opts* opts);
+
+/* Advance every replica by T steps.  Each launch runs k steps of every tile of
+ * every replica; the launches are the same kernels a single simulation uses. */
+int nasch_batch_step_n(nasch_batch* b, uint64_t T);
+int nasch_batch_timed_step_n(nasch_batch* b, uint64_t T, double* ms);
+
+/* out[R]: sum of F(t) over warmup <= t < current step, per replica.  Synchronises. */
+int nasch_batch_flux_sums(nasch_batch* b, uint64_t* out);
+
+/* F(t0 .. t0+count-1) of replica r (needs keep_log).  Synchronises. */
+int nasch_batch_flux(nasch_batch* b, uint32_t r, uint64_t t0, uint64_t count, uint64_t* out);
+
+/* Grid of replica r (L_r bytes) and the step count.  Synchronises. */
+int nasch_batch_snapshot(nasch_batch* b, uint32_t r, uint8_t* out, uint64_t* t_out);
+
+/* Choose (k, q) for this batch by timing candidates on a scratch copy of the
+ * arena (the replicas do not advance); *k_out / *q_out may be NULL. */
+int nasch_batch_autotune(nasch_batch* b, uint32_t* k_out, uint32_t* q_out);
+int nasch_batch_set_tuning(nasch_batch* b, uint32_t k, uint32_t q);
+int nasch_batch_last_device_error(const nasch_batch* b);
+void nasch_batch_free(nasch_batch* b);
+
+/* ======================================================================= */
+/* Serving: simulations submitted one by one, admitted onto the GPU while    */
+/* others run (continuous batching), state resident on the device.           */
+/* ======================================================================= */
+typedef struct nasch_server nasch_server;
+
+typedef struct {
+    uint64_t hbm_budget;  /* device bytes the server may hold for simulations; 0 = 1/2 of free memory */
+    uint32_t max_slots;   /* simulations on the device at once; 0 = 4096 */
+    uint32_t k;           /* steps per launch; 0 = 32 */
+    uint32_t q;           /* words per lane; 0 = 4 */
+    uint32_t reserved;
+    void*    stream;      /* NULL = owned stream */
+} nasch_server_opts;
+
+typedef struct {
+    uint64_t L, N;
+    uint32_t vmax, init_v;
+    double   p;
+    uint64_t seed;
+    uint32_t replica, reserved;
+    uint64_t T;           /* steps to run */
+    uint64_t* flux_out;   /* optional caller buffer of T uint64: F(0..T-1); must stay valid until polled */
+    uint8_t*  grid_out;   /* optional caller buffer of L bytes: final grid */
+} nasch_request;
+
+typedef struct {
+    uint64_t id;
+    int32_t  status;      /* NASCH_OK or an error code */
+    uint32_t reserved;
+    uint64_t flux_sum;    /* sum of F(t), 0 <= t < T */
+    double   t_submit, t_admit, t_done;  /* seconds on the server's monotonic clock */
+} nasch_result;
+
+void nasch_server_default_opts(nasch_server_opts* opts);
+/* Start the server and its scheduling thread. */
+int nasch_server_create(nasch_server** out, const nasch_server_opts* opts);
+/* Queue a request (validated as nasch_init, 1 <= T < 2^32); its footprint,
+ * 2 * ceil256(L) + ceil256(8 T) bytes (two grids and the flux log, each
+ * rounded up to 256 bytes), must fit hbm_budget.  *id receives its id.  Never
+ * blocks on the GPU; the request waits in arrival order until it fits. */
+int nasch_server_submit(nasch_server* s, const nasch_request* req, uint64_t* id);
+/* Move up to max finished results to out; *n receives the count.  If
+ * wait_ms > 0, waits up to that long for at least one. */
+int nasch_server_poll(nasch_server* s, nasch_result* out, uint32_t max, uint32_t* n,
+                      uint32_t wait_ms);
+/* Cancel a queued or running request; its result is reported with NASCH_ESTATE. */
+int nasch_server_cancel(nasch_server* s, uint64_t id);
+/* Counters: pending, running, finished; device bytes in use; launches. */
+int nasch_server_stats(nasch_server* s, uint64_t* pending, uint64_t* running, uint64_t* done,
+                       uint64_t* bytes_in_use, uint64_t* launches);
+/* Monotonic clock of the server in seconds (same clock as nasch_result). */
+double nasch_server_now(nasch_server* s);
+/* Stop the scheduling thread and release everything; unfinished requests are dropped. */
+void nasch_server_destroy(nasch_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NASCH_H */

@@ -1,0 +1,209 @@
+// agent.hip -- the agent representation ("Concepts Covered"; the Handout's starter
+// code keeps two length-N vectors): int32 positions x[N] in road order and
+// uint8 velocities v[N].  Car i's distance to the car in front is
+// d = (x[i+1] - x[i]) mod L (d = L for a car alone); rules 1-4 follow.
+//
+// Two kernels:
+//   agent_onestep_kernel  one thread per car, one step per launch;
+//   agent_kstep_kernel    one wave per 64 x kAgentCarsPerLane consecutive cars
+//                         kept in registers for k steps.  Car i after s steps
+//                         depends only on cars i .. i+s, so the last k cars of
+//                         a wave are a halo: each wave writes back the first
+//                         `own` cars and the waves overlap by the halo.
+// Rule 3 uses the same keyed draw as the grid kernels (R depends on the cell a
+// car starts the step in), so both representations give identical results.
+#include "launchers.hpp"
+
+namespace nasch {
+
+namespace {
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t hi_nibble(const Word4& w, uint32_t x) {
+    const uint32_t s = x & 31u;
+    return (((w.w0 >> s) & 1u) << 3) | (((w.w1 >> s) & 1u) << 2) | (((w.w2 >> s) & 1u) << 1) |
+           ((w.w3 >> s) & 1u);
+}
+
+// rules 1 and 2
+__device__ __forceinline__ uint32_t accel_brake(uint32_t v, uint32_t d, uint32_t vmax) {
+    uint32_t nv = min(v + 1u, vmax);
+    if (nv >= d) nv = d - 1u;
+    return nv;
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void agent_onestep_kernel(const AgentDesc* __restrict__ A,
+                                                            const Clock* __restrict__ clk,
+                                                            uint32_t s_off, uint32_t launch_idx) {
+    const uint32_t N = A->N, L = A->L, vmax = A->vmax;
+    const SlowParams sp = A->sp;
+    const uint32_t t = clk->t + A->t + s_off;
+    const uint32_t par = (clk->parity + A->parity + launch_idx) & 1u;
+    const int32_t* __restrict__ x = A->x[par];
+    const uint8_t* __restrict__ v = A->v[par];
+    int32_t* __restrict__ xo = A->x[par ^ 1u];
+    uint8_t* __restrict__ vo = A->v[par ^ 1u];
+
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t nv = 0;
+    if (i < N) {
+        const uint32_t xi = (uint32_t)x[i];
+        uint32_t d = L;
+        if (N > 1) {
+            const uint32_t xn = (uint32_t)x[i + 1 == N ? 0 : i + 1];
+            d = xn >= xi ? xn - xi : xn + L - xi;
+        }
+        nv = accel_brake(v[i], d, vmax);
+        if (nv > 0 && sp.thr != 0 && rand32(xi, t, sp) < sp.thr) --nv;   // rule 3
+        uint32_t xn = xi + nv;                                             // rule 4
+        if (xn >= L) xn -= L;
+        xo[i] = (int32_t)xn;
+        vo[i] = (uint8_t)nv;
+    }
+    const uint32_t total = wave_sum(nv);
+    if ((threadIdx.x & 63u) == 0 && total) {
+        if (A->flux_log) atomicAdd(&A->flux_log[(uint64_t)t - A->log_t0], (unsigned long long)total);
+        if (A->flux_acc && (uint64_t)t >= A->warmup) atomicAdd(A->flux_acc, (unsigned long long)total);
+    }
+}
+
+hipError_t launch_agent_onestep(const AgentDesc* a, uint32_t N, const Clock* clk, uint32_t s_off,
+                                uint32_t launch_idx, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    NASCH_LAUNCH(agent_onestep_kernel, dim3((N + 255) / 256), dim3(256), 0, s, a, clk, s_off,
+                       launch_idx);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+constexpr uint32_t CPL = kAgentCarsPerLane;
+
+__global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __restrict__ A,
+                                                          uint32_t k,
+                                                          const Clock* __restrict__ clk,
+                                                          uint32_t s_off, uint32_t launch_idx) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= A->ntiles) return;
+    const uint32_t N = A->N, L = A->L, vmax = A->vmax, own = A->own;
+    const SlowParams sp = A->sp;
+    const uint32_t t0 = clk->t + A->t + s_off;
+    const uint32_t par = (clk->parity + A->parity + launch_idx) & 1u;
+    const int32_t* __restrict__ xs = A->x[par];
+    const uint8_t* __restrict__ vs = A->v[par];
+    int32_t* __restrict__ xd = A->x[par ^ 1u];
+    uint8_t* __restrict__ vd = A->v[par ^ 1u];
+
+    const uint32_t c0 = wave * own;                  // first car of the wave
+    const uint32_t own_len = min(own, N - c0);
+    const uint32_t first = c0 + lane * CPL;          // first car of the lane (may exceed N)
+
+    uint32_t x[CPL], v[CPL];
+    if ((uint64_t)first + CPL <= N) {
+        const uint4* p = reinterpret_cast<const uint4*>(xs + first);
+        const uint4 a = p[0], b = p[1];
+        x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+        const uint2 vv = *reinterpret_cast<const uint2*>(vs + first);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = (vv.x >> (8 * q)) & 0xFFu;
+            v[q + 4] = (vv.y >> (8 * q)) & 0xFFu;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < (int)CPL; ++q) {
+            const uint32_t idx = (uint32_t)(((uint64_t)first + q) % N);
+            x[q] = (uint32_t)xs[idx];
+            v[q] = vs[idx];
+        }
+    }
+
+    unsigned long long acc = 0ull;
+    for (uint32_t s = 0; s < k; ++s) {
+        const uint32_t t = t0 + s;
+        const uint32_t x_next_lane = __shfl_down(x[0], 1);
+        uint32_t nv[CPL];
+#pragma unroll
+        for (int q = 0; q < (int)CPL; ++q) {
+            uint32_t d = L;
+            if (N > 1 && !(q == (int)CPL - 1 && lane == 63u)) {
+                const uint32_t xn = (q + 1 < (int)CPL) ? x[(q + 1) % CPL] : x_next_lane;
+                d = xn >= x[q] ? xn - x[q] : xn + L - x[q];
+            }
+            nv[q] = accel_brake(v[q], d, vmax);
+        }
+        if (sp.thr != 0u) {
+            // rule 3: one Philox block call serves every car of the lane in that block
+            uint32_t pending = 0u;
+#pragma unroll
+            for (int q = 0; q < (int)CPL; ++q) pending |= (nv[q] > 0u ? 1u : 0u) << q;
+            while (pending) {
+                uint32_t blk = 0u;
+                bool found = false;
+#pragma unroll
+                for (int q = 0; q < (int)CPL; ++q)
+                    if (!found && ((pending >> q) & 1u)) { blk = x[q] >> 5; found = true; }
+                const Word4 w = slow_hi_planes(blk, t, sp);
+#pragma unroll
+                for (int q = 0; q < (int)CPL; ++q) {
+                    if (((pending >> q) & 1u) && (x[q] >> 5) == blk) {
+                        pending &= ~(1u << q);
+                        if (slow_from_hi(hi_nibble(w, x[q]), x[q], t, sp)) --nv[q];
+                    }
+                }
+            }
+        }
+        uint32_t fl = 0u;
+#pragma unroll
+        for (int q = 0; q < (int)CPL; ++q) {
+            if (lane * CPL + q < own_len) fl += nv[q];
+            uint32_t xn = x[q] + nv[q];     // rule 4
+            if (xn >= L) xn -= L;
+            x[q] = xn;
+            v[q] = nv[q];
+        }
+        const uint32_t total = wave_sum(fl);
+        if (lane == 0u) {
+            if (A->flux_log) atomicAdd(&A->flux_log[(uint64_t)t - A->log_t0], (unsigned long long)total);
+            if ((uint64_t)t >= A->warmup) acc += total;
+        }
+    }
+    if (lane == 0u && A->flux_acc && acc) atomicAdd(A->flux_acc, acc);
+
+    // write back the owned cars
+    if (lane * CPL + CPL <= own_len) {
+        uint4* p = reinterpret_cast<uint4*>(xd + first);
+        p[0] = make_uint4(x[0], x[1], x[2], x[3]);
+        p[1] = make_uint4(x[4], x[5], x[6], x[7]);
+        uint32_t lo = 0, hi = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            lo |= v[q] << (8 * q);
+            hi |= v[q + 4] << (8 * q);
+        }
+        *reinterpret_cast<uint2*>(vd + first) = make_uint2(lo, hi);
+    } else {
+#pragma unroll
+        for (int q = 0; q < (int)CPL; ++q) {
+            if (lane * CPL + q < own_len) {
+                xd[first + q] = (int32_t)x[q];
+                vd[first + q] = (uint8_t)v[q];
+            }
+        }
+    }
+}
+
+hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t ntiles, uint32_t k, const Clock* clk,
+                              uint32_t s_off, uint32_t launch_idx, hipStream_t s) {
+    if (ntiles == 0) return hipSuccess;
+    NASCH_LAUNCH(agent_kstep_kernel, dim3((ntiles + 3) / 4), dim3(256), 0, s, a, k, clk,
+                       s_off, launch_idx);
+    return hipGetLastError();
+}
+
+}  // namespace nasch

@@ -1,0 +1,236 @@
+// batch.hip -- the batched ensemble: many independent rings in one device arena,
+// advanced together by the temporal-blocked grid kernel (all rings' tiles in
+// the same launches).  Entry points are documented in include/nasch.h.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "engine.hpp"
+#include "nasch.h"
+
+using namespace nasch;
+
+struct nasch_batch {
+    std::vector<nasch_replica> reps;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    HipStatus st;
+    uint8_t* arena = nullptr;
+    uint64_t arena_bytes = 0;
+    unsigned long long* d_acc = nullptr;   // per replica: sum of F(t), t >= warmup
+    unsigned long long* d_log = nullptr;   // per replica x log_steps: F(t)
+    uint64_t log_steps = 0;
+    Clock* d_clk = nullptr;
+    uint64_t t = 0;
+    uint32_t parity = 0;
+    uint32_t use_graph = 0;
+    GridEngine eng;
+    GraphCache graphs;
+
+    bool ok(hipError_t e) { return st.ok(e); }
+    ~nasch_batch() {
+        graphs.clear();
+        eng.release();
+        void* ps[] = {arena, d_acc, d_log, d_clk};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        (void)hipGetLastError();
+    }
+    int enqueue(uint64_t T) {
+        if (t + T > 0xFFFFFFFFull) return NASCH_ERANGE;
+        if (d_log && t + T > log_steps) return NASCH_ERANGE;
+        if (T == 0) return NASCH_OK;
+        auto body = [&]() -> hipError_t {
+            hipError_t e = eng.enqueue(T, d_clk, stream);
+            if (e != hipSuccess) return e;
+            return launch_clock_advance(d_clk, (uint32_t)T, eng.launches_for(T), stream);
+        };
+        hipError_t e = use_graph
+                           ? graphs.run(std::make_tuple(T, 0u, eng.k, eng.q, eng.version), stream, body)
+                           : body();
+        if (!ok(e)) return NASCH_EDEVICE;
+        t += T;
+        parity ^= eng.launches_for(T) & 1u;
+        return NASCH_OK;
+    }
+};
+
+extern "C" {
+
+void nasch_batch_default_opts(nasch_batch_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+}
+
+int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
+                     const nasch_batch_opts* opts) {
+    if (!out) return NASCH_EINVAL;
+    *out = nullptr;
+    if (!reps || R == 0) return NASCH_EINVAL;
+    nasch_batch_opts o;
+    nasch_batch_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.keep_log && o.log_steps == 0) return NASCH_EINVAL;
+    for (uint32_t r = 0; r < R; ++r) {
+        int rc = validate_params(reps[r].L, reps[r].N, reps[r].vmax, reps[r].p);
+        if (rc) return rc;
+        if (reps[r].init_v > NASCH_INIT_V_UNIFORM) return NASCH_EINVAL;
+    }
+    std::unique_ptr<nasch_batch> b(new (std::nothrow) nasch_batch());
+    if (!b) return NASCH_ENOMEM;
+    b->reps.assign(reps, reps + R);
+    b->use_graph = o.use_graph;
+    if (o.stream) {
+        b->stream = (hipStream_t)o.stream;
+    } else {
+        if (!b->ok(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking))) return NASCH_EDEVICE;
+        b->own_stream = true;
+    }
+    std::vector<uint64_t> offs(R);
+    uint64_t bytes = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        offs[r] = bytes;
+        bytes += 2 * ((reps[r].L + 255) / 256 * 256);
+    }
+    b->arena_bytes = bytes;
+    if (!b->ok(dev_alloc(&b->arena, bytes)) || !b->ok(dev_alloc(&b->d_acc, R)) ||
+        !b->ok(dev_alloc(&b->d_clk, 1)))
+        return NASCH_ENOMEM;
+    if (!b->ok(launch_fill_u64(b->d_acc, R, b->stream))) return NASCH_EDEVICE;
+    if (o.keep_log) {
+        b->log_steps = o.log_steps;
+        if (!b->ok(dev_alloc(&b->d_log, (uint64_t)R * o.log_steps))) return NASCH_ENOMEM;
+        if (!b->ok(launch_fill_u64(b->d_log, (uint64_t)R * o.log_steps, b->stream)))
+            return NASCH_EDEVICE;
+    }
+    const Clock c0{0u, 0u};
+    if (!b->ok(hipMemcpyAsync(b->d_clk, &c0, sizeof(Clock), hipMemcpyHostToDevice, b->stream)))
+        return NASCH_EDEVICE;
+    uint32_t vmax_all = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        const nasch_replica& p = reps[r];
+        const uint64_t sz = (p.L + 255) / 256 * 256;
+        RingDesc d{};
+        d.buf[0] = b->arena + offs[r];
+        d.buf[1] = b->arena + offs[r] + sz;
+        d.flux_log = b->d_log ? b->d_log + (uint64_t)r * b->log_steps : nullptr;
+        d.flux_acc = b->d_acc + r;
+        d.log_t0 = 0;
+        d.warmup = p.warmup;
+        d.L = (uint32_t)p.L;
+        d.vmax = p.vmax;
+        d.t_end = 0xFFFFFFFFu;
+        d.sp = slow_params(p.seed, p.replica, p.p);
+        b->eng.rings.push_back(d);
+        vmax_all = std::max(vmax_all, p.vmax);
+        if (!b->ok(launch_init_grid(d.buf[0], (uint32_t)p.L, (uint32_t)p.N, p.vmax, p.init_v, d.sp,
+                                    b->stream)))
+            return NASCH_EDEVICE;
+    }
+    uint32_t q = o.q ? o.q : 4u;
+    uint32_t k = o.k ? o.k : std::min(32u, std::max(1u, kstep_max_k(vmax_all, q)));
+    if (!b->eng.geometry_ok(k, q)) return NASCH_EINVAL;
+    if (!b->ok(b->eng.set_geometry(k, q, b->stream))) return NASCH_EDEVICE;
+    if (!b->ok(hipStreamSynchronize(b->stream))) return NASCH_EDEVICE;
+    *out = b.release();
+    return NASCH_OK;
+}
+
+int nasch_batch_step_n(nasch_batch* b, uint64_t T) {
+    if (!b) return NASCH_EINVAL;
+    return b->enqueue(T);
+}
+
+int nasch_batch_timed_step_n(nasch_batch* b, uint64_t T, double* ms) {
+    if (!b) return NASCH_EINVAL;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!b->ok(hipEventCreate(&e0)) || !b->ok(hipEventCreate(&e1))) return NASCH_EDEVICE;
+    int rc = NASCH_OK;
+    if (!b->ok(hipEventRecord(e0, b->stream))) rc = NASCH_EDEVICE;
+    if (!rc) rc = b->enqueue(T);
+    if (!rc && !b->ok(hipEventRecord(e1, b->stream))) rc = NASCH_EDEVICE;
+    if (!rc && !b->ok(hipEventSynchronize(e1))) rc = NASCH_EDEVICE;
+    float f = 0;
+    if (!rc && !b->ok(hipEventElapsedTime(&f, e0, e1))) rc = NASCH_EDEVICE;
+    if (ms) *ms = f;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int nasch_batch_flux_sums(nasch_batch* b, uint64_t* out) {
+    if (!b || !out) return NASCH_EINVAL;
+    if (!b->ok(hipMemcpyAsync(out, b->d_acc, b->reps.size() * sizeof(uint64_t),
+                              hipMemcpyDeviceToHost, b->stream)) ||
+        !b->ok(hipStreamSynchronize(b->stream)))
+        return NASCH_EDEVICE;
+    return NASCH_OK;
+}
+
+int nasch_batch_flux(nasch_batch* b, uint32_t r, uint64_t t0, uint64_t count, uint64_t* out) {
+    if (!b || (count && !out)) return NASCH_EINVAL;
+    if (r >= b->reps.size()) return NASCH_ENOTFOUND;
+    if (!b->d_log) return NASCH_ESTATE;
+    if (t0 + count > b->t) return NASCH_EINVAL;
+    if (count == 0) return NASCH_OK;
+    if (!b->ok(hipMemcpyAsync(out, b->d_log + (uint64_t)r * b->log_steps + t0,
+                              count * sizeof(uint64_t), hipMemcpyDeviceToHost, b->stream)) ||
+        !b->ok(hipStreamSynchronize(b->stream)))
+        return NASCH_EDEVICE;
+    return NASCH_OK;
+}
+
+int nasch_batch_snapshot(nasch_batch* b, uint32_t r, uint8_t* out, uint64_t* t_out) {
+    if (!b) return NASCH_EINVAL;
+    if (r >= b->reps.size()) return NASCH_ENOTFOUND;
+    if (out) {
+        const RingDesc& d = b->eng.rings[r];
+        if (!b->ok(hipMemcpyAsync(out, d.buf[b->parity], d.L, hipMemcpyDeviceToHost, b->stream)) ||
+            !b->ok(hipStreamSynchronize(b->stream)))
+            return NASCH_EDEVICE;
+    }
+    if (t_out) *t_out = b->t;
+    return NASCH_OK;
+}
+
+int nasch_batch_set_tuning(nasch_batch* b, uint32_t k, uint32_t q) {
+    if (!b) return NASCH_EINVAL;
+    if (k == 0) k = b->eng.k;
+    if (q == 0) q = b->eng.q;
+    if (!b->eng.geometry_ok(k, q)) return NASCH_EINVAL;
+    if (k == b->eng.k && q == b->eng.q) return NASCH_OK;
+    if (!b->ok(hipStreamSynchronize(b->stream))) return NASCH_EDEVICE;
+    if (!b->ok(b->eng.set_geometry(k, q, b->stream))) return NASCH_EDEVICE;
+    b->graphs.clear();
+    return NASCH_OK;
+}
+
+int nasch_batch_autotune(nasch_batch* b, uint32_t* k_out, uint32_t* q_out) {
+    if (!b) return NASCH_EINVAL;
+    if (!b->ok(hipStreamSynchronize(b->stream))) return NASCH_EDEVICE;
+    uint32_t bk = 0, bq = 0;
+    double cups = 0;
+    if (!b->ok(autotune_grid(b->eng.rings, (uint32_t)b->t, b->parity, 128, b->stream, &bk, &bq,
+                             &cups)))
+        return NASCH_EDEVICE;
+    if (!bk) return NASCH_EINVAL;
+    int rc = nasch_batch_set_tuning(b, bk, bq);
+    if (rc) return rc;
+    if (k_out) *k_out = bk;
+    if (q_out) *q_out = bq;
+    return NASCH_OK;
+}
+
+int nasch_batch_last_device_error(const nasch_batch* b) { return b ? b->st.err : 0; }
+
+void nasch_batch_free(nasch_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,327 @@
+// engine.hpp -- host-side machinery shared by single simulations, batches and the
+// server: device allocation helpers, tile geometry, the ring/tile-item tables
+// of the temporal-blocked grid kernel, launch sequences and their hipGraphs.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "launchers.hpp"
+#include "nasch.h"
+
+namespace nasch {
+
+// The last failing HIP call of this thread, for failures that leave no handle.
+inline int& thread_last_hip_error() {
+    static thread_local int e = 0;
+    return e;
+}
+
+// Remembers the first failing HIP call of a handle.
+struct HipStatus {
+    int err = 0;
+    bool ok(hipError_t e) {
+        if (e != hipSuccess) {
+            if (!err) err = (int)e;
+            thread_last_hip_error() = (int)e;
+            return false;
+        }
+        return true;
+    }
+};
+
+inline uint32_t threshold_of(double p) { return (uint32_t)std::floor(p * 4294967296.0); }
+
+inline int validate_params(uint64_t L, uint64_t N, uint32_t vmax, double p) {
+    if (L < 1 || L > NASCH_MAX_L) return NASCH_EINVAL;
+    if (N > L) return NASCH_EINVAL;
+    if (vmax > NASCH_MAX_VMAX) return NASCH_EINVAL;
+    if (!(p >= 0.0 && p < 1.0)) return NASCH_EINVAL;  // also rejects NaN
+    return NASCH_OK;
+}
+
+inline SlowParams slow_params(uint64_t seed, uint32_t replica, double p) {
+    SlowParams sp;
+    sp.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    sp.k1 = (uint32_t)(seed >> 32);
+    sp.replica = replica;
+    sp.thr = threshold_of(p);
+    return sp;
+}
+
+// Tile geometry of the bit-sliced kernel for one ring: halo H = k*vmax rounded
+// up to a whole 32-cell word, segment 2048*q cells, owned cells per tile the
+// rest.  A ring that fits one segment is one tile owning all L cells.
+inline bool kstep_geometry(uint32_t L, uint32_t vmax, uint32_t k, uint32_t q, uint32_t* own,
+                           uint32_t* halo, uint32_t* ntiles) {
+    if (k == 0 || (q != 1 && q != 2 && q != 4)) return false;
+    const uint64_t seg = kstep_segment(q);
+    const uint64_t H = ((uint64_t)k * vmax + 31u) / 32u * 32u;
+    if (seg < 2 * H + 32) return false;
+    const uint64_t own_full = seg - 2 * H;
+    if (L <= own_full) {
+        *own = L;
+        *ntiles = 1;
+    } else {
+        *own = (uint32_t)own_full;
+        *ntiles = (uint32_t)((L + own_full - 1) / own_full);
+    }
+    *halo = (uint32_t)H;
+    return true;
+}
+
+// Largest k the geometry admits for this vmax and q.
+inline uint32_t kstep_max_k(uint32_t vmax, uint32_t q) {
+    if (vmax == 0) return 1u << 20;
+    const uint32_t seg = kstep_segment(q);
+    return (seg - 32u) / 2u / 32u * 32u / vmax;
+}
+
+// Agent k-step geometry: 512 cars per wave, the last round_up(k, 8) are halo.
+inline bool agent_geometry(uint32_t N, uint32_t k, uint32_t* own, uint32_t* ntiles) {
+    const uint32_t per_wave = 64u * kAgentCarsPerLane;
+    const uint32_t halo = (k + 7u) / 8u * 8u;
+    if (k == 0 || halo + 8u > per_wave) return false;
+    *own = per_wave - halo;
+    *ntiles = N == 0 ? 0u : (N + *own - 1u) / *own;
+    return true;
+}
+
+template <typename T>
+inline hipError_t dev_alloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void**)p, count * sizeof(T));
+}
+
+// Ring table + tile items of the bit-sliced grid kernel, shared by every ring
+// that advances in the same launches.
+struct GridEngine {
+    std::vector<RingDesc> rings;      // host mirror of the device table
+    RingDesc* d_rings = nullptr;
+    size_t d_rings_cap = 0;
+    std::vector<TileItem> items;
+    TileItem* d_items = nullptr;
+    size_t d_items_cap = 0;
+    uint32_t k = 0, q = 0;
+    uint32_t launch_vmax = kMixedVmax;  // single specialisation when all rings agree
+    uint32_t version = 0;               // bumped whenever d_items / geometry change
+
+    ~GridEngine() { release(); }
+    void release() {
+        if (d_rings) (void)hipFree(d_rings);
+        if (d_items) (void)hipFree(d_items);
+        d_rings = nullptr;
+        d_items = nullptr;
+        d_rings_cap = d_items_cap = 0;
+    }
+
+    bool geometry_ok(uint32_t kk, uint32_t qq) const {
+        uint32_t o, h, n;
+        for (const RingDesc& r : rings)
+            if (!kstep_geometry(r.L, r.vmax, kk, qq, &o, &h, &n)) return false;
+        return true;
+    }
+
+    // Recompute every ring's geometry for (k, q), rebuild the items (rings of
+    // larger vmax first, so the heavier waves start first) and upload both.
+    hipError_t set_geometry(uint32_t kk, uint32_t qq, hipStream_t s) {
+        items.clear();
+        std::vector<uint32_t> order(rings.size());
+        for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+            return rings[a].vmax > rings[b].vmax;
+        });
+        uint32_t vmin = 0xFF, vmaxx = 0;
+        for (RingDesc& r : rings) {
+            kstep_geometry(r.L, r.vmax, kk, qq, &r.own, &r.halo, &r.ntiles);
+            vmin = std::min(vmin, r.vmax);
+            vmaxx = std::max(vmaxx, r.vmax);
+        }
+        for (uint32_t ri : order)
+            for (uint32_t t = 0; t < rings[ri].ntiles; ++t) items.push_back(TileItem{ri, t});
+        launch_vmax = (vmin == vmaxx) ? vmin : kMixedVmax;
+        k = kk;
+        q = qq;
+        ++version;
+        hipError_t e = upload_rings(s);
+        if (e != hipSuccess) return e;
+        if (items.size() > d_items_cap) {
+            if (d_items) (void)hipFree(d_items);
+            d_items = nullptr;
+            d_items_cap = 0;
+            e = dev_alloc(&d_items, items.size());
+            if (e != hipSuccess) return e;
+            d_items_cap = items.size();
+        }
+        if (!items.empty()) {
+            e = hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(TileItem),
+                               hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipStreamSynchronize(s);
+    }
+
+    hipError_t upload_rings(hipStream_t s) {
+        if (rings.size() > d_rings_cap) {
+            if (d_rings) (void)hipFree(d_rings);
+            d_rings = nullptr;
+            d_rings_cap = 0;
+            hipError_t e = dev_alloc(&d_rings, rings.size());
+            if (e != hipSuccess) return e;
+            d_rings_cap = rings.size();
+        }
+        if (rings.empty()) return hipSuccess;
+        hipError_t e = hipMemcpyAsync(d_rings, rings.data(), rings.size() * sizeof(RingDesc),
+                                      hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    }
+
+    uint32_t launches_for(uint64_t T) const { return (uint32_t)((T + k - 1) / k); }
+
+    // Launches that advance every ring by T steps from the device clock.
+    hipError_t enqueue(uint64_t T, const Clock* d_clk, hipStream_t s) const {
+        const uint32_t n = launches_for(T);
+        for (uint32_t i = 0; i < n; ++i) {
+            const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
+            hipError_t e = launch_grid_kstep(launch_vmax, q, d_rings, d_items,
+                                             (uint32_t)items.size(), ki, d_clk, i * k, i, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+};
+
+// Captured launch sequences, keyed by what they bake in.
+struct GraphCache {
+    std::map<std::tuple<uint64_t, uint32_t, uint32_t, uint32_t, uint32_t>, hipGraphExec_t> m;
+    ~GraphCache() { clear(); }
+    void clear() {
+        for (auto& kv : m) (void)hipGraphExecDestroy(kv.second);
+        m.clear();
+    }
+    template <typename F>
+    hipError_t run(std::tuple<uint64_t, uint32_t, uint32_t, uint32_t, uint32_t> key, hipStream_t s,
+                   F&& enqueue) {
+        auto it = m.find(key);
+        if (it == m.end()) {
+            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return e;
+            hipError_t e_enq = enqueue();
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(s, &g);
+            if (e_enq != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return e_enq;
+            }
+            if (e != hipSuccess) return e;
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return e;
+            it = m.emplace(key, ex).first;
+        }
+        return hipGraphLaunch(it->second, s);
+    }
+};
+
+}  // namespace nasch
+
+namespace nasch {
+
+// Candidate settings the autotuner times.
+inline std::vector<std::pair<uint32_t, uint32_t>> kstep_candidates() {
+    std::vector<std::pair<uint32_t, uint32_t>> c;
+    const uint32_t ks[] = {8, 16, 24, 32, 48, 64};
+    const uint32_t qs[] = {1, 2, 4};
+    for (uint32_t q : qs)
+        for (uint32_t k : ks) c.emplace_back(k, q);
+    return c;
+}
+
+// Times every candidate (k, q) admitted by all rings on scratch copies of their
+// current state (buf[cur] of each ring) and returns the fastest.  The rings
+// themselves are not touched.  `steps` steps are timed per candidate after one
+// untimed launch.
+inline hipError_t autotune_grid(const std::vector<RingDesc>& rings, uint32_t t_now, uint32_t cur,
+                                uint32_t steps, hipStream_t s, uint32_t* best_k,
+                                uint32_t* best_q, double* best_cups) {
+    *best_k = 0;
+    *best_q = 0;
+    *best_cups = 0.0;
+    if (rings.empty()) return hipSuccess;
+    uint64_t bytes = 0, cells = 0;
+    for (const RingDesc& r : rings) {
+        bytes += 2 * ((uint64_t)(r.L + 255u) / 256u * 256u);
+        cells += r.L;
+    }
+    uint8_t* arena = nullptr;
+    Clock* d_clk = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = dev_alloc(&arena, bytes);
+    if (e == hipSuccess) e = dev_alloc(&d_clk, 1);
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    GridEngine scratch;
+    if (e == hipSuccess) {
+        uint64_t off = 0;
+        for (const RingDesc& r : rings) {
+            RingDesc c = r;
+            const uint64_t sz = (uint64_t)(r.L + 255u) / 256u * 256u;
+            c.buf[0] = arena + off;
+            c.buf[1] = arena + off + sz;
+            off += 2 * sz;
+            c.flux_log = nullptr;
+            c.flux_acc = nullptr;
+            c.t = 0;
+            c.parity = 0;
+            c.t_end = 0xFFFFFFFFu;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c.buf[0], r.buf[(cur + r.parity) & 1u], r.L,
+                                   hipMemcpyDeviceToDevice, s);
+            scratch.rings.push_back(c);
+        }
+    }
+    const Clock c0{t_now, 0u};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_clk, &c0, sizeof(Clock), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    for (auto kq : kstep_candidates()) {
+        if (e != hipSuccess) break;
+        if (!scratch.geometry_ok(kq.first, kq.second)) continue;
+        e = scratch.set_geometry(kq.first, kq.second, s);
+        if (e != hipSuccess) break;
+        // one untimed launch, then `steps` steps (rounded up to whole launches);
+        // the clock is not advanced, so every candidate draws the same numbers
+        e = scratch.enqueue(kq.first, d_clk, s);
+        const uint64_t T = (uint64_t)std::max<uint32_t>(steps, kq.first) / kq.first * kq.first;
+        if (e == hipSuccess) e = hipEventRecord(a, s);
+        if (e == hipSuccess) e = scratch.enqueue(T, d_clk, s);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && ms > 0) {
+            const double cups = (double)cells * (double)T / (ms * 1e-3);
+            if (cups > *best_cups) {
+                *best_cups = cups;
+                *best_k = kq.first;
+                *best_q = kq.second;
+            }
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    scratch.release();
+    if (d_clk) (void)hipFree(d_clk);
+    if (arena) (void)hipFree(arena);
+    return e;
+}
+
+}  // namespace nasch

@@ -1,0 +1,399 @@
+// grid_kstep.hip -- temporal-blocked grid kernel: k steps of rules 1-4 per launch,
+// with the road held bit-sliced in registers.
+//
+// Layout.  Each wave owns one segment of 64 lanes x Q words x 32 cells.  A lane
+// holds Q consecutive 32-cell words; word q of lane l covers segment cells
+// [32 (l Q + q), +32).  A word is stored as VMAX + 1 bit planes:
+//   T[0]    occupancy (bit i set iff a car is in cell i),
+//   T[m]    the car in cell i has v >= m   (m = 1..VMAX, a thermometer code).
+// In this form the four rules become a few bitwise operations per 32 cells:
+//   rule 1   v1 >= m  <=>  T[m-1]                (m <= vmax; T[0] for m = 1)
+//   rule 2   gap >= m <=>  cells i+1..i+m empty  (OR of shifted occupancies)
+//            v2 >= m  <=>  T[m-1] & (gap >= m)
+//   rule 3   a slow-down mask S (moving cars with R < thr) shifts the
+//            thermometer down by one: v3 >= m <=> S ? v2 >= m+1 : v2 >= m
+//   rule 4   the cars with v3 == j are shifted j cells to the right, and the
+//            new thermometer is the suffix-OR of the shifted classes.
+// Neighbouring words come from the same lane or, at lane edges, from lane +-1
+// by cross-lane shuffles.  The segment is the tile's owned cells plus a halo
+// of H >= k*vmax cells on each side (read modulo L, so short rings repeat
+// periodically); after k steps only the owned cells are exact, and only they
+// are written back and counted in F(t).  Segments never talk to each other:
+// one launch reads one ping-pong buffer and writes the other.
+//
+// Rule 3 draws.  The top 4 bits of R for a 32-cell block are the four words of
+// one Philox call, bit-sliced already, so one call serves 32 cells; a lane
+// compares them with the top nibble of thr bit-sliced as well.  Only cars whose
+// top nibble ties (1 in 16) need the per-cell low 28 bits.
+#include "launchers.hpp"
+
+namespace nasch {
+
+namespace {
+
+// 4 bits at positions 0, 8, 16, 24 of y -> bits 0..3.
+__device__ __forceinline__ uint32_t gather4(uint32_t y) {
+    return (((y & 0x01010101u) * 0x00204081u) >> 21) & 0xFu;
+}
+// bits 0..3 of b -> bits 0, 8, 16, 24.
+__device__ __forceinline__ uint32_t spread4(uint32_t b) {
+    return ((b & 0xFu) * 0x00204081u) & 0x01010101u;
+}
+
+// mask of bits [a, b), 0 <= a <= b <= 32
+__device__ __forceinline__ uint32_t bit_range(uint32_t a, uint32_t b) {
+    const uint32_t hi = b >= 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
+    const uint32_t lo = a >= 32 ? 0xFFFFFFFFu : ((1u << a) - 1u);
+    return hi & ~lo;
+}
+
+// Top-nibble planes of R for the 32 consecutive ring cells x0, x0+1, ... (mod L)
+// when they are not one aligned block: assembled from the blocks they touch.
+__device__ __noinline__ Word4 planes_unaligned(uint32_t x0, uint32_t t, uint32_t L,
+                                              const SlowParams& sp) {
+    Word4 r{0, 0, 0, 0};
+    uint32_t pos = x0, i = 0;
+    while (i < 32u) {
+        const uint32_t off = pos & 31u;
+        uint32_t run = min(32u - off, L - pos);
+        run = min(run, 32u - i);
+        const Word4 w = slow_hi_planes(pos >> 5, t, sp);
+        const uint32_t m = run >= 32u ? 0xFFFFFFFFu : ((1u << run) - 1u);
+        r.w0 |= ((w.w0 >> off) & m) << i;
+        r.w1 |= ((w.w1 >> off) & m) << i;
+        r.w2 |= ((w.w2 >> off) & m) << i;
+        r.w3 |= ((w.w3 >> off) & m) << i;
+        i += run;
+        pos += run;
+        if (pos >= L) pos = 0;
+    }
+    return r;
+}
+
+// Rule 3 mask for the moving cars of one word (ring cells x0 .. x0+31, mod L).
+__device__ __forceinline__ uint32_t slow_mask(uint32_t moving, uint32_t x0, bool aligned,
+                                              uint32_t t, uint32_t L, const SlowParams& sp) {
+    const Word4 hp = aligned ? slow_hi_planes(x0 >> 5, t, sp) : planes_unaligned(x0, t, L, sp);
+    const uint32_t th = sp.thr >> 28;
+    uint32_t lt = 0u, eq = 0xFFFFFFFFu;
+    // compare the nibble (w0 w1 w2 w3) with th, most significant plane first
+    if (th & 8u) { lt |= eq & ~hp.w0; eq &= hp.w0; } else { eq &= ~hp.w0; }
+    if (th & 4u) { lt |= eq & ~hp.w1; eq &= hp.w1; } else { eq &= ~hp.w1; }
+    if (th & 2u) { lt |= eq & ~hp.w2; eq &= hp.w2; } else { eq &= ~hp.w2; }
+    if (th & 1u) { lt |= eq & ~hp.w3; eq &= hp.w3; } else { eq &= ~hp.w3; }
+    uint32_t S = moving & lt;
+    const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
+    if (lo_thr != 0u) {
+        uint32_t u = moving & eq;
+        while (u) {
+            const uint32_t j = __builtin_ctz(u);
+            u &= u - 1u;
+            uint32_t x = x0 + j;
+            if (x >= L) x %= L;
+            if (slow_lo28(x, t, sp) < lo_thr) S |= 1u << j;
+        }
+    }
+    return S;
+}
+
+// (P3 P2 P1 P0) >= M for a constant M, bit-sliced over 32 cells.
+template <int M>
+__device__ __forceinline__ uint32_t ge_const(uint32_t P0, uint32_t P1, uint32_t P2, uint32_t P3) {
+    const uint32_t P[4] = {P0, P1, P2, P3};
+    uint32_t gt = 0u, eq = 0xFFFFFFFFu;
+#pragma unroll
+    for (int b = 3; b >= 0; --b) {
+        if ((M >> b) & 1) {
+            eq &= P[b];
+        } else {
+            gt |= eq & P[b];
+            eq &= ~P[b];
+        }
+    }
+    return gt | eq;
+}
+
+template <int VMAX, int M>
+struct Thermo {
+    __device__ static __forceinline__ void fill(uint32_t* T, uint32_t occ, uint32_t P0,
+                                                uint32_t P1, uint32_t P2, uint32_t P3) {
+        T[M] = occ & ge_const<M>(P0, P1, P2, P3);
+        Thermo<VMAX, M + 1>::fill(T, occ, P0, P1, P2, P3);
+    }
+};
+template <int VMAX>
+struct Thermo<VMAX, VMAX + 1> {
+    __device__ static __forceinline__ void fill(uint32_t*, uint32_t, uint32_t, uint32_t, uint32_t,
+                                                uint32_t) {}
+};
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+}  // namespace
+
+// One wave advances one tile item by up to k steps.
+template <int VMAX, int Q>
+__device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it, uint32_t lane,
+                                           uint32_t k, const Clock* __restrict__ clk,
+                                           uint32_t s_off, uint32_t launch_idx) {
+    const uint32_t L = R.L;
+    const SlowParams sp = R.sp;
+    const uint32_t t0 = clk->t + R.t + s_off;
+    uint32_t nsteps = k;
+    if (R.t_end != 0xFFFFFFFFu) nsteps = R.t_end > t0 ? min(k, R.t_end - t0) : 0u;
+    const uint32_t par = (clk->parity + R.parity + launch_idx) & 1u;
+    const uint8_t* __restrict__ src = R.buf[par];
+    uint8_t* __restrict__ dst = R.buf[par ^ 1u];
+
+    const uint32_t own_start = it.tile * R.own;
+    const uint32_t own_len = min(R.own, L - own_start);
+    const uint32_t H = R.halo;
+    const uint32_t seg_len = own_len + 2u * H;
+    const uint32_t s0 = (own_start + L - (H % L)) % L;  // ring cell of segment cell 0
+
+    uint32_t T[Q][VMAX + 1];
+    uint32_t xw[Q];       // ring cell of each word's first cell
+    bool aligned[Q];      // word is one aligned rule-3 block
+    uint32_t own[Q];      // owned cells of each word
+
+    // ---- load: bytes -> bit planes
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t j0 = 32u * (lane * Q + q);
+        const uint32_t x0 = (uint32_t)(((uint64_t)s0 + j0) % L);
+        xw[q] = x0;
+        aligned[q] = ((x0 & 31u) == 0u) && (x0 + 32u <= L);
+        const uint32_t lo = max(H, j0), hi = min(H + own_len, j0 + 32u);
+        own[q] = lo < hi ? bit_range(lo - j0, hi - j0) : 0u;
+
+        uint32_t by[8];
+        if (j0 + 32u <= seg_len && (x0 & 15u) == 0u && x0 + 32u <= L) {
+            const uint4* p = reinterpret_cast<const uint4*>(src + x0);
+            const uint4 a = p[0], b = p[1];
+            by[0] = a.x; by[1] = a.y; by[2] = a.z; by[3] = a.w;
+            by[4] = b.x; by[5] = b.y; by[6] = b.z; by[7] = b.w;
+        } else {
+            uint32_t pos = x0;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                uint32_t w = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    uint32_t val = kEmpty;
+                    if (j0 + (uint32_t)(4 * d + e) < seg_len) val = src[pos];
+                    w |= val << (8 * e);
+                    ++pos;
+                    if (pos >= L) pos = 0;
+                }
+                by[d] = w;
+            }
+        }
+        uint32_t P0 = 0, P1 = 0, P2 = 0, P3 = 0, E = 0;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const uint32_t w = by[d];
+            const uint32_t sh = 4u * d;
+            E |= gather4(w >> 7) << sh;
+            P0 |= gather4(w) << sh;
+            P1 |= gather4(w >> 1) << sh;
+            P2 |= gather4(w >> 2) << sh;
+            P3 |= gather4(w >> 3) << sh;
+        }
+        const uint32_t occ = ~E;
+        T[q][0] = occ;
+        Thermo<VMAX, 1>::fill(T[q], occ, P0, P1, P2, P3);
+    }
+
+    // ---- k steps
+    unsigned long long acc = 0ull;
+    for (uint32_t s = 0; s < nsteps; ++s) {
+        const uint32_t t = t0 + s;
+        uint32_t fl = 0;
+        if constexpr (VMAX > 0) {
+            uint32_t occ_next = __shfl_down(T[0][0], 1);
+            if (lane == 63u) occ_next = 0u;
+            uint32_t Eq[Q][VMAX + 1];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const uint32_t occ = T[q][0];
+                const uint32_t nxt = (q + 1 < Q) ? T[(q + 1) % Q][0] : occ_next;
+                uint32_t T2[VMAX + 2];
+                uint32_t U = 0u;
+#pragma unroll
+                for (int g = 1; g <= VMAX; ++g) {
+                    U |= __builtin_amdgcn_alignbit(nxt, occ, g);   // car in cell i+g
+                    T2[g] = T[q][g - 1] & ~U;                       // rules 1 and 2
+                }
+                T2[VMAX + 1] = 0u;
+                uint32_t S = 0u;
+                if (sp.thr != 0u) {
+                    const uint32_t moving = T2[1];
+                    if (moving) S = slow_mask(moving, xw[q], aligned[q], t, L, sp);  // rule 3
+                }
+                uint32_t T3[VMAX + 2];
+                T3[0] = occ;
+#pragma unroll
+                for (int m = 1; m <= VMAX; ++m) T3[m] = (T2[m] & ~S) | (T2[m + 1] & S);
+                T3[VMAX + 1] = 0u;
+                if (own[q]) {
+#pragma unroll
+                    for (int m = 1; m <= VMAX; ++m) fl += __popc(T3[m] & own[q]);
+                }
+#pragma unroll
+                for (int j = 0; j <= VMAX; ++j) Eq[q][j] = T3[j] & ~T3[j + 1];
+            }
+            // rule 4: cars with v3 == j move j cells right
+            uint32_t prevEq[VMAX + 1];
+#pragma unroll
+            for (int j = 1; j <= VMAX; ++j) {
+                const uint32_t v = __shfl_up(Eq[Q - 1][j], 1);
+                prevEq[j] = lane == 0u ? 0u : v;
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                uint32_t accm = 0u;
+#pragma unroll
+                for (int j = VMAX; j >= 1; --j) {
+                    const uint32_t prv = (q > 0) ? Eq[(q + Q - 1) % Q][j] : prevEq[j];
+                    accm |= __builtin_amdgcn_alignbit(Eq[q][j], prv, 32 - j);
+                    T[q][j] = accm;
+                }
+                T[q][0] = accm | Eq[q][0];
+            }
+        }
+        const uint32_t total = wave_sum(fl);
+        if (lane == 0u) {
+            if (R.flux_log) atomicAdd(&R.flux_log[(uint64_t)t - R.log_t0], (unsigned long long)total);
+            if ((uint64_t)t >= R.warmup) acc += total;
+        }
+    }
+    if (lane == 0u && R.flux_acc && acc) atomicAdd(R.flux_acc, acc);
+
+    // ---- store the owned cells: bit planes -> bytes
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (own[q] == 0u) continue;
+        const uint32_t j0 = 32u * (lane * Q + q);
+        const uint32_t xs = own_start + (j0 - H);
+        uint32_t B0 = 0u, B1 = 0u, B2 = 0u, B3 = 0u;
+        uint32_t Tm[9];
+#pragma unroll
+        for (int m = 0; m <= 8; ++m) Tm[m] = 0u;
+#pragma unroll
+        for (int m = 1; m <= VMAX; ++m) Tm[m] = T[q][m];
+#pragma unroll
+        for (int m = 1; m <= VMAX; ++m) B0 ^= T[q][m];
+        B1 = (Tm[2] & ~Tm[4]) | (Tm[6] & ~Tm[8]);
+        B2 = Tm[4] & ~Tm[8];
+        B3 = Tm[8];
+        const uint32_t E = ~T[q][0];
+        uint32_t by[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const uint32_t sh = 4u * d;
+            by[d] = spread4(B0 >> sh) | (spread4(B1 >> sh) << 1) | (spread4(B2 >> sh) << 2) |
+                    (spread4(B3 >> sh) << 3) | (spread4(E >> sh) * 0xFFu);
+        }
+        if (own[q] == 0xFFFFFFFFu && (xs & 15u) == 0u) {
+            uint4* p = reinterpret_cast<uint4*>(dst + xs);
+            p[0] = make_uint4(by[0], by[1], by[2], by[3]);
+            p[1] = make_uint4(by[4], by[5], by[6], by[7]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 32; ++i)
+                if ((own[q] >> i) & 1u) dst[xs + i] = (uint8_t)(by[i >> 2] >> (8 * (i & 3)));
+        }
+    }
+}
+
+// All items of a launch share vmax: one specialisation.
+template <int VMAX, int Q>
+__global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restrict__ rings,
+                                                         const TileItem* __restrict__ items,
+                                                         uint32_t n_items, uint32_t k,
+                                                         const Clock* __restrict__ clk,
+                                                         uint32_t s_off, uint32_t launch_idx) {
+    const uint32_t wave = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= n_items) return;
+    const TileItem it = items[wave];
+    kstep_tile<VMAX, Q>(rings[it.ring], it, threadIdx.x & 63u, k, clk, s_off, launch_idx);
+}
+
+// Items of different vmax in one launch: the branch on the ring's vmax is
+// uniform over the wave.
+template <int Q>
+__global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* __restrict__ rings,
+                                                               const TileItem* __restrict__ items,
+                                                               uint32_t n_items, uint32_t k,
+                                                               const Clock* __restrict__ clk,
+                                                               uint32_t s_off,
+                                                               uint32_t launch_idx) {
+    const uint32_t wave = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= n_items) return;
+    const TileItem it = items[wave];
+    const RingDesc& R = rings[it.ring];
+    const uint32_t lane = threadIdx.x & 63u;
+    switch (R.vmax) {
+        case 0: kstep_tile<0, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
+        case 1: kstep_tile<1, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
+        case 2: kstep_tile<2, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
+        case 3: kstep_tile<3, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
+        case 4: kstep_tile<4, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
+        case 5: kstep_tile<5, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
+        case 6: kstep_tile<6, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
+        case 7: kstep_tile<7, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
+        case 8: kstep_tile<8, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
+        default: break;
+    }
+}
+
+namespace {
+template <int Q>
+hipError_t launch_q(uint32_t vmax, dim3 grid, hipStream_t s, const RingDesc* rings,
+                    const TileItem* items, uint32_t n_items, uint32_t k, const Clock* clk,
+                    uint32_t s_off, uint32_t launch_idx) {
+#define NASCH_KSTEP_CASE(V)                                                                      \
+    case V:                                                                                      \
+        NASCH_LAUNCH((grid_kstep_kernel<V, Q>), grid, dim3(256), 0, s, rings, items,      \
+                           n_items, k, clk, s_off, launch_idx);                                  \
+        break;
+    switch (vmax) {
+        NASCH_KSTEP_CASE(0)
+        NASCH_KSTEP_CASE(1)
+        NASCH_KSTEP_CASE(2)
+        NASCH_KSTEP_CASE(3)
+        NASCH_KSTEP_CASE(4)
+        NASCH_KSTEP_CASE(5)
+        NASCH_KSTEP_CASE(6)
+        NASCH_KSTEP_CASE(7)
+        NASCH_KSTEP_CASE(8)
+        case kMixedVmax:
+            NASCH_LAUNCH((grid_kstep_mixed_kernel<Q>), grid, dim3(256), 0, s, rings, items,
+                               n_items, k, clk, s_off, launch_idx);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef NASCH_KSTEP_CASE
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_grid_kstep(uint32_t vmax, uint32_t q, const RingDesc* rings,
+                             const TileItem* items, uint32_t n_items, uint32_t k,
+                             const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                             hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const dim3 grid((n_items + 3u) / 4u);
+    switch (q) {
+        case 1: return launch_q<1>(vmax, grid, s, rings, items, n_items, k, clk, s_off, launch_idx);
+        case 2: return launch_q<2>(vmax, grid, s, rings, items, n_items, k, clk, s_off, launch_idx);
+        case 4: return launch_q<4>(vmax, grid, s, rings, items, n_items, k, clk, s_off, launch_idx);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace nasch

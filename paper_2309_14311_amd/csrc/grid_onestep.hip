@@ -1,0 +1,149 @@
+// grid_onestep.hip -- the plain grid kernel: one step per launch, one byte per
+// cell, a workgroup per tile of kOneStepTile cells staged through LDS with a
+// vmax halo on each side (rules 1-4 of the Handout, applied car by car).
+//
+// Each thread owns 32 consecutive cells (one aligned rule-3 block, so one
+// Philox call covers them), computes the new velocity of every car it owns and
+// scatters the car into a cleared LDS copy of the tile.  Cars up to vmax cells
+// left of the tile can land inside it; thread 0 recomputes those as well.  The
+// tile is then written back with 16-byte stores.  F(t) counts owned cars only.
+#include "launchers.hpp"
+
+namespace nasch {
+
+namespace {
+constexpr uint32_t kThreads = 256;
+constexpr uint32_t kHalo = 16;  // >= vmax
+constexpr uint32_t kTile = kOneStepTile;
+static_assert(kTile == kThreads * 32, "one 32-cell block per thread");
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// New velocity of the car at tile-local cell c (rules 1-3); `in` is the LDS
+// copy indexed by tile-local cell + kHalo.
+__device__ __forceinline__ uint32_t car_velocity(const uint8_t* in, int c, uint32_t vmax,
+                                                 uint32_t hi4, bool hi_known, uint32_t x,
+                                                 uint32_t t, const SlowParams& sp) {
+    const uint32_t v = in[kHalo + c];
+    uint32_t d = 1;
+    while (d <= vmax && in[kHalo + c + d] == kEmpty) ++d;
+    uint32_t nv = min(v + 1u, vmax);       // rule 1
+    if (nv >= d) nv = d - 1u;              // rule 2
+    if (nv > 0 && sp.thr != 0) {           // rule 3
+        bool slow;
+        if (hi_known) slow = slow_from_hi(hi4, x, t, sp);
+        else slow = rand32(x, t, sp) < sp.thr;
+        if (slow) --nv;
+    }
+    return nv;
+}
+}  // namespace
+
+__global__ __launch_bounds__(kThreads) void grid_onestep_kernel(const RingDesc* __restrict__ ring,
+                                                                const Clock* __restrict__ clk,
+                                                                uint32_t s_off,
+                                                                uint32_t launch_idx) {
+    __shared__ __align__(16) uint8_t s_in[kTile + 2 * kHalo];
+    __shared__ __align__(16) uint8_t s_out[kTile];
+    __shared__ uint32_t s_flux[kThreads / 64];
+
+    const RingDesc& R = *ring;
+    const uint32_t L = R.L, vmax = R.vmax;
+    const SlowParams sp = R.sp;
+    const uint32_t t = clk->t + R.t + s_off;
+    const uint32_t par = (clk->parity + R.parity + launch_idx) & 1u;
+    const uint8_t* __restrict__ src = R.buf[par];
+    uint8_t* __restrict__ dst = R.buf[par ^ 1u];
+
+    const uint32_t start = blockIdx.x * kTile;
+    const uint32_t len = min(kTile, L - start);
+    const uint32_t tid = threadIdx.x;
+
+    // ---- load the tile and its halos (cells start-kHalo .. start+len+kHalo, mod L)
+    if (start >= kHalo && (uint64_t)start + kTile + kHalo <= L) {
+        const uint4* s4 = reinterpret_cast<const uint4*>(src + start - kHalo);
+        uint4* d4 = reinterpret_cast<uint4*>(s_in);
+        for (uint32_t i = tid; i < (kTile + 2 * kHalo) / 16; i += kThreads) d4[i] = s4[i];
+    } else {
+        for (uint32_t i = tid; i < kTile + 2 * kHalo; i += kThreads) {
+            const int64_t c = (int64_t)i - kHalo;
+            uint8_t val = (uint8_t)kEmpty;
+            if (c < (int64_t)len + kHalo) {
+                int64_t pos = ((int64_t)start + c) % (int64_t)L;
+                if (pos < 0) pos += L;
+                val = src[pos];
+            }
+            s_in[i] = val;
+        }
+    }
+    {
+        uint4* o4 = reinterpret_cast<uint4*>(s_out);
+        const uint4 e = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+        for (uint32_t i = tid; i < kTile / 16; i += kThreads) o4[i] = e;
+    }
+    __syncthreads();
+
+    // ---- owned cars
+    uint32_t flux = 0;
+    const uint32_t c0 = tid * 32u;
+    if (c0 < len) {
+        const uint32_t n = min(32u, len - c0);
+        bool any = false;
+        for (uint32_t j = 0; j < n; ++j) any |= (s_in[kHalo + c0 + j] != kEmpty);
+        if (any) {
+            Word4 hp{0, 0, 0, 0};
+            if (sp.thr != 0) hp = slow_hi_planes((start + c0) >> 5, t, sp);
+            for (uint32_t j = 0; j < n; ++j) {
+                const int c = (int)(c0 + j);
+                if (s_in[kHalo + c] == kEmpty) continue;
+                const uint32_t hi4 = (((hp.w0 >> j) & 1u) << 3) | (((hp.w1 >> j) & 1u) << 2) |
+                                     (((hp.w2 >> j) & 1u) << 1) | ((hp.w3 >> j) & 1u);
+                const uint32_t v = car_velocity(s_in, c, vmax, hi4, true, start + c0 + j, t, sp);
+                if ((uint32_t)c + v < len) s_out[c + v] = (uint8_t)v;
+                flux += v;
+            }
+        }
+    }
+    // ---- cars up to vmax cells left of the tile that may land inside it
+    if (tid == 0) {
+        for (int c = -(int)vmax; c < 0; ++c) {
+            if (s_in[kHalo + c] == kEmpty) continue;
+            int64_t pos = ((int64_t)start + c) % (int64_t)L;
+            if (pos < 0) pos += L;
+            const uint32_t v = car_velocity(s_in, c, vmax, 0, false, (uint32_t)pos, t, sp);
+            const int dstc = c + (int)v;
+            if (dstc >= 0 && (uint32_t)dstc < len) s_out[dstc] = (uint8_t)v;
+        }
+    }
+    const uint32_t wsum = wave_sum(flux);
+    if ((tid & 63u) == 0) s_flux[tid >> 6] = wsum;
+    __syncthreads();
+
+    // ---- write back
+    if (len == kTile) {
+        const uint4* o4 = reinterpret_cast<const uint4*>(s_out);
+        uint4* d4 = reinterpret_cast<uint4*>(dst + start);
+        for (uint32_t i = tid; i < kTile / 16; i += kThreads) d4[i] = o4[i];
+    } else {
+        for (uint32_t i = tid; i < len; i += kThreads) dst[start + i] = s_out[i];
+    }
+    if (tid == 0) {
+        uint32_t total = 0;
+        for (uint32_t w = 0; w < kThreads / 64; ++w) total += s_flux[w];
+        if (R.flux_log) atomicAdd(&R.flux_log[(uint64_t)t - R.log_t0], (unsigned long long)total);
+        if (R.flux_acc && (uint64_t)t >= R.warmup) atomicAdd(R.flux_acc, (unsigned long long)total);
+    }
+}
+
+hipError_t launch_grid_onestep(const RingDesc* ring, uint32_t L, const Clock* clk, uint32_t s_off,
+                               uint32_t launch_idx, hipStream_t s) {
+    const uint32_t blocks = (uint32_t)(((uint64_t)L + kTile - 1) / kTile);
+    NASCH_LAUNCH(grid_onestep_kernel, dim3(blocks), dim3(kThreads), 0, s, ring, clk, s_off,
+                       launch_idx);
+    return hipGetLastError();
+}
+
+}  // namespace nasch

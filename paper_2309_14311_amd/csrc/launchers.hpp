@@ -1,0 +1,62 @@
+// launchers.hpp -- host-side entry points of the kernel translation units.
+// Each returns the hipError_t of its launch (hipSuccess = 0).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nasch_device.hpp"
+
+namespace nasch {
+
+// Launch and report the launch's own error: a stale error left by an earlier
+// call whose status was deliberately ignored is cleared first.
+#define NASCH_LAUNCH(...)                 \
+    do {                                  \
+        (void)hipGetLastError();          \
+        hipLaunchKernelGGL(__VA_ARGS__);  \
+    } while (0)
+
+// ---- init (init.hip) ----------------------------------------------------------
+// Grid at t = 0 for cells [0, L): EMPTY, or the initial velocity where the
+// placement puts a car.
+hipError_t launch_init_grid(uint8_t* g, uint32_t L, uint32_t N, uint32_t vmax, uint32_t init_v,
+                            SlowParams sp, hipStream_t s);
+// Occupied-cell count of each chunk of kCompactChunk cells.
+constexpr uint32_t kCompactChunk = 65536;
+hipError_t launch_count_chunks(const uint8_t* g, uint32_t L, uint32_t* counts, hipStream_t s);
+// Writes x, v of the occupied cells in ascending order; offsets[c] is the
+// exclusive prefix of counts.
+hipError_t launch_compact_chunks(const uint8_t* g, uint32_t L, const uint32_t* offsets,
+                                 int32_t* x, uint8_t* v, hipStream_t s);
+// Grid of an agent state: fill with EMPTY, then g[x[i]] = v[i].
+hipError_t launch_agent_to_grid(const int32_t* x, const uint8_t* v, uint32_t N, uint8_t* g,
+                                uint32_t L, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t value, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, hipStream_t s);
+hipError_t launch_clock_advance(Clock* clk, uint32_t T, uint32_t nlaunch, hipStream_t s);
+
+// ---- grid, byte-wise one step per launch (grid_onestep.hip) --------------------
+constexpr uint32_t kOneStepTile = 8192;
+hipError_t launch_grid_onestep(const RingDesc* ring, uint32_t L, const Clock* clk, uint32_t s_off,
+                               uint32_t launch_idx, hipStream_t s);
+
+// ---- grid, bit-sliced, k steps per launch (grid_kstep.hip) --------------------
+// Cells per wave segment for q words of 32 cells per lane.
+constexpr uint32_t kstep_segment(uint32_t q) { return 64u * 32u * q; }
+// vmax = kMixedVmax launches the kernel that branches on each ring's vmax;
+// otherwise every item's ring must have this vmax.
+constexpr uint32_t kMixedVmax = 0xFFu;
+hipError_t launch_grid_kstep(uint32_t vmax, uint32_t q, const RingDesc* rings,
+                             const TileItem* items, uint32_t n_items, uint32_t k,
+                             const Clock* clk, uint32_t s_off, uint32_t launch_idx, hipStream_t s);
+
+// ---- agent (agent.hip) --------------------------------------------------------
+hipError_t launch_agent_onestep(const AgentDesc* a, uint32_t N, const Clock* clk, uint32_t s_off,
+                                uint32_t launch_idx, hipStream_t s);
+// k steps per launch: each wave holds 64 * kAgentCarsPerLane consecutive cars and
+// writes back all but the last k of them.
+constexpr uint32_t kAgentCarsPerLane = 8;
+hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t ntiles, uint32_t k, const Clock* clk,
+                              uint32_t s_off, uint32_t launch_idx, hipStream_t s);
+
+}  // namespace nasch

@@ -1,0 +1,170 @@
+// nasch_device.hpp -- device-side building blocks shared by the libnasch kernels:
+// Philox4x32-10, the rule-3 draw, the Feistel placement, and the descriptor
+// structs the runtime hands to the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nasch {
+
+constexpr uint32_t kEmpty = 0xFFu;
+// Counter word 3 of Philox separates the independent streams.
+constexpr uint32_t kTagSlowHi = 1u;  // rule 3: top 4 bits of R, one block per 32 cells
+constexpr uint32_t kTagSlowLo = 2u;  // rule 3: low 28 bits of R, one block per cell
+constexpr uint32_t kTagPlace = 3u;   // initial placement (Feistel round function)
+constexpr uint32_t kTagVel0 = 4u;    // initial velocities
+
+struct Word4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two 32x32->64
+// multiplies by the Philox constants, key bumped by the Weyl constants between
+// rounds.  With a wave-uniform key and counter words 1-3 uniform, the compiler
+// keeps the key schedule and the first multiply of round 0 in scalar registers.
+__device__ __forceinline__ Word4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Word4{c0, c1, c2, c3};
+}
+
+// Per-simulation constants of rule 3.
+struct SlowParams {
+    uint32_t k0, k1;     // Philox key: seed low / high word
+    uint32_t replica;    // counter word 2
+    uint32_t thr;        // floor(p * 2^32); 0 disables rule 3 draws entirely
+};
+
+// The four top-bit planes of R for the aligned block of 32 cells [32*blk, 32*blk+32):
+// bit j of word i is bit (31 - i) of R for cell 32*blk + j.
+__device__ __forceinline__ Word4 slow_hi_planes(uint32_t blk, uint32_t t, const SlowParams& sp) {
+    return philox(blk, t, sp.replica, kTagSlowHi, sp.k0, sp.k1);
+}
+
+// Low 28 bits of R for cell x.
+__device__ __forceinline__ uint32_t slow_lo28(uint32_t x, uint32_t t, const SlowParams& sp) {
+    return philox(x, t, sp.replica, kTagSlowLo, sp.k0, sp.k1).w0 >> 4;
+}
+
+// Full R for one cell (used where cells are handled one at a time).
+__device__ __forceinline__ uint32_t rand32(uint32_t x, uint32_t t, const SlowParams& sp) {
+    const Word4 b = slow_hi_planes(x >> 5, t, sp);
+    const uint32_t s = x & 31u;
+    const uint32_t hi = (((b.w0 >> s) & 1u) << 3) | (((b.w1 >> s) & 1u) << 2) |
+                        (((b.w2 >> s) & 1u) << 1) | ((b.w3 >> s) & 1u);
+    return (hi << 28) | slow_lo28(x, t, sp);
+}
+
+// Rule 3 decision for a car whose top nibble of R is already known.
+__device__ __forceinline__ bool slow_from_hi(uint32_t hi4, uint32_t x, uint32_t t,
+                                             const SlowParams& sp) {
+    const uint32_t th = sp.thr >> 28;
+    if (hi4 != th) return hi4 < th;
+    const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
+    if (lo_thr == 0) return false;
+    return slow_lo28(x, t, sp) < lo_thr;
+}
+
+// ---- initial placement --------------------------------------------------------
+// b = ceil(log2 L) rounded up to even, at least 2.
+__host__ __device__ inline uint32_t feistel_bits(uint64_t L) {
+    uint32_t b = 0;
+    while ((1ull << b) < L) ++b;
+    b += b & 1u;
+    return b < 2 ? 2 : b;
+}
+
+// Inverse of the 4-round Feistel permutation on b bits: forward round j maps
+// (l, r) to (r, l ^ F_j(r)); undo rounds 3..0.
+__device__ __forceinline__ uint32_t feistel_inv(uint32_t y, uint32_t half, uint32_t mask,
+                                                const SlowParams& sp) {
+    uint32_t l = (y >> half) & mask, r = y & mask;
+#pragma unroll
+    for (int j = 3; j >= 0; --j) {
+        const uint32_t f = philox(l, (uint32_t)j, sp.replica, kTagPlace, sp.k0, sp.k1).w0 & mask;
+        const uint32_t pr = l;
+        l = r ^ f;
+        r = pr;
+    }
+    return (l << half) | r;
+}
+
+// Index of the car that starts in cell y (cycle-walking the inverse until it
+// lands in [0, L)); the cell is occupied iff the index is below N.
+__device__ __forceinline__ uint32_t placement_preimage(uint32_t y, uint32_t L, uint32_t b,
+                                                       const SlowParams& sp) {
+    const uint32_t half = b >> 1;
+    const uint32_t mask = (half >= 32) ? 0xFFFFFFFFu : ((1u << half) - 1u);
+    uint32_t z = feistel_inv(y, half, mask, sp);
+    while (z >= L) z = feistel_inv(z, half, mask, sp);
+    return z;
+}
+
+__device__ __forceinline__ uint32_t initial_velocity(uint32_t x, uint32_t vmax, const SlowParams& sp) {
+    const uint32_t w = philox(x, 0u, sp.replica, kTagVel0, sp.k0, sp.k1).w0;
+    return (uint32_t)(((uint64_t)w * (uint64_t)(vmax + 1u)) >> 32);
+}
+
+// ---- descriptors --------------------------------------------------------------
+// One ring as the temporal-blocked grid kernel sees it.  Tiles own `own` cells
+// each (the last one the remainder); a tile's segment is its owned cells plus
+// `halo` cells on each side, read modulo L.
+struct RingDesc {
+    uint8_t* buf[2];         // ping-pong grids, L bytes each
+    unsigned long long* flux_log;  // F(t) at flux_log[t - log_t0] (may be null)
+    unsigned long long* flux_acc;  // += F(t) for t >= warmup (may be null)
+    uint64_t log_t0;
+    uint64_t warmup;
+    uint32_t t;              // step of the state in buf[parity] when the launch sequence starts
+    uint32_t parity;
+    uint32_t L, vmax;
+    uint32_t own, halo;      // geometry for the current (k, q)
+    uint32_t ntiles;
+    uint32_t t_end;          // no step t >= t_end is run (serving); 0xFFFFFFFF = none
+    SlowParams sp;
+};
+
+struct TileItem {
+    uint32_t ring;   // index into the RingDesc table
+    uint32_t tile;   // tile index within the ring
+};
+
+// Step counter and buffer parity shared by every ring of a launch sequence.  It
+// lives in device memory so that a captured launch sequence can be replayed:
+// launch i of a sequence runs steps clock.t + ring.t + s_off ... and reads
+// buf[(clock.parity + ring.parity + i) & 1].  A one-thread kernel advances it
+// after the sequence.
+struct Clock {
+    uint32_t t;
+    uint32_t parity;
+};
+
+// One ring in the agent representation.
+struct AgentDesc {
+    int32_t* x[2];           // ping-pong positions, road order
+    uint8_t* v[2];           // ping-pong velocities
+    unsigned long long* flux_log;
+    unsigned long long* flux_acc;
+    uint64_t log_t0;
+    uint64_t warmup;
+    uint32_t t, parity;
+    uint32_t N, L, vmax;
+    uint32_t own;            // cars written back per tile by the k-step kernel
+    uint32_t ntiles;
+    uint32_t pad;
+    SlowParams sp;
+};
+
+}  // namespace nasch

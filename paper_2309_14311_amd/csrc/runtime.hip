@@ -1,0 +1,549 @@
+// runtime.hip -- the C ABI of libnasch for single simulations and batches.
+// Entry points are declared and documented in include/nasch.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "engine.hpp"
+#include "nasch.h"
+
+using namespace nasch;
+
+namespace {
+constexpr uint32_t kDefaultK = 32;
+constexpr uint32_t kDefaultQ = 4;
+constexpr uint32_t kDefaultAgentK = 32;
+
+// Default (k, q) for a ring: the largest segment, k = 32 or the most it admits.
+void default_tuning(uint32_t L, uint32_t vmax, uint32_t* k, uint32_t* q) {
+    *q = kDefaultQ;
+    if (L <= 2048) *q = 1;
+    *k = std::min(kDefaultK, kstep_max_k(vmax, *q));
+    if (*k == 0) *k = 1;
+}
+}  // namespace
+
+struct nasch_sim {
+    // model
+    uint64_t L = 0, N = 0, seed = 0;
+    uint32_t vmax = 0, thr = 0, replica = 0, rep = 0, init_v = 0;
+    double p = 0;
+    // tuning
+    uint32_t kernel = NASCH_KERNEL_KSTEP, k = kDefaultK, q = kDefaultQ, use_graph = 0;
+    // stream and status
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    HipStatus st;
+    // step counter (host mirror of the device clock)
+    uint64_t t = 0;
+    uint32_t parity = 0;
+    Clock* d_clk = nullptr;
+    // grid representation
+    uint8_t* grid[2] = {nullptr, nullptr};
+    GridEngine eng;           // one ring, its tiles
+    RingDesc* d_onestep = nullptr;  // the same ring for the one-step kernel
+    // agent representation
+    int32_t* ax[2] = {nullptr, nullptr};
+    uint8_t* av[2] = {nullptr, nullptr};
+    AgentDesc h_agent{};
+    AgentDesc* d_agent = nullptr;
+    uint8_t* agent_grid = nullptr;  // scratch grid for snapshots
+    // F(t) log: flux[t - log_t0]
+    unsigned long long* flux = nullptr;
+    uint64_t flux_cap = 0, log_t0 = 0;
+    GraphCache graphs;
+    uint64_t dev_bytes = 0;
+
+    ~nasch_sim();
+    int fail() { return NASCH_EDEVICE; }
+    bool ok(hipError_t e) { return st.ok(e); }
+    int ensure_log(uint64_t steps);
+    int refresh_descs();
+    int enqueue_steps(uint64_t T);
+    int set_tuning(uint32_t kern, uint32_t kk, uint32_t qq);
+    const uint8_t* current_grid_device();
+};
+
+nasch_sim::~nasch_sim() {
+    graphs.clear();
+    eng.release();
+    // agent_grid aliases grid[0]
+    void* ps[] = {d_clk, grid[0], grid[1], d_onestep, ax[0], ax[1], av[0], av[1], d_agent, flux};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+    (void)hipGetLastError();  // errors of the teardown are not reported to later calls
+}
+
+// Keep room in the flux log for `steps` more steps from t.
+int nasch_sim::ensure_log(uint64_t steps) {
+    const uint64_t need = t + steps - log_t0;
+    if (need <= flux_cap) return NASCH_OK;
+    uint64_t cap = std::max<uint64_t>(need, std::max<uint64_t>(1024, flux_cap * 2));
+    unsigned long long* nf = nullptr;
+    if (!ok(dev_alloc(&nf, cap))) return NASCH_ENOMEM;
+    if (!ok(launch_fill_u64(nf, cap, stream))) { (void)hipFree(nf); return fail(); }
+    if (flux && flux_cap) {
+        if (!ok(hipMemcpyAsync(nf, flux, flux_cap * sizeof(unsigned long long),
+                               hipMemcpyDeviceToDevice, stream))) {
+            (void)hipFree(nf);
+            return fail();
+        }
+    }
+    if (!ok(hipStreamSynchronize(stream))) { (void)hipFree(nf); return fail(); }
+    if (flux) (void)hipFree(flux);
+    dev_bytes += (cap - flux_cap) * sizeof(unsigned long long);
+    flux = nf;
+    flux_cap = cap;
+    return refresh_descs();
+}
+
+// Push the descriptors (pointers, geometry) to the device.
+int nasch_sim::refresh_descs() {
+    if (rep == NASCH_REP_GRID) {
+        RingDesc& r = eng.rings[0];
+        r.flux_log = flux;
+        r.log_t0 = log_t0;
+        if (!ok(eng.upload_rings(stream))) return fail();
+        if (!ok(hipMemcpyAsync(d_onestep, &r, sizeof(RingDesc), hipMemcpyHostToDevice, stream)))
+            return fail();
+    } else {
+        h_agent.flux_log = flux;
+        h_agent.log_t0 = log_t0;
+        if (!ok(hipMemcpyAsync(d_agent, &h_agent, sizeof(AgentDesc), hipMemcpyHostToDevice, stream)))
+            return fail();
+    }
+    if (!ok(hipStreamSynchronize(stream))) return fail();
+    return NASCH_OK;
+}
+
+int nasch_sim::set_tuning(uint32_t kern, uint32_t kk, uint32_t qq) {
+    if (kern == NASCH_KERNEL_AUTO) kern = NASCH_KERNEL_KSTEP;
+    if (kern != NASCH_KERNEL_ONESTEP && kern != NASCH_KERNEL_KSTEP) return NASCH_EINVAL;
+    if (kk == 0) kk = k;
+    if (qq == 0) qq = q;
+    if (rep == NASCH_REP_GRID) {
+        if (kern == NASCH_KERNEL_KSTEP) {
+            uint32_t o, h, n;
+            if (!kstep_geometry((uint32_t)L, vmax, kk, qq, &o, &h, &n)) return NASCH_EINVAL;
+            if (eng.k != kk || eng.q != qq) {
+                if (!ok(eng.set_geometry(kk, qq, stream))) return fail();
+                graphs.clear();
+            }
+        }
+    } else {
+        if (qq != 1 && qq != 2 && qq != 4) return NASCH_EINVAL;
+        if (kern == NASCH_KERNEL_KSTEP) {
+            uint32_t own, ntiles;
+            if (!agent_geometry((uint32_t)N, kk, &own, &ntiles)) return NASCH_EINVAL;
+            if (h_agent.own != own || h_agent.ntiles != ntiles) {
+                h_agent.own = own;
+                h_agent.ntiles = ntiles;
+                graphs.clear();
+                if (!ok(hipMemcpyAsync(d_agent, &h_agent, sizeof(AgentDesc), hipMemcpyHostToDevice,
+                                       stream)) ||
+                    !ok(hipStreamSynchronize(stream)))
+                    return fail();
+            }
+        }
+    }
+    kernel = kern;
+    k = kk;
+    q = qq;
+    return NASCH_OK;
+}
+
+// The launches of T steps followed by the clock update (not synchronised).
+int nasch_sim::enqueue_steps(uint64_t T) {
+    auto body = [&]() -> hipError_t {
+        uint32_t nl = 0;
+        if (rep == NASCH_REP_GRID) {
+            if (kernel == NASCH_KERNEL_ONESTEP) {
+                for (uint64_t i = 0; i < T; ++i) {
+                    hipError_t e = launch_grid_onestep(d_onestep, (uint32_t)L, d_clk, (uint32_t)i,
+                                                       (uint32_t)i, stream);
+                    if (e != hipSuccess) return e;
+                }
+                nl = (uint32_t)T;
+            } else {
+                hipError_t e = eng.enqueue(T, d_clk, stream);
+                if (e != hipSuccess) return e;
+                nl = eng.launches_for(T);
+            }
+        } else {
+            if (kernel == NASCH_KERNEL_ONESTEP) {
+                for (uint64_t i = 0; i < T; ++i) {
+                    hipError_t e = launch_agent_onestep(d_agent, (uint32_t)N, d_clk, (uint32_t)i,
+                                                        (uint32_t)i, stream);
+                    if (e != hipSuccess) return e;
+                }
+                nl = (uint32_t)T;
+            } else {
+                nl = (uint32_t)((T + k - 1) / k);
+                for (uint32_t i = 0; i < nl; ++i) {
+                    const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
+                    hipError_t e = launch_agent_kstep(d_agent, h_agent.ntiles, ki, d_clk, i * k, i,
+                                                      stream);
+                    if (e != hipSuccess) return e;
+                }
+            }
+        }
+        return launch_clock_advance(d_clk, (uint32_t)T, nl, stream);
+    };
+    hipError_t e;
+    if (use_graph) {
+        e = graphs.run(std::make_tuple(T, kernel, k, q, eng.version), stream, body);
+    } else {
+        e = body();
+    }
+    if (!ok(e)) return fail();
+    uint32_t nl;
+    if (kernel == NASCH_KERNEL_ONESTEP) nl = (uint32_t)T;
+    else if (rep == NASCH_REP_GRID) nl = eng.launches_for(T);
+    else nl = (uint32_t)((T + k - 1) / k);
+    t += T;
+    parity ^= nl & 1u;
+    return NASCH_OK;
+}
+
+const uint8_t* nasch_sim::current_grid_device() {
+    if (rep == NASCH_REP_GRID) return grid[parity];
+    if (!ok(launch_agent_to_grid(ax[parity], av[parity], (uint32_t)N, agent_grid, (uint32_t)L,
+                                 stream)))
+        return nullptr;
+    return agent_grid;
+}
+
+// Agent vectors from the grid in grid[0] (used at init and restore).
+static int agent_from_grid(nasch_sim* h, const uint8_t* d_grid) {
+    const uint32_t chunks = (uint32_t)((h->L + kCompactChunk - 1) / kCompactChunk);
+    uint32_t* d_counts = nullptr;
+    if (!h->ok(dev_alloc(&d_counts, chunks))) return NASCH_ENOMEM;
+    std::vector<uint32_t> counts(chunks), offs(chunks);
+    int rc = NASCH_OK;
+    if (!h->ok(launch_count_chunks(d_grid, (uint32_t)h->L, d_counts, h->stream)) ||
+        !h->ok(hipMemcpyAsync(counts.data(), d_counts, chunks * sizeof(uint32_t),
+                              hipMemcpyDeviceToHost, h->stream)) ||
+        !h->ok(hipStreamSynchronize(h->stream))) {
+        rc = NASCH_EDEVICE;
+    } else {
+        uint64_t acc = 0;
+        for (uint32_t c = 0; c < chunks; ++c) {
+            offs[c] = (uint32_t)acc;
+            acc += counts[c];
+        }
+        if (acc != h->N) {
+            rc = NASCH_EINVAL;
+        } else if (!h->ok(hipMemcpyAsync(d_counts, offs.data(), chunks * sizeof(uint32_t),
+                                         hipMemcpyHostToDevice, h->stream)) ||
+                   !h->ok(launch_compact_chunks(d_grid, (uint32_t)h->L, d_counts,
+                                                h->ax[h->parity], h->av[h->parity], h->stream)) ||
+                   !h->ok(hipStreamSynchronize(h->stream))) {
+            rc = NASCH_EDEVICE;
+        }
+    }
+    (void)hipFree(d_counts);
+    return rc;
+}
+
+extern "C" {
+
+void nasch_default_opts(nasch_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->rep = NASCH_REP_GRID;
+    o->init_v = NASCH_INIT_V_ZERO;
+    o->kernel = NASCH_KERNEL_AUTO;
+}
+
+const char* nasch_strerror(int s) {
+    switch (s) {
+        case NASCH_OK: return "ok";
+        case NASCH_EINVAL: return "invalid argument";
+        case NASCH_ENOMEM: return "out of memory";
+        case NASCH_EDEVICE: return "HIP device error";
+        case NASCH_ERANGE: return "step counter would reach 2^32";
+        case NASCH_ESTATE: return "invalid state for this call";
+        case NASCH_EBUSY: return "busy";
+        case NASCH_ENOTFOUND: return "not found";
+        default: return "unknown status";
+    }
+}
+
+int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p, uint64_t seed,
+               const nasch_opts* opts) {
+    if (!out) return NASCH_EINVAL;
+    *out = nullptr;
+    int rc = validate_params(L, N, vmax, p);
+    if (rc) return rc;
+    nasch_opts o;
+    nasch_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.rep > NASCH_REP_AGENT || o.init_v > NASCH_INIT_V_UNIFORM || o.kernel > NASCH_KERNEL_KSTEP)
+        return NASCH_EINVAL;
+    std::unique_ptr<nasch_sim> h(new (std::nothrow) nasch_sim());
+    if (!h) return NASCH_ENOMEM;
+    h->L = L; h->N = N; h->vmax = vmax; h->p = p; h->seed = seed;
+    h->thr = threshold_of(p);
+    h->replica = o.replica; h->rep = o.rep; h->init_v = o.init_v;
+    h->use_graph = o.use_graph;
+    if (o.stream) {
+        h->stream = (hipStream_t)o.stream;
+    } else {
+        if (!h->ok(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking))) return NASCH_EDEVICE;
+        h->own_stream = true;
+    }
+    const SlowParams sp = slow_params(seed, o.replica, p);
+    if (!h->ok(dev_alloc(&h->d_clk, 1))) return NASCH_ENOMEM;
+    const Clock c0{0u, 0u};
+    if (!h->ok(hipMemcpyAsync(h->d_clk, &c0, sizeof(Clock), hipMemcpyHostToDevice, h->stream)))
+        return NASCH_EDEVICE;
+
+    // initial grid (both representations start from it)
+    uint8_t* g0 = nullptr;
+    if (!h->ok(dev_alloc(&h->grid[0], L))) return NASCH_ENOMEM;
+    g0 = h->grid[0];
+    if (!h->ok(launch_init_grid(g0, (uint32_t)L, (uint32_t)N, vmax, o.init_v, sp, h->stream)))
+        return NASCH_EDEVICE;
+    h->dev_bytes += L;
+
+    if (o.rep == NASCH_REP_GRID) {
+        if (!h->ok(dev_alloc(&h->grid[1], L))) return NASCH_ENOMEM;
+        h->dev_bytes += L;
+        RingDesc r{};
+        r.buf[0] = h->grid[0];
+        r.buf[1] = h->grid[1];
+        r.L = (uint32_t)L;
+        r.vmax = vmax;
+        r.sp = sp;
+        r.t_end = 0xFFFFFFFFu;
+        r.warmup = ~0ull;
+        h->eng.rings.push_back(r);
+        if (!h->ok(dev_alloc(&h->d_onestep, 1))) return NASCH_ENOMEM;
+        uint32_t kk = o.k, qq = o.q;
+        uint32_t dk, dq;
+        default_tuning((uint32_t)L, vmax, &dk, &dq);
+        if (!qq) qq = dq;
+        if (!kk) kk = std::min(dk, std::max(1u, kstep_max_k(vmax, qq)));
+        h->k = kk; h->q = qq;
+        uint32_t kern = o.kernel == NASCH_KERNEL_AUTO ? NASCH_KERNEL_KSTEP : o.kernel;
+        // geometry of the k-step kernel is needed even when starting one-step
+        uint32_t ow, ha, nt;
+        if (!kstep_geometry((uint32_t)L, vmax, kk, qq, &ow, &ha, &nt)) return NASCH_EINVAL;
+        if (!h->ok(h->eng.set_geometry(kk, qq, h->stream))) return NASCH_EDEVICE;
+        h->kernel = kern;
+    } else {
+        if (!h->ok(dev_alloc(&h->ax[0], N)) || !h->ok(dev_alloc(&h->ax[1], N)) ||
+            !h->ok(dev_alloc(&h->av[0], N)) || !h->ok(dev_alloc(&h->av[1], N)) ||
+            !h->ok(dev_alloc(&h->d_agent, 1)))
+            return NASCH_ENOMEM;
+        h->agent_grid = g0;  // the init grid doubles as the snapshot scratch
+        h->dev_bytes += 10 * N;
+        AgentDesc& a = h->h_agent;
+        a.x[0] = h->ax[0]; a.x[1] = h->ax[1];
+        a.v[0] = h->av[0]; a.v[1] = h->av[1];
+        a.N = (uint32_t)N; a.L = (uint32_t)L; a.vmax = vmax;
+        a.sp = sp;
+        a.warmup = ~0ull;
+        uint32_t kk = o.k ? o.k : kDefaultAgentK;
+        if (!agent_geometry((uint32_t)N, kk, &a.own, &a.ntiles)) return NASCH_EINVAL;
+        h->k = kk;
+        h->q = o.q ? o.q : 1;
+        h->kernel = o.kernel == NASCH_KERNEL_AUTO ? NASCH_KERNEL_KSTEP : o.kernel;
+        rc = agent_from_grid(h.get(), g0);
+        if (rc) return rc;
+    }
+    rc = h->ensure_log(1024);
+    if (rc) return rc;
+    rc = h->refresh_descs();
+    if (rc) return rc;
+    if (!h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
+    *out = h.release();
+    return NASCH_OK;
+}
+
+int nasch_step_n(nasch_sim* h, uint64_t T) {
+    if (!h) return NASCH_EINVAL;
+    if (T == 0) return NASCH_OK;
+    if (h->t + T > 0xFFFFFFFFull) return NASCH_ERANGE;
+    int rc = h->ensure_log(T);
+    if (rc) return rc;
+    return h->enqueue_steps(T);
+}
+
+int nasch_timed_step_n(nasch_sim* h, uint64_t T, double* ms) {
+    if (!h) return NASCH_EINVAL;
+    if (h->t + T > 0xFFFFFFFFull) return NASCH_ERANGE;
+    int rc = h->ensure_log(T);
+    if (rc) return rc;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (!h->ok(hipEventCreate(&a)) || !h->ok(hipEventCreate(&b))) return NASCH_EDEVICE;
+    rc = NASCH_OK;
+    if (!h->ok(hipEventRecord(a, h->stream))) rc = NASCH_EDEVICE;
+    if (!rc && T) rc = h->enqueue_steps(T);
+    if (!rc && !h->ok(hipEventRecord(b, h->stream))) rc = NASCH_EDEVICE;
+    if (!rc && !h->ok(hipEventSynchronize(b))) rc = NASCH_EDEVICE;
+    float f = 0;
+    if (!rc && !h->ok(hipEventElapsedTime(&f, a, b))) rc = NASCH_EDEVICE;
+    if (ms) *ms = f;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return rc;
+}
+
+int nasch_flux(nasch_sim* h, uint64_t t0, uint64_t count, uint64_t* out) {
+    if (!h || (count && !out)) return NASCH_EINVAL;
+    if (t0 < h->log_t0 || t0 + count > h->t) return NASCH_EINVAL;
+    if (count == 0) return NASCH_OK;
+    if (!h->ok(hipMemcpyAsync(out, h->flux + (t0 - h->log_t0), count * sizeof(uint64_t),
+                              hipMemcpyDeviceToHost, h->stream)) ||
+        !h->ok(hipStreamSynchronize(h->stream)))
+        return NASCH_EDEVICE;
+    return NASCH_OK;
+}
+
+int nasch_snapshot_range(nasch_sim* h, uint64_t start, uint64_t len, uint8_t* out) {
+    if (!h || (len && !out)) return NASCH_EINVAL;
+    if (len == 0) return NASCH_OK;
+    const uint8_t* g = h->current_grid_device();
+    if (!g) return NASCH_EDEVICE;
+    uint64_t done = 0;
+    uint64_t pos = start % h->L;
+    while (done < len) {
+        const uint64_t n = std::min(len - done, h->L - pos);
+        if (!h->ok(hipMemcpyAsync(out + done, g + pos, n, hipMemcpyDeviceToHost, h->stream)))
+            return NASCH_EDEVICE;
+        done += n;
+        pos = 0;
+    }
+    if (!h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
+    return NASCH_OK;
+}
+
+int nasch_snapshot(nasch_sim* h, uint8_t* out, uint64_t* t_out) {
+    if (!h) return NASCH_EINVAL;
+    if (out) {
+        int rc = nasch_snapshot_range(h, 0, h->L, out);
+        if (rc) return rc;
+    }
+    if (t_out) *t_out = h->t;
+    return NASCH_OK;
+}
+
+int nasch_agent_state(nasch_sim* h, int32_t* x, uint8_t* v) {
+    if (!h) return NASCH_EINVAL;
+    if (h->rep != NASCH_REP_AGENT) return NASCH_ESTATE;
+    if (x && h->N &&
+        !h->ok(hipMemcpyAsync(x, h->ax[h->parity], h->N * sizeof(int32_t), hipMemcpyDeviceToHost,
+                              h->stream)))
+        return NASCH_EDEVICE;
+    if (v && h->N &&
+        !h->ok(hipMemcpyAsync(v, h->av[h->parity], h->N, hipMemcpyDeviceToHost, h->stream)))
+        return NASCH_EDEVICE;
+    if (!h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
+    return NASCH_OK;
+}
+
+int nasch_restore(nasch_sim* h, const uint8_t* grid, uint64_t t) {
+    if (!h || !grid) return NASCH_EINVAL;
+    if (t > 0xFFFFFFFFull) return NASCH_ERANGE;
+    uint64_t cars = 0;
+    for (uint64_t i = 0; i < h->L; ++i) {
+        if (grid[i] == 0xFF) continue;
+        if (grid[i] > h->vmax) return NASCH_EINVAL;
+        ++cars;
+    }
+    if (cars != h->N) return NASCH_EINVAL;
+    if (!h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
+    h->parity = 0;
+    h->t = t;
+    const Clock c{(uint32_t)t, 0u};
+    if (!h->ok(hipMemcpyAsync(h->d_clk, &c, sizeof(Clock), hipMemcpyHostToDevice, h->stream)))
+        return NASCH_EDEVICE;
+    uint8_t* g = h->rep == NASCH_REP_GRID ? h->grid[0] : h->agent_grid;
+    if (!h->ok(hipMemcpyAsync(g, grid, h->L, hipMemcpyHostToDevice, h->stream)) ||
+        !h->ok(hipStreamSynchronize(h->stream)))
+        return NASCH_EDEVICE;
+    if (h->rep == NASCH_REP_AGENT) {
+        int rc = agent_from_grid(h, g);
+        if (rc) return rc;
+    }
+    // forget the old flux log
+    h->log_t0 = t;
+    if (h->flux && !h->ok(launch_fill_u64(h->flux, h->flux_cap, h->stream))) return NASCH_EDEVICE;
+    int rc = h->refresh_descs();
+    if (rc) return rc;
+    return NASCH_OK;
+}
+
+int nasch_set_tuning(nasch_sim* h, uint32_t kernel, uint32_t k, uint32_t q) {
+    if (!h) return NASCH_EINVAL;
+    return h->set_tuning(kernel, k, q);
+}
+
+int nasch_get_info(const nasch_sim* h, nasch_info* info) {
+    if (!h || !info) return NASCH_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->L = h->L; info->N = h->N; info->t = h->t;
+    info->vmax = h->vmax; info->thr = h->thr; info->replica = h->replica; info->rep = h->rep;
+    info->init_v = h->init_v; info->kernel = h->kernel; info->k = h->k; info->q = h->q;
+    info->seed = h->seed;
+    info->device_bytes = h->dev_bytes;
+    return NASCH_OK;
+}
+
+int nasch_last_device_error(const nasch_sim* h) { return h ? h->st.err : 0; }
+
+int nasch_thread_last_device_error(void) { return thread_last_hip_error(); }
+
+void nasch_free(nasch_sim* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+}  // extern "C"
+
+extern "C" int nasch_autotune(nasch_sim* h) {
+    if (!h) return NASCH_EINVAL;
+    if (h->rep == NASCH_REP_GRID) {
+        uint32_t bk = 0, bq = 0;
+        double cups = 0;
+        RingDesc cur = h->eng.rings[0];
+        std::vector<RingDesc> rs{cur};
+        if (!h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
+        if (!h->ok(autotune_grid(rs, (uint32_t)h->t, h->parity, 256, h->stream, &bk, &bq, &cups)))
+            return NASCH_EDEVICE;
+        if (!bk) return NASCH_EINVAL;
+        return h->set_tuning(NASCH_KERNEL_KSTEP, bk, bq);
+    }
+    // agent representation: time k on the real state, then put it back
+    if (!h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
+    std::vector<uint8_t> snap(h->L);
+    const uint64_t t0 = h->t;
+    int rc = nasch_snapshot(h, snap.data(), nullptr);
+    if (rc) return rc;
+    const uint32_t ks[] = {8, 16, 32, 64, 128};
+    uint32_t best_k = h->k;
+    double best = 0;
+    for (uint32_t kk : ks) {
+        if (h->set_tuning(NASCH_KERNEL_KSTEP, kk, 0) != NASCH_OK) continue;
+        const uint64_t T = std::max<uint64_t>(256, kk) / kk * kk;
+        if (t0 + 2 * T > 0xFFFFFFFFull) break;
+        double ms = 0;
+        rc = nasch_step_n(h, kk);
+        if (!rc) rc = nasch_timed_step_n(h, T, &ms);
+        if (rc) return rc;
+        if (ms > 0 && (double)T / ms > best) {
+            best = (double)T / ms;
+            best_k = kk;
+        }
+        rc = nasch_restore(h, snap.data(), t0);
+        if (rc) return rc;
+    }
+    return h->set_tuning(NASCH_KERNEL_KSTEP, best_k, 0);
+}

@@ -1,0 +1,197 @@
+"""GPU parity of single simulations against the CPU oracle, element by element:
+initial state, every kernel (byte-wise one-step, bit-sliced k-step for every
+(k, q), agent one-step and k-step), flux logs and snapshots, tiny and ragged
+rings, every vmax, the degenerate p and densities, checkpoint/restore and
+launch-sequence replay.  Integer work: the bar is bit-exact equality."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_14311_amd import NaschError, Sim
+
+pytestmark = pytest.mark.gpu
+EMPTY = 0xFF
+
+
+def _run_and_compare(L, N, vmax, p, seed, T, *, rep="grid", kernel="kstep", k=0, q=0,
+                     init_v=0, replica=0, use_graph=False):
+    g0 = oracle.init_grid(L, N, vmax, seed, replica=replica, init_v=init_v)
+    want, want_flux = oracle.run_grid(g0, vmax, p, seed, T, replica=replica)
+    s = Sim(L, N, vmax, p, seed, rep=rep, kernel=kernel, k=k, q=q, init_v=init_v,
+            replica=replica, use_graph=use_graph)
+    try:
+        g, t = s.snapshot()
+        assert t == 0
+        np.testing.assert_array_equal(g, g0)
+        s.step(T)
+        g, t = s.snapshot()
+        assert t == T
+        np.testing.assert_array_equal(g, want)
+        np.testing.assert_array_equal(s.flux(0, T), want_flux)
+    finally:
+        s.close()
+
+
+# ---------------------------------------------------------------- reference case
+def test_reference_case_every_step_onestep_and_kstep():
+    """The paper's test case (200 cars, L = 1000, p = 0.13, vmax = 5), 2000
+    steps: every snapshot and every F(t) equal the oracle's."""
+    L, N, vmax, p, seed, T = 1000, 200, 5, 0.13, 1, 2000
+    g = oracle.init_grid(L, N, vmax, seed)
+    sims = [Sim(L, N, vmax, p, seed, kernel="onestep"), Sim(L, N, vmax, p, seed, kernel="kstep"),
+            Sim(L, N, vmax, p, seed, rep="agent", kernel="onestep")]
+    try:
+        for t in range(T):
+            g, f = oracle.step_grid(g, vmax, p, seed, t)
+            for s in sims:
+                s.step(1)
+                got, tt = s.snapshot()
+                assert tt == t + 1
+                if not np.array_equal(got, g):
+                    raise AssertionError(f"step {t}: snapshot differs ({s.info()['kernel']})")
+        for s in sims:
+            _, want_flux = oracle.run_grid(oracle.init_grid(L, N, vmax, seed), vmax, p, seed, T)
+            np.testing.assert_array_equal(s.flux(0, T), want_flux)
+    finally:
+        for s in sims:
+            s.close()
+
+
+# ---------------------------------------------------------------- initial state
+@pytest.mark.parametrize("L,N,vmax,init_v,replica,seed", [
+    (1, 0, 3, 0, 0, 1), (1, 1, 3, 1, 0, 1), (2, 1, 1, 1, 0, 2), (37, 11, 8, 1, 5, 3),
+    (1000, 200, 5, 0, 0, 1), (65537, 13000, 5, 1, 9, 2**40 + 7), (4096, 4096, 2, 1, 0, 4),
+    (300000, 60000, 8, 1, 3, 11)])
+def test_initial_grid(L, N, vmax, init_v, replica, seed):
+    s = Sim(L, N, vmax, 0.1, seed, init_v=init_v, replica=replica)
+    g, _ = s.snapshot()
+    s.close()
+    np.testing.assert_array_equal(g, oracle.init_grid(L, N, vmax, seed, replica=replica,
+                                                      init_v=init_v))
+
+
+# ---------------------------------------------------------------- kernels
+@pytest.mark.parametrize("vmax", range(0, 9))
+@pytest.mark.parametrize("kernel", ["onestep", "kstep"])
+def test_every_vmax(vmax, kernel):
+    _run_and_compare(20011, 5000, vmax, 0.13, 7, 70, kernel=kernel, init_v=1)
+
+
+@pytest.mark.parametrize("p", [0.0, 1e-9, 0.0625, 0.13, 0.25, 0.5, 0.999])
+def test_probabilities(p):
+    _run_and_compare(9001, 3000, 5, p, 3, 50, init_v=1)
+    _run_and_compare(9001, 3000, 5, p, 3, 20, kernel="onestep", init_v=1)
+
+
+@pytest.mark.parametrize("q", [1, 2, 4])
+@pytest.mark.parametrize("k", [1, 2, 3, 7, 16, 32, 50])
+def test_kstep_tilings(k, q):
+    """Results do not depend on the temporal block depth or the segment size;
+    L spans several tiles with a ragged last one."""
+    from paper_2309_14311_amd.native import NaschError as E
+    try:
+        _run_and_compare(3 * 8192 * q + 333, 7000 * q, 6, 0.13, 5, 101, k=k, q=q, init_v=1)
+    except E as e:
+        assert k * 6 > (2048 * q - 32) // 2, e   # only geometries that cannot fit may fail
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 5, 8, 31, 32, 33, 63, 64, 100, 1023, 2047, 2048, 2049])
+def test_tiny_and_ragged_rings(L):
+    for N in sorted({0, 1, L // 3, L - 1, L}):
+        if N < 0 or N > L:
+            continue
+        for kernel in ("kstep", "onestep"):
+            _run_and_compare(L, N, 5, 0.3, L + 17, 40, kernel=kernel, init_v=1)
+        if N > 0:
+            _run_and_compare(L, N, 5, 0.3, L + 17, 40, rep="agent", init_v=1)
+
+
+@pytest.mark.parametrize("rho", [0.02, 0.2, 0.5, 0.9, 1.0])
+def test_densities_grid_and_agent(rho):
+    L = 50000
+    N = int(rho * L)
+    for rep, kernel in (("grid", "kstep"), ("grid", "onestep"), ("agent", "kstep"),
+                        ("agent", "onestep")):
+        _run_and_compare(L, N, 5, 0.13, 9, 60, rep=rep, kernel=kernel, init_v=1, replica=2)
+
+
+@pytest.mark.parametrize("k", [1, 5, 8, 31, 64, 100])
+def test_agent_kstep_depths(k):
+    _run_and_compare(100003, 25000, 5, 0.25, 1, 203, rep="agent", kernel="kstep", k=k, init_v=1)
+
+
+# ---------------------------------------------------------------- invariances
+def test_split_steps_equal_one_call_and_graph_replay():
+    L, N, vmax, p, seed = 70000, 14000, 5, 0.13, 21
+    ref = Sim(L, N, vmax, p, seed, init_v=1)
+    ref.step(300)
+    want, _ = ref.snapshot()
+    want_flux = ref.flux(0, 300)
+    ref.close()
+    for use_graph in (False, True):
+        for chunks in ([1, 2, 3, 294], [100, 100, 100], [37] * 8 + [4]):
+            s = Sim(L, N, vmax, p, seed, init_v=1, use_graph=use_graph, k=16)
+            for c in chunks:
+                s.step(c)
+            g, t = s.snapshot()
+            assert t == 300
+            np.testing.assert_array_equal(g, want)
+            np.testing.assert_array_equal(s.flux(0, 300), want_flux)
+            s.close()
+
+
+def test_checkpoint_restore_resumes_exactly():
+    L, N, vmax, p, seed = 40000, 9000, 5, 0.13, 4
+    for rep in ("grid", "agent"):
+        a = Sim(L, N, vmax, p, seed, rep=rep, init_v=1)
+        a.step(150)
+        mid, t1 = a.snapshot()
+        a.step(100)
+        end, t2 = a.snapshot()
+        tail = a.flux(150, 100)
+        b = Sim(L, N, vmax, p, seed, rep=rep)   # a fresh handle with a different start
+        b.restore(mid, t1)
+        b.step(100)
+        g, t = b.snapshot()
+        assert t == t2 == 250
+        np.testing.assert_array_equal(g, end)
+        np.testing.assert_array_equal(b.flux(150, 100), tail)
+        a.close()
+        b.close()
+
+
+def test_agent_state_is_cyclically_sorted():
+    s = Sim(30000, 7000, 5, 0.13, 2, rep="agent", init_v=1)
+    s.step(500)
+    x, v = s.agent_state()
+    g, _ = s.snapshot()
+    s.close()
+    assert int((np.diff(x) < 0).sum()) <= 1
+    ox, ov = oracle.grid_to_agent(g)
+    assert np.array_equal(np.sort(x), ox)
+    np.testing.assert_array_equal(oracle.agent_to_grid(30000, x, v), g)
+
+
+# ---------------------------------------------------------------- errors
+def test_invalid_arguments_are_rejected():
+    for args in [(0, 0, 5, 0.1), (10, 11, 5, 0.1), (10, 5, 9, 0.1), (10, 5, 5, 1.0),
+                 (10, 5, 5, -0.1), (10, 5, 5, float("nan")), (2**31, 5, 5, 0.1)]:
+        with pytest.raises(NaschError) as e:
+            Sim(*args, 1)
+        assert e.value.code == -1
+    s = Sim(1000, 100, 5, 0.1, 1)
+    with pytest.raises(NaschError) as e:
+        s.flux(0, 1)               # nothing run yet
+    assert e.value.code == -1
+    with pytest.raises(NaschError) as e:
+        s.step(2**32)
+    assert e.value.code == -4
+    bad = np.full(1000, EMPTY, np.uint8)
+    with pytest.raises(NaschError):
+        s.restore(bad, 0)          # wrong car count
+    bad[:100] = 9
+    with pytest.raises(NaschError):
+        s.restore(bad, 0)          # velocity above vmax
+    with pytest.raises(NaschError):
+        s.set_tuning("kstep", k=10000, q=1)
+    s.close()
