@@ -1,0 +1,238 @@
+#!/usr/bin/env python
+"""Benchmark of the NaSch hot path on one MI355X.
+
+Default workload (the metric's): the fundamental-diagram ensemble, 4096 rings
+with L log-uniform in [1e3, 1e6], density in [0.05, 0.6], p in {0, .13, .25, .5},
+vmax in 1..8, T = 5000 steps (1000 warm-up), all advanced together by the
+batched temporal-blocked grid kernel.  One benchmark step = one pass of the
+whole hot path over that batch: initial placement, T time steps of every
+replica, and the per-replica flux sums copied to the host.  Inputs are
+resident in HBM when the timed region starts.
+
+Besides the JSON line's `value` (batched cell-updates/s) it reports the same
+work run as the plain one-replica-per-launch loop, the roofline of the
+dominant kernel, and the CPU oracle timed on the host (`cpu_baseline`).
+
+Other workloads (`--workload large_ring|agent|reference`) measure the single
+large ring (k-step vs one-step), the agent form and the paper's reference case.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
+BYTES_PER_CELL_UPDATE = 2.0  # read 1 B + write 1 B of uint8 state per cell per step
+KSTEP_SRC = os.path.join(ROOT, "paper_2309_14311_amd", "csrc", "grid_kstep.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grid_kstep_ensemble.json")
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _src_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(launch_cells_steps):
+    """Counter-measured HBM bytes per launch of the k-step kernel, if the
+    committed counter summary was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_src_sha256_16") != _src_hash(KSTEP_SRC):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline_ensemble(reps, budget_s=15.0, steps=100):
+    """The oracle (all-core OpenMP twin) on a bounded sample of the ensemble:
+    replicas taken in order, each run `steps` steps from its initial state,
+    until `budget_s` seconds of CPU work have been spent."""
+    import oracle
+    nthreads = min(16, os.cpu_count() or 1)
+    done_cells, spent, n = 0, 0.0, 0
+    for r in reps:
+        g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
+                              init_v=r["init_v"])
+        t0 = time.perf_counter()
+        oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], steps, replica=r["replica"],
+                        nthreads=nthreads)
+        spent += time.perf_counter() - t0
+        done_cells += r["L"] * steps
+        n += 1
+        if spent >= budget_s:
+            break
+    return {"value": done_cells / spent, "unit": "cell-updates/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"first {n} of {len(reps)} replicas, {steps} steps each from t=0, "
+                      f"{done_cells:.3g} cell-updates in {spent:.1f} s"}
+
+
+def bench_ensemble(args):
+    import torch
+    from paper_2309_14311_amd import Batch, Sim, workloads
+
+    reps = workloads.ensemble(args.replicas, seed=1, T=args.T, warmup=args.warmup_steps)
+    cells = sum(r["L"] for r in reps)
+    _log(f"ensemble: {len(reps)} replicas, sum L = {cells:.4g}, T = {args.T}")
+    b = Batch(reps, use_graph=True)
+    k, q = b.autotune()
+    _log(f"autotuned k={k} q={q}")
+    launches = (args.T + k - 1) // k
+
+    def one_pass():
+        b.reset()
+        ms = b.timed_step(args.T)
+        sums = b.flux_sums()
+        return ms, sums
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_ms = []
+    for _ in range(args.steps):
+        ms, sums = one_pass()
+        step_ms.append(ms)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    cell_updates = cells * args.T
+    value = cell_updates / (ms_per_step * 1e-3)
+    kernel_ms = float(np.mean(step_ms)) / launches      # average k-step launch
+    achieved = BYTES_PER_CELL_UPDATE * cell_updates / launches / (kernel_ms * 1e-3)
+    traffic = _traffic(cells * k)
+
+    extra = {"batched_kernel_cups": cell_updates / (np.mean(step_ms) * 1e-3),
+             "k": k, "q": q, "launches_per_pass": launches,
+             "mean_flux_per_cell": float(np.sum(sums)) / max(1, sum(
+                 r["L"] * (args.T - r["warmup"]) for r in reps))}
+
+    # the plain loop: one replica per launch sequence, the same kernel, one stream
+    if not args.no_plain:
+        sample = reps[::args.plain_stride]
+        stream = torch.cuda.Stream()
+        sims = [Sim(r["L"], r["N"], r["vmax"], r["p"], r["seed"], replica=r["replica"],
+                    init_v=r["init_v"], stream=stream, use_graph=True) for r in sample]
+        for s in sims:
+            s.reserve_log(2 * args.plain_T)
+            s.step(args.plain_T)          # warm-up: captures each sim's launch graph
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for s in sims:
+            s.step(args.plain_T)
+        e1.record(stream)
+        e1.synchronize()
+        plain_ms = e0.elapsed_time(e1)
+        plain_cells = sum(r["L"] for r in sample) * args.plain_T
+        extra["plain_cups"] = plain_cells / (plain_ms * 1e-3)
+        extra["plain_sample"] = f"every {args.plain_stride}th replica ({len(sample)}), " \
+                                f"{args.plain_T} steps each"
+        extra["batched_over_plain"] = extra["batched_kernel_cups"] / extra["plain_cups"]
+        for s in sims:
+            s.close()
+    b.close()
+    line = {
+        "metric": "cell-updates/s and % HBM roofline, batched vs plain on 1 GPU, bit-exact",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"batched ensemble: {len(reps)} rings, L log-uniform "
+                               f"[1e3,1e6], rho U[0.05,0.6], p in {{0,.13,.25,.5}}, vmax U{{1..8}}, "
+                               f"T={args.T} ({args.warmup_steps} warm-up)",
+                   "cells": cells, "T": args.T},
+        "hbm_roofline_frac": value * BYTES_PER_CELL_UPDATE / HBM_PEAK,
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
+                     "kernel": f"grid_kstep_mixed_kernel<{q}>", "kernel_ms": kernel_ms},
+        "extra": extra,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_ensemble(reps, budget_s=args.cpu_budget)
+    return line
+
+
+def bench_single(args, cfg, rep, kernels):
+    """One ring: value = k-step (autotuned) CUPS; the one-step kernel beside it."""
+    import torch
+    from paper_2309_14311_amd import Sim
+    s = Sim(cfg["L"], cfg["N"], cfg["vmax"], cfg["p"], cfg["seed"], rep=rep,
+            init_v=cfg["init_v"], use_graph=True)
+    s.autotune()
+    info = s.info()
+    T = cfg["T"] if args.T_single is None else args.T_single
+    res = {}
+    for kern in kernels:
+        s.set_tuning(kern, info["k"], info["q"])
+        for _ in range(args.warmup):
+            s.timed_step(T)
+        ms = [s.timed_step(T) for _ in range(args.steps)]
+        res[kern] = cfg["L"] * T / (np.mean(ms) * 1e-3)
+    torch.cuda.synchronize()
+    s.close()
+    value = res["kstep"]
+    return {
+        "metric": "cell-updates/s and % HBM roofline, batched vs plain on 1 GPU, bit-exact",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": cfg["L"] * T / value * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"{rep} ring L={cfg['L']} N={cfg['N']} vmax={cfg['vmax']} "
+                               f"p={cfg['p']} T={T}", "k": info["k"], "q": info["q"]},
+        "hbm_roofline_frac": value * BYTES_PER_CELL_UPDATE / HBM_PEAK,
+        "extra": {f"{k}_cups": v for k, v in res.items()},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ensemble",
+                    choices=["ensemble", "large_ring", "agent", "reference"])
+    ap.add_argument("--replicas", type=int, default=4096)
+    ap.add_argument("--T", type=int, default=5000)
+    ap.add_argument("--warmup-steps", type=int, default=1000)
+    ap.add_argument("--T-single", type=int, default=None)
+    ap.add_argument("--plain-stride", type=int, default=8)
+    ap.add_argument("--plain-T", type=int, default=1000)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the NaSch hot path here is measured per GPU "
+              "(--gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    from paper_2309_14311_amd import workloads
+    if args.workload == "ensemble":
+        line = bench_ensemble(args)
+    elif args.workload == "large_ring":
+        line = bench_single(args, workloads.LARGE_RING, "grid", ["kstep", "onestep"])
+    elif args.workload == "agent":
+        line = bench_single(args, workloads.AGENT_RING, "agent", ["kstep", "onestep"])
+    else:
+        line = bench_single(args, workloads.REFERENCE, "grid", ["kstep", "onestep"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -120,6 +120,10 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
  * t + T would exceed 2^32 - 1 (nothing is enqueued then). */
 int nasch_step_n(nasch_sim* h, uint64_t T);
 
+/* Make room in the device flux log for `steps` more steps, so that the next
+ * nasch_step_n calls covering them allocate nothing and do not synchronise. */
+int nasch_reserve_log(nasch_sim* h, uint64_t steps);
+
 /* As nasch_step_n, then waits; *ms receives the device time between two HIP
  * events recorded on the handle's stream around the enqueued launches. */
 int nasch_timed_step_n(nasch_sim* h, uint64_t T, double* ms);
@@ -205,6 +209,10 @@ void nasch_batch_default_opts(nasch_batch_opts* opts);
  * arena, all at t = 0. */
 int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
                      const nasch_batch_opts* opts);
+
+/* Put every replica back to its initial state at t = 0 (init kernels again)
+ * and zero the flux sums and logs.  Synchronises. */
+int nasch_batch_reset(nasch_batch* b);
 
 /* Advance every replica by T steps.  Each launch runs k steps of every tile of
  * every replica; the launches are the same kernels a single simulation uses. */

@@ -17,11 +17,6 @@
 namespace nasch {
 
 namespace {
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
 __device__ __forceinline__ uint32_t hi_nibble(const Word4& w, uint32_t x) {
     const uint32_t s = x & 31u;
     return (((w.w0 >> s) & 1u) << 3) | (((w.w1 >> s) & 1u) << 2) | (((w.w2 >> s) & 1u) << 1) |
@@ -36,7 +31,9 @@ __device__ __forceinline__ uint32_t accel_brake(uint32_t v, uint32_t d, uint32_t
 }
 }  // namespace
 
+// F(t) of each wave goes to partials[wave] (summed by the fold kernel).
 __global__ __launch_bounds__(256) void agent_onestep_kernel(const AgentDesc* __restrict__ A,
+                                                            uint32_t* __restrict__ partials,
                                                             const Clock* __restrict__ clk,
                                                             uint32_t s_off, uint32_t launch_idx) {
     const uint32_t N = A->N, L = A->L, vmax = A->vmax;
@@ -64,25 +61,29 @@ __global__ __launch_bounds__(256) void agent_onestep_kernel(const AgentDesc* __r
         xo[i] = (int32_t)xn;
         vo[i] = (uint8_t)nv;
     }
-    const uint32_t total = wave_sum(nv);
-    if ((threadIdx.x & 63u) == 0 && total) {
-        if (A->flux_log) atomicAdd(&A->flux_log[(uint64_t)t - A->log_t0], (unsigned long long)total);
-        if (A->flux_acc && (uint64_t)t >= A->warmup) atomicAdd(A->flux_acc, (unsigned long long)total);
+    const uint32_t total = wave_total(nv);
+    if ((threadIdx.x & 63u) == 0) {
+        if (A->flux_log) partials[i >> 6] = total;
+        if (A->flux_acc && (uint64_t)t >= A->warmup && total)
+            atomicAdd(A->flux_acc, (unsigned long long)total);
     }
 }
 
-hipError_t launch_agent_onestep(const AgentDesc* a, uint32_t N, const Clock* clk, uint32_t s_off,
-                                uint32_t launch_idx, hipStream_t s) {
+hipError_t launch_agent_onestep(const AgentDesc* a, uint32_t N, uint32_t* partials,
+                                const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                                hipStream_t s) {
     if (N == 0) return hipSuccess;
-    NASCH_LAUNCH(agent_onestep_kernel, dim3((N + 255) / 256), dim3(256), 0, s, a, clk, s_off,
-                       launch_idx);
+    NASCH_LAUNCH(agent_onestep_kernel, dim3((N + 255) / 256), dim3(256), 0, s, a, partials, clk,
+                 s_off, launch_idx);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------
 constexpr uint32_t CPL = kAgentCarsPerLane;
 
+// F(t) of each wave and step goes to partials[s * ntiles + wave].
 __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __restrict__ A,
+                                                          uint32_t* __restrict__ partials,
                                                           uint32_t k,
                                                           const Clock* __restrict__ clk,
                                                           uint32_t s_off, uint32_t launch_idx) {
@@ -123,10 +124,12 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
         }
     }
 
-    unsigned long long acc = 0ull;
+    uint32_t acc = 0u;
+    const bool log = A->flux_log != nullptr;
+    const uint32_t ntiles = A->ntiles;
     for (uint32_t s = 0; s < k; ++s) {
         const uint32_t t = t0 + s;
-        const uint32_t x_next_lane = __shfl_down(x[0], 1);
+        const uint32_t x_next_lane = from_next_lane(x[0]);
         uint32_t nv[CPL];
 #pragma unroll
         for (int q = 0; q < (int)CPL; ++q) {
@@ -167,13 +170,16 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
             x[q] = xn;
             v[q] = nv[q];
         }
-        const uint32_t total = wave_sum(fl);
-        if (lane == 0u) {
-            if (A->flux_log) atomicAdd(&A->flux_log[(uint64_t)t - A->log_t0], (unsigned long long)total);
-            if ((uint64_t)t >= A->warmup) acc += total;
+        if (log) {
+            const uint32_t total = wave_total(fl);
+            if (lane == 0u) partials[(size_t)s * ntiles + wave] = total;
         }
+        if ((uint64_t)t >= A->warmup) acc += fl;
     }
-    if (lane == 0u && A->flux_acc && acc) atomicAdd(A->flux_acc, acc);
+    if (A->flux_acc) {
+        const uint32_t total = wave_total(acc);
+        if (lane == 0u && total) atomicAdd(A->flux_acc, (unsigned long long)total);
+    }
 
     // write back the owned cars
     if (lane * CPL + CPL <= own_len) {
@@ -198,11 +204,12 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
     }
 }
 
-hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t ntiles, uint32_t k, const Clock* clk,
-                              uint32_t s_off, uint32_t launch_idx, hipStream_t s) {
+hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t ntiles, uint32_t* partials, uint32_t k,
+                              const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                              hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
-    NASCH_LAUNCH(agent_kstep_kernel, dim3((ntiles + 3) / 4), dim3(256), 0, s, a, k, clk,
-                       s_off, launch_idx);
+    NASCH_LAUNCH(agent_kstep_kernel, dim3((ntiles + 3) / 4), dim3(256), 0, s, a, partials, k, clk,
+                 s_off, launch_idx);
     return hipGetLastError();
 }
 

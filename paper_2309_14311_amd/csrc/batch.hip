@@ -29,12 +29,20 @@ struct nasch_batch {
     uint32_t use_graph = 0;
     GridEngine eng;
     GraphCache graphs;
+    InitRing* d_init_rings = nullptr;     // placement of every replica, one launch
+    InitChunk* d_init_chunks = nullptr;
+    uint32_t n_init_chunks = 0;
 
     bool ok(hipError_t e) { return st.ok(e); }
+    // Every replica at t = 0: the whole arena EMPTY, then all cars scattered.
+    bool init_state() {
+        return ok(launch_fill_u8(arena, arena_bytes, 0xFFu, stream)) &&
+               ok(launch_init_scatter(d_init_rings, d_init_chunks, n_init_chunks, stream));
+    }
     ~nasch_batch() {
         graphs.clear();
         eng.release();
-        void* ps[] = {arena, d_acc, d_log, d_clk};
+        void* ps[] = {arena, d_acc, d_log, d_clk, d_init_rings, d_init_chunks};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -111,6 +119,8 @@ int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
     if (!b->ok(hipMemcpyAsync(b->d_clk, &c0, sizeof(Clock), hipMemcpyHostToDevice, b->stream)))
         return NASCH_EDEVICE;
     uint32_t vmax_all = 0;
+    std::vector<InitRing> init_rings;
+    std::vector<InitChunk> init_chunks;
     for (uint32_t r = 0; r < R; ++r) {
         const nasch_replica& p = reps[r];
         const uint64_t sz = (p.L + 255) / 256 * 256;
@@ -127,16 +137,43 @@ int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
         d.sp = slow_params(p.seed, p.replica, p.p);
         b->eng.rings.push_back(d);
         vmax_all = std::max(vmax_all, p.vmax);
-        if (!b->ok(launch_init_grid(d.buf[0], (uint32_t)p.L, (uint32_t)p.N, p.vmax, p.init_v, d.sp,
-                                    b->stream)))
-            return NASCH_EDEVICE;
+        init_rings.push_back(InitRing{d.buf[0], (uint32_t)p.L, (uint32_t)p.N, p.vmax, p.init_v,
+                                      feistel_bits(p.L), 0u, d.sp});
+        for (uint64_t c = 0; c < p.N; c += kInitChunk) init_chunks.push_back(InitChunk{r, (uint32_t)c});
     }
+    b->n_init_chunks = (uint32_t)init_chunks.size();
+    if (!b->ok(dev_alloc(&b->d_init_rings, R)) ||
+        !b->ok(dev_alloc(&b->d_init_chunks, init_chunks.size())))
+        return NASCH_ENOMEM;
+    if (!b->ok(hipMemcpy(b->d_init_rings, init_rings.data(), R * sizeof(InitRing),
+                         hipMemcpyHostToDevice)) ||
+        (!init_chunks.empty() &&
+         !b->ok(hipMemcpy(b->d_init_chunks, init_chunks.data(),
+                          init_chunks.size() * sizeof(InitChunk), hipMemcpyHostToDevice))))
+        return NASCH_EDEVICE;
+    if (!b->init_state()) return NASCH_EDEVICE;
     uint32_t q = o.q ? o.q : 4u;
     uint32_t k = o.k ? o.k : std::min(32u, std::max(1u, kstep_max_k(vmax_all, q)));
     if (!b->eng.geometry_ok(k, q)) return NASCH_EINVAL;
     if (!b->ok(b->eng.set_geometry(k, q, b->stream))) return NASCH_EDEVICE;
     if (!b->ok(hipStreamSynchronize(b->stream))) return NASCH_EDEVICE;
     *out = b.release();
+    return NASCH_OK;
+}
+
+int nasch_batch_reset(nasch_batch* b) {
+    if (!b) return NASCH_EINVAL;
+    const uint32_t R = (uint32_t)b->reps.size();
+    if (!b->init_state()) return NASCH_EDEVICE;
+    if (!b->ok(launch_fill_u64(b->d_acc, R, b->stream))) return NASCH_EDEVICE;
+    if (b->d_log && !b->ok(launch_fill_u64(b->d_log, (uint64_t)R * b->log_steps, b->stream)))
+        return NASCH_EDEVICE;
+    const Clock c0{0u, 0u};
+    if (!b->ok(hipMemcpyAsync(b->d_clk, &c0, sizeof(Clock), hipMemcpyHostToDevice, b->stream)) ||
+        !b->ok(hipStreamSynchronize(b->stream)))
+        return NASCH_EDEVICE;
+    b->t = 0;
+    b->parity = 0;
     return NASCH_OK;
 }
 

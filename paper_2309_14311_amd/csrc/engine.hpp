@@ -111,14 +111,24 @@ struct GridEngine {
     uint32_t k = 0, q = 0;
     uint32_t launch_vmax = kMixedVmax;  // single specialisation when all rings agree
     uint32_t version = 0;               // bumped whenever d_items / geometry change
+    // per-launch F(t) partials of every item and step, and the rings that keep a log
+    uint32_t* d_partials = nullptr;
+    size_t partials_cap = 0;
+    uint32_t* d_log_rings = nullptr;
+    size_t log_rings_cap = 0;
+    uint32_t n_log_rings = 0;
 
     ~GridEngine() { release(); }
     void release() {
-        if (d_rings) (void)hipFree(d_rings);
-        if (d_items) (void)hipFree(d_items);
+        void* ps[] = {d_rings, d_items, d_partials, d_log_rings};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
         d_rings = nullptr;
         d_items = nullptr;
-        d_rings_cap = d_items_cap = 0;
+        d_partials = nullptr;
+        d_log_rings = nullptr;
+        d_rings_cap = d_items_cap = partials_cap = log_rings_cap = 0;
+        n_log_rings = 0;
     }
 
     bool geometry_ok(uint32_t kk, uint32_t qq) const {
@@ -143,14 +153,25 @@ struct GridEngine {
             vmin = std::min(vmin, r.vmax);
             vmaxx = std::max(vmaxx, r.vmax);
         }
-        for (uint32_t ri : order)
+        for (uint32_t ri : order) {
+            rings[ri].first_item = (uint32_t)items.size();
             for (uint32_t t = 0; t < rings[ri].ntiles; ++t) items.push_back(TileItem{ri, t});
+        }
         launch_vmax = (vmin == vmaxx) ? vmin : kMixedVmax;
         k = kk;
         q = qq;
         ++version;
         hipError_t e = upload_rings(s);
         if (e != hipSuccess) return e;
+        const size_t np = items.size() * (size_t)kk;
+        if (np > partials_cap) {
+            if (d_partials) (void)hipFree(d_partials);
+            d_partials = nullptr;
+            partials_cap = 0;
+            e = dev_alloc(&d_partials, np);
+            if (e != hipSuccess) return e;
+            partials_cap = np;
+        }
         if (items.size() > d_items_cap) {
             if (d_items) (void)hipFree(d_items);
             d_items = nullptr;
@@ -168,6 +189,23 @@ struct GridEngine {
     }
 
     hipError_t upload_rings(hipStream_t s) {
+        std::vector<uint32_t> logs;
+        for (uint32_t i = 0; i < rings.size(); ++i)
+            if (rings[i].flux_log) logs.push_back(i);
+        n_log_rings = (uint32_t)logs.size();
+        if (logs.size() > log_rings_cap) {
+            if (d_log_rings) (void)hipFree(d_log_rings);
+            d_log_rings = nullptr;
+            log_rings_cap = 0;
+            hipError_t e = dev_alloc(&d_log_rings, logs.size());
+            if (e != hipSuccess) return e;
+            log_rings_cap = logs.size();
+        }
+        if (!logs.empty()) {
+            hipError_t e = hipMemcpyAsync(d_log_rings, logs.data(), logs.size() * sizeof(uint32_t),
+                                          hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return e;
+        }
         if (rings.size() > d_rings_cap) {
             if (d_rings) (void)hipFree(d_rings);
             d_rings = nullptr;
@@ -191,7 +229,11 @@ struct GridEngine {
         for (uint32_t i = 0; i < n; ++i) {
             const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
             hipError_t e = launch_grid_kstep(launch_vmax, q, d_rings, d_items,
-                                             (uint32_t)items.size(), ki, d_clk, i * k, i, s);
+                                             (uint32_t)items.size(), d_partials, ki, d_clk, i * k,
+                                             i, s);
+            if (e == hipSuccess && n_log_rings)
+                e = launch_fold_ring_flux(d_rings, d_log_rings, n_log_rings, d_partials,
+                                          (uint32_t)items.size(), ki, d_clk, i * k, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;

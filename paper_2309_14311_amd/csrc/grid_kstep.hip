@@ -49,7 +49,7 @@ __device__ __forceinline__ uint32_t bit_range(uint32_t a, uint32_t b) {
 
 // Top-nibble planes of R for the 32 consecutive ring cells x0, x0+1, ... (mod L)
 // when they are not one aligned block: assembled from the blocks they touch.
-__device__ __noinline__ Word4 planes_unaligned(uint32_t x0, uint32_t t, uint32_t L,
+__device__ __forceinline__ Word4 planes_unaligned(uint32_t x0, uint32_t t, uint32_t L,
                                               const SlowParams& sp) {
     Word4 r{0, 0, 0, 0};
     uint32_t pos = x0, i = 0;
@@ -127,18 +127,17 @@ struct Thermo<VMAX, VMAX + 1> {
                                                 uint32_t) {}
 };
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
 }  // namespace
 
-// One wave advances one tile item by up to k steps.
+// One wave advances one tile item by up to k steps.  F(t) of a ring with a
+// flux log goes to partials[s * n_items + item] (summed per ring and step by
+// the fold kernel); flux_acc gets one atomic per wave.
 template <int VMAX, int Q>
-__device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it, uint32_t lane,
-                                           uint32_t k, const Clock* __restrict__ clk,
-                                           uint32_t s_off, uint32_t launch_idx) {
+__device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it, uint32_t item,
+                                           uint32_t n_items, uint32_t* __restrict__ partials,
+                                           uint32_t lane, uint32_t k,
+                                           const Clock* __restrict__ clk, uint32_t s_off,
+                                           uint32_t launch_idx) {
     const uint32_t L = R.L;
     const SlowParams sp = R.sp;
     const uint32_t t0 = clk->t + R.t + s_off;
@@ -208,13 +207,13 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     }
 
     // ---- k steps
-    unsigned long long acc = 0ull;
+    uint32_t acc = 0u;
+    const bool log = R.flux_log != nullptr;
     for (uint32_t s = 0; s < nsteps; ++s) {
         const uint32_t t = t0 + s;
         uint32_t fl = 0;
         if constexpr (VMAX > 0) {
-            uint32_t occ_next = __shfl_down(T[0][0], 1);
-            if (lane == 63u) occ_next = 0u;
+            const uint32_t occ_next = from_next_lane(T[0][0]);
             uint32_t Eq[Q][VMAX + 1];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
@@ -248,10 +247,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
             // rule 4: cars with v3 == j move j cells right
             uint32_t prevEq[VMAX + 1];
 #pragma unroll
-            for (int j = 1; j <= VMAX; ++j) {
-                const uint32_t v = __shfl_up(Eq[Q - 1][j], 1);
-                prevEq[j] = lane == 0u ? 0u : v;
-            }
+            for (int j = 1; j <= VMAX; ++j) prevEq[j] = from_prev_lane(Eq[Q - 1][j]);
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 uint32_t accm = 0u;
@@ -264,13 +260,16 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                 T[q][0] = accm | Eq[q][0];
             }
         }
-        const uint32_t total = wave_sum(fl);
-        if (lane == 0u) {
-            if (R.flux_log) atomicAdd(&R.flux_log[(uint64_t)t - R.log_t0], (unsigned long long)total);
-            if ((uint64_t)t >= R.warmup) acc += total;
+        if (log) {
+            const uint32_t total = wave_total(fl);
+            if (lane == 0u) partials[(size_t)s * n_items + item] = total;
         }
+        if ((uint64_t)t >= R.warmup) acc += fl;
     }
-    if (lane == 0u && R.flux_acc && acc) atomicAdd(R.flux_acc, acc);
+    if (R.flux_acc) {
+        const uint32_t total = wave_total(acc);
+        if (lane == 0u && total) atomicAdd(R.flux_acc, (unsigned long long)total);
+    }
 
     // ---- store the owned cells: bit planes -> bytes
 #pragma unroll
@@ -313,13 +312,14 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
 template <int VMAX, int Q>
 __global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restrict__ rings,
                                                          const TileItem* __restrict__ items,
-                                                         uint32_t n_items, uint32_t k,
-                                                         const Clock* __restrict__ clk,
+                                                         uint32_t n_items, uint32_t* partials,
+                                                         uint32_t k, const Clock* __restrict__ clk,
                                                          uint32_t s_off, uint32_t launch_idx) {
     const uint32_t wave = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= n_items) return;
     const TileItem it = items[wave];
-    kstep_tile<VMAX, Q>(rings[it.ring], it, threadIdx.x & 63u, k, clk, s_off, launch_idx);
+    kstep_tile<VMAX, Q>(rings[it.ring], it, wave, n_items, partials, threadIdx.x & 63u, k, clk,
+                        s_off, launch_idx);
 }
 
 // Items of different vmax in one launch: the branch on the ring's vmax is
@@ -327,7 +327,8 @@ __global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restr
 template <int Q>
 __global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* __restrict__ rings,
                                                                const TileItem* __restrict__ items,
-                                                               uint32_t n_items, uint32_t k,
+                                                               uint32_t n_items, uint32_t* partials,
+                                                               uint32_t k,
                                                                const Clock* __restrict__ clk,
                                                                uint32_t s_off,
                                                                uint32_t launch_idx) {
@@ -337,15 +338,15 @@ __global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* _
     const RingDesc& R = rings[it.ring];
     const uint32_t lane = threadIdx.x & 63u;
     switch (R.vmax) {
-        case 0: kstep_tile<0, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
-        case 1: kstep_tile<1, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
-        case 2: kstep_tile<2, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
-        case 3: kstep_tile<3, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
-        case 4: kstep_tile<4, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
-        case 5: kstep_tile<5, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
-        case 6: kstep_tile<6, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
-        case 7: kstep_tile<7, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
-        case 8: kstep_tile<8, Q>(R, it, lane, k, clk, s_off, launch_idx); break;
+        case 0: kstep_tile<0, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
+        case 1: kstep_tile<1, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
+        case 2: kstep_tile<2, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
+        case 3: kstep_tile<3, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
+        case 4: kstep_tile<4, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
+        case 5: kstep_tile<5, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
+        case 6: kstep_tile<6, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
+        case 7: kstep_tile<7, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
+        case 8: kstep_tile<8, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
         default: break;
     }
 }
@@ -353,12 +354,12 @@ __global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* _
 namespace {
 template <int Q>
 hipError_t launch_q(uint32_t vmax, dim3 grid, hipStream_t s, const RingDesc* rings,
-                    const TileItem* items, uint32_t n_items, uint32_t k, const Clock* clk,
-                    uint32_t s_off, uint32_t launch_idx) {
+                    const TileItem* items, uint32_t n_items, uint32_t* partials, uint32_t k,
+                    const Clock* clk, uint32_t s_off, uint32_t launch_idx) {
 #define NASCH_KSTEP_CASE(V)                                                                      \
     case V:                                                                                      \
         NASCH_LAUNCH((grid_kstep_kernel<V, Q>), grid, dim3(256), 0, s, rings, items,      \
-                           n_items, k, clk, s_off, launch_idx);                                  \
+                           n_items, partials, k, clk, s_off, launch_idx);                        \
         break;
     switch (vmax) {
         NASCH_KSTEP_CASE(0)
@@ -372,7 +373,7 @@ hipError_t launch_q(uint32_t vmax, dim3 grid, hipStream_t s, const RingDesc* rin
         NASCH_KSTEP_CASE(8)
         case kMixedVmax:
             NASCH_LAUNCH((grid_kstep_mixed_kernel<Q>), grid, dim3(256), 0, s, rings, items,
-                               n_items, k, clk, s_off, launch_idx);
+                               n_items, partials, k, clk, s_off, launch_idx);
             break;
         default:
             return hipErrorInvalidValue;
@@ -383,15 +384,15 @@ hipError_t launch_q(uint32_t vmax, dim3 grid, hipStream_t s, const RingDesc* rin
 }  // namespace
 
 hipError_t launch_grid_kstep(uint32_t vmax, uint32_t q, const RingDesc* rings,
-                             const TileItem* items, uint32_t n_items, uint32_t k,
-                             const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                             const TileItem* items, uint32_t n_items, uint32_t* partials,
+                             uint32_t k, const Clock* clk, uint32_t s_off, uint32_t launch_idx,
                              hipStream_t s) {
     if (n_items == 0) return hipSuccess;
     const dim3 grid((n_items + 3u) / 4u);
     switch (q) {
-        case 1: return launch_q<1>(vmax, grid, s, rings, items, n_items, k, clk, s_off, launch_idx);
-        case 2: return launch_q<2>(vmax, grid, s, rings, items, n_items, k, clk, s_off, launch_idx);
-        case 4: return launch_q<4>(vmax, grid, s, rings, items, n_items, k, clk, s_off, launch_idx);
+        case 1: return launch_q<1>(vmax, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
+        case 2: return launch_q<2>(vmax, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
+        case 4: return launch_q<4>(vmax, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         default: return hipErrorInvalidValue;
     }
 }

@@ -17,11 +17,6 @@ constexpr uint32_t kHalo = 16;  // >= vmax
 constexpr uint32_t kTile = kOneStepTile;
 static_assert(kTile == kThreads * 32, "one 32-cell block per thread");
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
 // New velocity of the car at tile-local cell c (rules 1-3); `in` is the LDS
 // copy indexed by tile-local cell + kHalo.
 __device__ __forceinline__ uint32_t car_velocity(const uint8_t* in, int c, uint32_t vmax,
@@ -42,7 +37,9 @@ __device__ __forceinline__ uint32_t car_velocity(const uint8_t* in, int c, uint3
 }
 }  // namespace
 
+// F(t) of the tile goes to partials[blockIdx.x] (summed by the fold kernel).
 __global__ __launch_bounds__(kThreads) void grid_onestep_kernel(const RingDesc* __restrict__ ring,
+                                                                uint32_t* __restrict__ partials,
                                                                 const Clock* __restrict__ clk,
                                                                 uint32_t s_off,
                                                                 uint32_t launch_idx) {
@@ -118,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void grid_onestep_kernel(const RingDesc* 
             if (dstc >= 0 && (uint32_t)dstc < len) s_out[dstc] = (uint8_t)v;
         }
     }
-    const uint32_t wsum = wave_sum(flux);
+    const uint32_t wsum = wave_total(flux);
     if ((tid & 63u) == 0) s_flux[tid >> 6] = wsum;
     __syncthreads();
 
@@ -133,16 +130,18 @@ __global__ __launch_bounds__(kThreads) void grid_onestep_kernel(const RingDesc* 
     if (tid == 0) {
         uint32_t total = 0;
         for (uint32_t w = 0; w < kThreads / 64; ++w) total += s_flux[w];
-        if (R.flux_log) atomicAdd(&R.flux_log[(uint64_t)t - R.log_t0], (unsigned long long)total);
-        if (R.flux_acc && (uint64_t)t >= R.warmup) atomicAdd(R.flux_acc, (unsigned long long)total);
+        if (R.flux_log) partials[blockIdx.x] = total;
+        if (R.flux_acc && (uint64_t)t >= R.warmup && total)
+            atomicAdd(R.flux_acc, (unsigned long long)total);
     }
 }
 
-hipError_t launch_grid_onestep(const RingDesc* ring, uint32_t L, const Clock* clk, uint32_t s_off,
-                               uint32_t launch_idx, hipStream_t s) {
-    const uint32_t blocks = (uint32_t)(((uint64_t)L + kTile - 1) / kTile);
-    NASCH_LAUNCH(grid_onestep_kernel, dim3(blocks), dim3(kThreads), 0, s, ring, clk, s_off,
-                       launch_idx);
+hipError_t launch_grid_onestep(const RingDesc* ring, uint32_t L, uint32_t* partials,
+                               const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                               hipStream_t s) {
+    const uint32_t blocks = onestep_blocks(L);
+    NASCH_LAUNCH(grid_onestep_kernel, dim3(blocks), dim3(kThreads), 0, s, ring, partials, clk,
+                 s_off, launch_idx);
     return hipGetLastError();
 }
 

@@ -3,36 +3,35 @@
 
 namespace nasch {
 
-// One thread per 4 cells; a cell holds a car iff the cycle-walked inverse
-// Feistel permutation maps it below N.
-__global__ __launch_bounds__(256) void init_grid_kernel(uint8_t* __restrict__ g, uint32_t L,
-                                                        uint32_t N, uint32_t vmax,
-                                                        uint32_t init_v, SlowParams sp,
-                                                        uint32_t b) {
-    const uint64_t base = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4u;
-    if (base >= L) return;
-    uint32_t word = 0;
-    const uint32_t n = (uint32_t)min((uint64_t)4, (uint64_t)L - base);
-    for (uint32_t i = 0; i < n; ++i) {
-        const uint32_t y = (uint32_t)base + i;
-        uint32_t cell = kEmpty;
-        if (N > 0 && placement_preimage(y, L, b, sp) < N)
-            cell = init_v ? initial_velocity(y, vmax, sp) : 0u;
-        word |= cell << (8 * i);
+// Initial grid of one ring: EMPTY everywhere, then car i < N at its placement.
+// Scatter form: one Feistel evaluation (with cycle-walking) per car.
+__global__ __launch_bounds__(256) void init_scatter_kernel(const InitRing* __restrict__ rings,
+                                                           const InitChunk* __restrict__ chunks,
+                                                           InitRing single) {
+    const InitChunk c = chunks ? chunks[blockIdx.x] : InitChunk{0u, blockIdx.x * kInitChunk};
+    const InitRing R = chunks ? rings[c.ring] : single;
+    for (uint32_t j = threadIdx.x; j < kInitChunk; j += blockDim.x) {
+        const uint32_t i = c.first + j;
+        if (i >= R.N) break;
+        const uint32_t x = placement(i, R.L, R.b, R.sp);
+        R.g[x] = (uint8_t)(R.init_v ? initial_velocity(x, R.vmax, R.sp) : 0u);
     }
-    if (n == 4) {
-        *reinterpret_cast<uint32_t*>(g + base) = word;
-    } else {
-        for (uint32_t i = 0; i < n; ++i) g[base + i] = (uint8_t)(word >> (8 * i));
-    }
+}
+
+hipError_t launch_init_scatter(const InitRing* rings, const InitChunk* chunks, uint32_t n_chunks,
+                               hipStream_t s) {
+    if (n_chunks == 0) return hipSuccess;
+    NASCH_LAUNCH(init_scatter_kernel, dim3(n_chunks), dim3(256), 0, s, rings, chunks, InitRing{});
+    return hipGetLastError();
 }
 
 hipError_t launch_init_grid(uint8_t* g, uint32_t L, uint32_t N, uint32_t vmax, uint32_t init_v,
                             SlowParams sp, hipStream_t s) {
-    const uint64_t threads = ((uint64_t)L + 3) / 4;
-    const uint32_t blocks = (uint32_t)((threads + 255) / 256);
-    NASCH_LAUNCH(init_grid_kernel, dim3(blocks), dim3(256), 0, s, g, L, N, vmax, init_v,
-                       sp, feistel_bits(L));
+    hipError_t e = launch_fill_u8(g, L, (uint8_t)kEmpty, s);
+    if (e != hipSuccess || N == 0) return e;
+    InitRing r{g, L, N, vmax, init_v, feistel_bits(L), 0u, sp};
+    const uint32_t chunks = (N + kInitChunk - 1) / kInitChunk;
+    NASCH_LAUNCH(init_scatter_kernel, dim3(chunks), dim3(256), 0, s, nullptr, nullptr, r);
     return hipGetLastError();
 }
 
@@ -157,6 +156,68 @@ hipError_t launch_agent_to_grid(const int32_t* x, const uint8_t* v, uint32_t N, 
     if (e != hipSuccess || N == 0) return e;
     NASCH_LAUNCH(scatter_agents_kernel, dim3((N + 255) / 256), dim3(256), 0, s, x, v, N, g,
                        L);
+    return hipGetLastError();
+}
+
+// ---- flux folding -------------------------------------------------------------
+// Block (r, s): F(t0 + s) of ring log_rings[r] = sum of its items' partials of step s.
+__device__ __forceinline__ unsigned long long block_sum(const uint32_t* p, uint32_t n) {
+    __shared__ unsigned long long part[4];
+    unsigned long long v = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+    // 64-bit sum of the wave: two 32-bit wave totals (partials fit 32 bits each,
+    // a wave's sum of up to n/64 of them may not)
+    const uint32_t lo = wave_total((uint32_t)(v & 0xFFFFFFFFull));
+    const uint32_t hi = wave_total((uint32_t)(v >> 32));
+    const unsigned long long w = ((unsigned long long)hi << 32) + lo;
+    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = w;
+    __syncthreads();
+    unsigned long long total = 0;
+    if (threadIdx.x == 0)
+        for (uint32_t i = 0; i < blockDim.x / 64; ++i) total += part[i];
+    return total;
+}
+
+__global__ __launch_bounds__(256) void fold_ring_flux_kernel(const RingDesc* __restrict__ rings,
+                                                             const uint32_t* __restrict__ log_rings,
+                                                             const uint32_t* __restrict__ partials,
+                                                             uint32_t n_items, uint32_t k,
+                                                             const Clock* __restrict__ clk,
+                                                             uint32_t s_off) {
+    const RingDesc& R = rings[log_rings[blockIdx.x]];
+    const uint32_t s = blockIdx.y;
+    const uint32_t t = clk->t + R.t + s_off + s;
+    if (s >= k || (R.t_end != 0xFFFFFFFFu && t >= R.t_end)) return;
+    const unsigned long long total =
+        block_sum(partials + (size_t)s * n_items + R.first_item, R.ntiles);
+    if (threadIdx.x == 0) R.flux_log[(uint64_t)t - R.log_t0] = total;
+}
+
+hipError_t launch_fold_ring_flux(const RingDesc* rings, const uint32_t* log_rings, uint32_t n_log,
+                                 const uint32_t* partials, uint32_t n_items, uint32_t k,
+                                 const Clock* clk, uint32_t s_off, hipStream_t s) {
+    if (n_log == 0 || k == 0) return hipSuccess;
+    NASCH_LAUNCH(fold_ring_flux_kernel, dim3(n_log, k), dim3(256), 0, s, rings, log_rings, partials,
+                 n_items, k, clk, s_off);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fold_agent_flux_kernel(const AgentDesc* __restrict__ A,
+                                                              const uint32_t* __restrict__ partials,
+                                                              uint32_t n_items, uint32_t k,
+                                                              const Clock* __restrict__ clk,
+                                                              uint32_t s_off) {
+    const uint32_t s = blockIdx.x;
+    const uint32_t t = clk->t + A->t + s_off + s;
+    const unsigned long long total = block_sum(partials + (size_t)s * n_items, n_items);
+    if (threadIdx.x == 0 && A->flux_log) A->flux_log[(uint64_t)t - A->log_t0] = total;
+}
+
+hipError_t launch_fold_agent_flux(const AgentDesc* a, const uint32_t* partials, uint32_t n_items,
+                                  uint32_t k, const Clock* clk, uint32_t s_off, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    NASCH_LAUNCH(fold_agent_flux_kernel, dim3(k), dim3(256), 0, s, a, partials, n_items, k, clk,
+                 s_off);
     return hipGetLastError();
 }
 

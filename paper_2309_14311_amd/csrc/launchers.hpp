@@ -21,6 +21,10 @@ namespace nasch {
 // placement puts a car.
 hipError_t launch_init_grid(uint8_t* g, uint32_t L, uint32_t N, uint32_t vmax, uint32_t init_v,
                             SlowParams sp, hipStream_t s);
+// Scatter the cars of many rings (grids must already be EMPTY): one thread per
+// car, chunk c places cars [chunks[c].first, +kInitChunk) of ring chunks[c].ring.
+hipError_t launch_init_scatter(const InitRing* rings, const InitChunk* chunks, uint32_t n_chunks,
+                               hipStream_t s);
 // Occupied-cell count of each chunk of kCompactChunk cells.
 constexpr uint32_t kCompactChunk = 65536;
 hipError_t launch_count_chunks(const uint8_t* g, uint32_t L, uint32_t* counts, hipStream_t s);
@@ -34,11 +38,24 @@ hipError_t launch_agent_to_grid(const int32_t* x, const uint8_t* v, uint32_t N, 
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t value, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, hipStream_t s);
 hipError_t launch_clock_advance(Clock* clk, uint32_t T, uint32_t nlaunch, hipStream_t s);
+// F(t) of each step of a launch from the per-item partials it wrote:
+// partials[s * n_items + item], items of a ring contiguous from ring.first_item.
+hipError_t launch_fold_ring_flux(const RingDesc* rings, const uint32_t* log_rings, uint32_t n_log,
+                                 const uint32_t* partials, uint32_t n_items, uint32_t k,
+                                 const Clock* clk, uint32_t s_off, hipStream_t s);
+hipError_t launch_fold_agent_flux(const AgentDesc* a, const uint32_t* partials, uint32_t n_items,
+                                  uint32_t k, const Clock* clk, uint32_t s_off, hipStream_t s);
 
 // ---- grid, byte-wise one step per launch (grid_onestep.hip) --------------------
 constexpr uint32_t kOneStepTile = 8192;
-hipError_t launch_grid_onestep(const RingDesc* ring, uint32_t L, const Clock* clk, uint32_t s_off,
-                               uint32_t launch_idx, hipStream_t s);
+constexpr uint32_t onestep_blocks(uint32_t L) {
+    return (uint32_t)(((uint64_t)L + kOneStepTile - 1) / kOneStepTile);
+}
+// F(t) of block b goes to partials[b]; the ring desc for the fold has
+// first_item 0 and ntiles = onestep_blocks(L).
+hipError_t launch_grid_onestep(const RingDesc* ring, uint32_t L, uint32_t* partials,
+                               const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                               hipStream_t s);
 
 // ---- grid, bit-sliced, k steps per launch (grid_kstep.hip) --------------------
 // Cells per wave segment for q words of 32 cells per lane.
@@ -47,16 +64,20 @@ constexpr uint32_t kstep_segment(uint32_t q) { return 64u * 32u * q; }
 // otherwise every item's ring must have this vmax.
 constexpr uint32_t kMixedVmax = 0xFFu;
 hipError_t launch_grid_kstep(uint32_t vmax, uint32_t q, const RingDesc* rings,
-                             const TileItem* items, uint32_t n_items, uint32_t k,
-                             const Clock* clk, uint32_t s_off, uint32_t launch_idx, hipStream_t s);
+                             const TileItem* items, uint32_t n_items, uint32_t* partials,
+                             uint32_t k, const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                             hipStream_t s);
 
 // ---- agent (agent.hip) --------------------------------------------------------
-hipError_t launch_agent_onestep(const AgentDesc* a, uint32_t N, const Clock* clk, uint32_t s_off,
-                                uint32_t launch_idx, hipStream_t s);
+// F(t) of wave w goes to partials[w], w < ceil(N / 64).
+hipError_t launch_agent_onestep(const AgentDesc* a, uint32_t N, uint32_t* partials,
+                                const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                                hipStream_t s);
 // k steps per launch: each wave holds 64 * kAgentCarsPerLane consecutive cars and
 // writes back all but the last k of them.
 constexpr uint32_t kAgentCarsPerLane = 8;
-hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t ntiles, uint32_t k, const Clock* clk,
-                              uint32_t s_off, uint32_t launch_idx, hipStream_t s);
+hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t ntiles, uint32_t* partials, uint32_t k,
+                              const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                              hipStream_t s);
 
 }  // namespace nasch

@@ -18,6 +18,11 @@ struct Word4 {
     uint32_t w0, w1, w2, w3;
 };
 
+// a ^ b ^ c in one gfx950 three-input bitwise instruction (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two 32x32->64
 // multiplies by the Philox constants, key bumped by the Weyl constants between
 // rounds.  With a wave-uniform key and counter words 1-3 uniform, the compiler
@@ -28,8 +33,8 @@ __device__ __forceinline__ Word4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     for (int r = 0; r < 10; ++r) {
         const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(m1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(m0 >> 32), c3, k1);
         c1 = (uint32_t)m1;
         c3 = (uint32_t)m0;
         c0 = n0;
@@ -101,6 +106,31 @@ __device__ __forceinline__ uint32_t feistel_inv(uint32_t y, uint32_t half, uint3
     return (l << half) | r;
 }
 
+// Forward 4-round Feistel permutation on b bits: round j maps (l, r) to
+// (r, l ^ F_j(r)).
+__device__ __forceinline__ uint32_t feistel_fwd(uint32_t i, uint32_t half, uint32_t mask,
+                                                const SlowParams& sp) {
+    uint32_t l = (i >> half) & mask, r = i & mask;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t f = philox(r, (uint32_t)j, sp.replica, kTagPlace, sp.k0, sp.k1).w0 & mask;
+        const uint32_t nl = r;
+        r = l ^ f;
+        l = nl;
+    }
+    return (l << half) | r;
+}
+
+// Cell of car i: the Feistel permutation cycle-walked until it lands in [0, L).
+__device__ __forceinline__ uint32_t placement(uint32_t i, uint32_t L, uint32_t b,
+                                              const SlowParams& sp) {
+    const uint32_t half = b >> 1;
+    const uint32_t mask = (half >= 32) ? 0xFFFFFFFFu : ((1u << half) - 1u);
+    uint32_t y = feistel_fwd(i, half, mask, sp);
+    while (y >= L) y = feistel_fwd(y, half, mask, sp);
+    return y;
+}
+
 // Index of the car that starts in cell y (cycle-walking the inverse until it
 // lands in [0, L)); the cell is occupied iff the index is below N.
 __device__ __forceinline__ uint32_t placement_preimage(uint32_t y, uint32_t L, uint32_t b,
@@ -133,8 +163,25 @@ struct RingDesc {
     uint32_t own, halo;      // geometry for the current (k, q)
     uint32_t ntiles;
     uint32_t t_end;          // no step t >= t_end is run (serving); 0xFFFFFFFF = none
+    uint32_t first_item;     // index of the ring's first item in the launch
+    uint32_t pad;
     SlowParams sp;
 };
+
+// Initial placement of one ring: cars [0, N) scattered into g (already EMPTY).
+struct InitRing {
+    uint8_t* g;
+    uint32_t L, N, vmax, init_v;
+    uint32_t b;              // Feistel width
+    uint32_t pad;
+    SlowParams sp;
+};
+// kInitChunk consecutive cars of one ring.
+struct InitChunk {
+    uint32_t ring;
+    uint32_t first;
+};
+constexpr uint32_t kInitChunk = 4096;
 
 struct TileItem {
     uint32_t ring;   // index into the RingDesc table
@@ -166,5 +213,27 @@ struct AgentDesc {
     uint32_t pad;
     SlowParams sp;
 };
+
+// ---- cross-lane helpers (gfx9 DPP) ----------------------------------------------
+// Lane i receives lane i+1's value; lane 63 receives 0.
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+}
+// Lane i receives lane i-1's value; lane 0 receives 0.
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+// Sum over the 64 lanes of a wave (all lanes active), returned to every lane:
+// an inclusive DPP scan (row shifts 1, 2, 4, 8, then the row broadcasts of
+// lanes 15 and 31) leaves the total in lane 63.
+__device__ __forceinline__ uint32_t wave_total(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111 /* row_shr:1 */, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112 /* row_shr:2 */, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114 /* row_shr:4 */, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118 /* row_shr:8 */, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142 /* row_bcast:15 */, 0xa, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143 /* row_bcast:31 */, 0xc, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
 
 }  // namespace nasch

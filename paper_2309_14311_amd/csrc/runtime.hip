@@ -46,6 +46,9 @@ struct nasch_sim {
     uint8_t* grid[2] = {nullptr, nullptr};
     GridEngine eng;           // one ring, its tiles
     RingDesc* d_onestep = nullptr;  // the same ring for the one-step kernel
+    uint32_t* os_partials = nullptr;   // one-step / agent F(t) partials
+    size_t os_partials_cap = 0;
+    uint32_t* d_zero = nullptr;        // device index list {0}
     // agent representation
     int32_t* ax[2] = {nullptr, nullptr};
     uint8_t* av[2] = {nullptr, nullptr};
@@ -66,13 +69,28 @@ struct nasch_sim {
     int enqueue_steps(uint64_t T);
     int set_tuning(uint32_t kern, uint32_t kk, uint32_t qq);
     const uint8_t* current_grid_device();
+    // Captured graphs bake the partials pointer in: a new buffer drops them.
+    int ensure_os_partials(size_t n) {
+        if (n <= os_partials_cap) return NASCH_OK;
+        graphs.clear();
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (os_partials) (void)hipFree(os_partials);
+        os_partials = nullptr;
+        os_partials_cap = 0;
+        if (!ok(dev_alloc(&os_partials, n))) return NASCH_ENOMEM;
+        os_partials_cap = n;
+        return NASCH_OK;
+    }
+    // agent one-step waves = all waves of its grid
+    uint32_t agent_onestep_waves() const { return 4u * (uint32_t)((N + 255) / 256); }
 };
 
 nasch_sim::~nasch_sim() {
     graphs.clear();
     eng.release();
     // agent_grid aliases grid[0]
-    void* ps[] = {d_clk, grid[0], grid[1], d_onestep, ax[0], ax[1], av[0], av[1], d_agent, flux};
+    void* ps[] = {d_clk, grid[0], grid[1], d_onestep, ax[0], ax[1], av[0], av[1], d_agent, flux,
+                  os_partials, d_zero};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -109,7 +127,10 @@ int nasch_sim::refresh_descs() {
         r.flux_log = flux;
         r.log_t0 = log_t0;
         if (!ok(eng.upload_rings(stream))) return fail();
-        if (!ok(hipMemcpyAsync(d_onestep, &r, sizeof(RingDesc), hipMemcpyHostToDevice, stream)))
+        RingDesc os = r;
+        os.first_item = 0;
+        os.ntiles = onestep_blocks((uint32_t)L);
+        if (!ok(hipMemcpyAsync(d_onestep, &os, sizeof(RingDesc), hipMemcpyHostToDevice, stream)))
             return fail();
     } else {
         h_agent.flux_log = flux;
@@ -140,6 +161,8 @@ int nasch_sim::set_tuning(uint32_t kern, uint32_t kk, uint32_t qq) {
         if (kern == NASCH_KERNEL_KSTEP) {
             uint32_t own, ntiles;
             if (!agent_geometry((uint32_t)N, kk, &own, &ntiles)) return NASCH_EINVAL;
+            int rc = ensure_os_partials((size_t)ntiles * kk);
+            if (rc) return rc;
             if (h_agent.own != own || h_agent.ntiles != ntiles) {
                 h_agent.own = own;
                 h_agent.ntiles = ntiles;
@@ -163,9 +186,13 @@ int nasch_sim::enqueue_steps(uint64_t T) {
         uint32_t nl = 0;
         if (rep == NASCH_REP_GRID) {
             if (kernel == NASCH_KERNEL_ONESTEP) {
+                const uint32_t nb = onestep_blocks((uint32_t)L);
                 for (uint64_t i = 0; i < T; ++i) {
-                    hipError_t e = launch_grid_onestep(d_onestep, (uint32_t)L, d_clk, (uint32_t)i,
-                                                       (uint32_t)i, stream);
+                    hipError_t e = launch_grid_onestep(d_onestep, (uint32_t)L, os_partials, d_clk,
+                                                       (uint32_t)i, (uint32_t)i, stream);
+                    if (e == hipSuccess)
+                        e = launch_fold_ring_flux(d_onestep, d_zero, 1, os_partials, nb, 1, d_clk,
+                                                  (uint32_t)i, stream);
                     if (e != hipSuccess) return e;
                 }
                 nl = (uint32_t)T;
@@ -176,9 +203,13 @@ int nasch_sim::enqueue_steps(uint64_t T) {
             }
         } else {
             if (kernel == NASCH_KERNEL_ONESTEP) {
+                const uint32_t nw = agent_onestep_waves();
                 for (uint64_t i = 0; i < T; ++i) {
-                    hipError_t e = launch_agent_onestep(d_agent, (uint32_t)N, d_clk, (uint32_t)i,
-                                                        (uint32_t)i, stream);
+                    hipError_t e = launch_agent_onestep(d_agent, (uint32_t)N, os_partials, d_clk,
+                                                        (uint32_t)i, (uint32_t)i, stream);
+                    if (e == hipSuccess)
+                        e = launch_fold_agent_flux(d_agent, os_partials, nw, 1, d_clk, (uint32_t)i,
+                                                   stream);
                     if (e != hipSuccess) return e;
                 }
                 nl = (uint32_t)T;
@@ -186,8 +217,11 @@ int nasch_sim::enqueue_steps(uint64_t T) {
                 nl = (uint32_t)((T + k - 1) / k);
                 for (uint32_t i = 0; i < nl; ++i) {
                     const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
-                    hipError_t e = launch_agent_kstep(d_agent, h_agent.ntiles, ki, d_clk, i * k, i,
-                                                      stream);
+                    hipError_t e = launch_agent_kstep(d_agent, h_agent.ntiles, os_partials, ki,
+                                                      d_clk, i * k, i, stream);
+                    if (e == hipSuccess)
+                        e = launch_fold_agent_flux(d_agent, os_partials, h_agent.ntiles, ki, d_clk,
+                                                   i * k, stream);
                     if (e != hipSuccess) return e;
                 }
             }
@@ -298,7 +332,8 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
         h->own_stream = true;
     }
     const SlowParams sp = slow_params(seed, o.replica, p);
-    if (!h->ok(dev_alloc(&h->d_clk, 1))) return NASCH_ENOMEM;
+    if (!h->ok(dev_alloc(&h->d_clk, 1)) || !h->ok(dev_alloc(&h->d_zero, 1))) return NASCH_ENOMEM;
+    if (!h->ok(hipMemsetAsync(h->d_zero, 0, sizeof(uint32_t), h->stream))) return NASCH_EDEVICE;
     const Clock c0{0u, 0u};
     if (!h->ok(hipMemcpyAsync(h->d_clk, &c0, sizeof(Clock), hipMemcpyHostToDevice, h->stream)))
         return NASCH_EDEVICE;
@@ -324,6 +359,8 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
         r.warmup = ~0ull;
         h->eng.rings.push_back(r);
         if (!h->ok(dev_alloc(&h->d_onestep, 1))) return NASCH_ENOMEM;
+        rc = h->ensure_os_partials(onestep_blocks((uint32_t)L));
+        if (rc) return rc;
         uint32_t kk = o.k, qq = o.q;
         uint32_t dk, dq;
         default_tuning((uint32_t)L, vmax, &dk, &dq);
@@ -351,6 +388,8 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
         a.warmup = ~0ull;
         uint32_t kk = o.k ? o.k : kDefaultAgentK;
         if (!agent_geometry((uint32_t)N, kk, &a.own, &a.ntiles)) return NASCH_EINVAL;
+        rc = h->ensure_os_partials(std::max<size_t>((size_t)a.ntiles * kk, h->agent_onestep_waves()));
+        if (rc) return rc;
         h->k = kk;
         h->q = o.q ? o.q : 1;
         h->kernel = o.kernel == NASCH_KERNEL_AUTO ? NASCH_KERNEL_KSTEP : o.kernel;
@@ -373,6 +412,12 @@ int nasch_step_n(nasch_sim* h, uint64_t T) {
     int rc = h->ensure_log(T);
     if (rc) return rc;
     return h->enqueue_steps(T);
+}
+
+int nasch_reserve_log(nasch_sim* h, uint64_t steps) {
+    if (!h) return NASCH_EINVAL;
+    if (h->t + steps > 0xFFFFFFFFull) return NASCH_ERANGE;
+    return h->ensure_log(steps);
 }
 
 int nasch_timed_step_n(nasch_sim* h, uint64_t T, double* ms) {

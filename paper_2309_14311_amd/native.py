@@ -71,6 +71,7 @@ _SIGS = {
     "nasch_default_opts": (None, [ctypes.POINTER(Opts)]),
     "nasch_init": (I32, [vpp, U64, U64, U32, DBL, U64, ctypes.POINTER(Opts)]),
     "nasch_step_n": (I32, [VP, U64]),
+    "nasch_reserve_log": (I32, [VP, U64]),
     "nasch_timed_step_n": (I32, [VP, U64, f64p]),
     "nasch_flux": (I32, [VP, U64, U64, u64p]),
     "nasch_snapshot": (I32, [VP, u8p, u64p]),
@@ -86,6 +87,7 @@ _SIGS = {
     "nasch_strerror": (ctypes.c_char_p, [I32]),
     "nasch_batch_default_opts": (None, [ctypes.POINTER(BatchOpts)]),
     "nasch_batch_init": (I32, [vpp, ctypes.POINTER(Replica), U32, ctypes.POINTER(BatchOpts)]),
+    "nasch_batch_reset": (I32, [VP]),
     "nasch_batch_step_n": (I32, [VP, U64]),
     "nasch_batch_timed_step_n": (I32, [VP, U64, f64p]),
     "nasch_batch_flux_sums": (I32, [VP, u64p]),
@@ -186,6 +188,9 @@ class Sim:
     def step(self, T: int):
         self._check(_lib.nasch_step_n(self._h, T), "nasch_step_n")
 
+    def reserve_log(self, steps: int):
+        self._check(_lib.nasch_reserve_log(self._h, steps), "nasch_reserve_log")
+
     def timed_step(self, T: int) -> float:
         ms = ctypes.c_double()
         self._check(_lib.nasch_timed_step_n(self._h, T, ctypes.byref(ms)), "nasch_timed_step_n")
@@ -278,6 +283,9 @@ class Batch:
     def _check(self, rc, where):
         if rc:
             raise NaschError(rc, where, _lib.nasch_batch_last_device_error(self._h))
+
+    def reset(self):
+        self._check(_lib.nasch_batch_reset(self._h), "nasch_batch_reset")
 
     def step(self, T):
         self._check(_lib.nasch_batch_step_n(self._h, T), "nasch_batch_step_n")

@@ -1,0 +1,92 @@
+"""GPU parity of the batched ensemble: every replica equals the oracle and equals
+itself run alone; results do not depend on (k, q), graph replay or reset."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_14311_amd import Batch, NaschError, Sim, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_ensemble(n=48, seed=3, T=300, warmup=100):
+    return workloads.ensemble(n, seed=seed, T=T, warmup=warmup, L_lo_exp=1.0, L_hi_exp=4.3)
+
+
+def _oracle_replica(r, T):
+    g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
+                          init_v=r["init_v"])
+    return oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], T, replica=r["replica"])
+
+
+def test_every_replica_matches_oracle_with_logs():
+    reps = _small_ensemble()
+    T = 300
+    b = Batch(reps, keep_log=True, log_steps=T)
+    b.step(T)
+    sums = b.flux_sums()
+    for i, r in enumerate(reps):
+        g, flux = _oracle_replica(r, T)
+        got, t = b.snapshot(i)
+        assert t == T
+        np.testing.assert_array_equal(got, g, err_msg=f"replica {i} {r}")
+        np.testing.assert_array_equal(b.flux(i, 0, T), flux)
+        assert int(sums[i]) == int(flux[r["warmup"]:].sum())
+    b.close()
+
+
+@pytest.mark.parametrize("k,q", [(1, 1), (5, 2), (16, 4), (32, 4), (64, 4), (24, 1)])
+def test_tuning_and_graph_do_not_change_results(k, q):
+    reps = _small_ensemble(32, seed=9)
+    T = 257
+    ref = Batch(reps)
+    ref.step(T)
+    want = ref.flux_sums()
+    want_g = [ref.snapshot(i)[0] for i in range(len(reps))]
+    ref.close()
+    for use_graph in (False, True):
+        b = Batch(reps, k=k, q=q, use_graph=use_graph)
+        for chunk in (100, 57, 100):
+            b.step(chunk)
+        np.testing.assert_array_equal(b.flux_sums(), want)
+        for i in range(len(reps)):
+            np.testing.assert_array_equal(b.snapshot(i)[0], want_g[i])
+        b.close()
+
+
+def test_replica_in_batch_equals_replica_alone():
+    """A replica's result does not depend on the other replicas of the launch."""
+    reps = workloads.ensemble(64, seed=5, T=400, warmup=100, L_lo_exp=3.0, L_hi_exp=5.5)
+    b = Batch(reps, use_graph=True)
+    b.step(400)
+    sums = b.flux_sums()
+    for i in range(0, 64, 7):
+        r = reps[i]
+        s = Sim(r["L"], r["N"], r["vmax"], r["p"], r["seed"], replica=r["replica"],
+                init_v=r["init_v"])
+        s.step(400)
+        g, _ = s.snapshot()
+        np.testing.assert_array_equal(b.snapshot(i)[0], g)
+        assert int(sums[i]) == int(s.flux(r["warmup"], 400 - r["warmup"]).sum())
+        s.close()
+    b.close()
+
+
+def test_reset_and_autotune_reproduce():
+    reps = _small_ensemble(24, seed=11)
+    b = Batch(reps, use_graph=True)
+    b.step(200)
+    first = b.flux_sums().copy()
+    k, q = b.autotune()
+    assert k > 0 and q in (1, 2, 4)
+    b.reset()
+    b.step(200)
+    np.testing.assert_array_equal(b.flux_sums(), first)
+    b.close()
+
+
+def test_batch_rejects_bad_replicas():
+    with pytest.raises(NaschError):
+        Batch([dict(L=10, N=11, vmax=5, p=0.1, seed=1)])
+    with pytest.raises(NaschError):
+        Batch([dict(L=10, N=5, vmax=5, p=1.5, seed=1)])

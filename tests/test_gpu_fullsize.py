@@ -1,0 +1,108 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark
+times.  The oracle cannot run these rings whole, so the checks are:
+  - sampled windows of the final road against the oracle's light-cone
+    evaluation (a cell after T steps depends only on cells within T*vmax);
+  - the temporal-blocked, one-step and agent paths agree on the whole state;
+  - properties of the flux log that hold at any size: F(T-1) is the sum of the
+    final velocities, and F(t) <= min(N vmax, L - N) (no car exceeds vmax or
+    its gap, and the gaps add up to L - N).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_14311_amd import Batch, Sim, workloads
+
+pytestmark = pytest.mark.gpu
+EMPTY = 0xFF
+
+
+def _windows(L, n, w, seed):
+    rng = np.random.default_rng(seed)
+    starts = [0, L - w // 2, L // 2] + [int(x) for x in rng.integers(0, L, size=n)]
+    return [(s % L, w) for s in starts]
+
+
+def _check_windows(sim_range, cfg, T, windows):
+    for a, w in windows:
+        want = oracle.window_from_init(cfg["L"], cfg["N"], cfg["vmax"], cfg["p"], cfg["seed"], T,
+                                       a, w, replica=cfg["replica"], init_v=cfg["init_v"])
+        got = sim_range(a, w)
+        np.testing.assert_array_equal(got, want, err_msg=f"window at {a}")
+
+
+def _flux_properties(flux, final_grid, N, vmax):
+    L = final_grid.size
+    assert int(flux.max()) <= min(N * vmax, L - N)
+    occ = final_grid != EMPTY
+    assert int(occ.sum()) == N
+    assert int(final_grid[occ].astype(np.int64).sum()) == int(flux[-1])
+
+
+def test_large_ring_kstep_onestep_and_oracle_windows():
+    cfg = workloads.LARGE_RING
+    L, N, T = cfg["L"], cfg["N"], cfg["T"]
+    a = Sim(L, N, cfg["vmax"], cfg["p"], cfg["seed"], init_v=cfg["init_v"], use_graph=True)
+    a.autotune()
+    a.step(T)
+    _check_windows(a.snapshot_range, cfg, T, _windows(L, 5, 192, 1))
+    ga, _ = a.snapshot()
+    fa = a.flux(0, T)
+    a.close()
+    _flux_properties(fa, ga, N, cfg["vmax"])
+    b = Sim(L, N, cfg["vmax"], cfg["p"], cfg["seed"], init_v=cfg["init_v"], kernel="onestep")
+    b.step(T)
+    gb, _ = b.snapshot()
+    np.testing.assert_array_equal(b.flux(0, T), fa)
+    b.close()
+    assert np.array_equal(ga, gb)
+
+
+def test_agent_ring_equals_grid_and_oracle_windows():
+    cfg = workloads.AGENT_RING
+    L, N, T = cfg["L"], cfg["N"], cfg["T"]
+    a = Sim(L, N, cfg["vmax"], cfg["p"], cfg["seed"], rep="agent", init_v=cfg["init_v"],
+            use_graph=True)
+    a.step(T)
+    _check_windows(a.snapshot_range, cfg, T, _windows(L, 4, 160, 2))
+    ga, _ = a.snapshot()
+    fa = a.flux(0, T)
+    x, v = a.agent_state()
+    a.close()
+    assert int((np.diff(x) < 0).sum()) <= 1          # order kept: one cyclic descent
+    _flux_properties(fa, ga, N, cfg["vmax"])
+    g = Sim(L, N, cfg["vmax"], cfg["p"], cfg["seed"], init_v=cfg["init_v"])
+    g.step(T)
+    gg, _ = g.snapshot()
+    np.testing.assert_array_equal(g.flux(0, T), fa)
+    g.close()
+    assert np.array_equal(ga, gg)
+
+
+def test_ensemble_in_bench_configuration():
+    """The 4096-replica ensemble as the benchmark runs it (graph replay, autotuned
+    (k, q), reset between passes): the smallest replicas against the oracle in
+    full, a sample of the rest against the same replica run alone."""
+    reps = workloads.ensemble(4096, seed=1, T=5000, warmup=1000)
+    b = Batch(reps, use_graph=True)
+    b.autotune()
+    b.reset()
+    b.step(5000)
+    sums = b.flux_sums()
+    order = np.argsort([r["L"] for r in reps])
+    for i in order[:12]:
+        r = reps[i]
+        g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
+                              init_v=r["init_v"])
+        g, flux = oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], 5000, replica=r["replica"])
+        np.testing.assert_array_equal(b.snapshot(i)[0], g)
+        assert int(sums[i]) == int(flux[1000:].sum())
+    for i in order[::400]:
+        r = reps[i]
+        s = Sim(r["L"], r["N"], r["vmax"], r["p"], r["seed"], replica=r["replica"],
+                init_v=r["init_v"])
+        s.step(5000)
+        np.testing.assert_array_equal(b.snapshot(i)[0], s.snapshot()[0])
+        assert int(sums[i]) == int(s.flux(1000, 4000).sum())
+        s.close()
+    b.close()

@@ -1,0 +1,82 @@
+"""GPU tests of the serving loop: every result equals the oracle, a request gives
+the same result alone and in the mix, requests queue when the HBM budget is
+small, cancellation and invalid requests."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_14311_amd import NaschError, Server, Sim, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(r):
+    g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
+                          init_v=r["init_v"])
+    return oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], r["T"], replica=r["replica"])
+
+
+def _drain(srv, n, timeout=120.0):
+    out = {}
+    deadline = time.time() + timeout
+    while len(out) < n and time.time() < deadline:
+        for res in srv.poll(wait_ms=50):
+            out[res["id"]] = res
+    assert len(out) == n, f"only {len(out)} of {n} results"
+    return out
+
+
+def test_results_match_oracle():
+    reqs = workloads.requests(40, seed=3, L_exp=(1.5, 4.0), T_exp=(1.0, 2.7))
+    srv = Server(k=16)
+    ids = [srv.submit(r["L"], r["N"], r["vmax"], r["p"], r["seed"], r["T"], init_v=r["init_v"],
+                      want_grid=True) for r in reqs]
+    res = _drain(srv, len(ids))
+    for rid, r in zip(ids, reqs):
+        g, flux = _oracle(r)
+        got = res[rid]
+        assert got["status"] == 0
+        np.testing.assert_array_equal(got["flux"], flux)
+        np.testing.assert_array_equal(got["grid"], g)
+        assert got["flux_sum"] == int(flux.sum())
+        assert got["t_submit"] <= got["t_admit"] <= got["t_done"]
+    srv.close()
+
+
+def test_alone_equals_in_mix_and_queueing_under_small_budget():
+    reqs = workloads.requests(60, seed=4, L_exp=(3.0, 5.0), T_exp=(1.5, 3.0))
+    # budget fits a few requests only: the rest must wait, not fail
+    budget = 6 * max(2 * ((r["L"] + 255) // 256 * 256) + 8 * r["T"] + 256 for r in reqs)
+    srv = Server(k=32, hbm_budget=budget)
+    ids = [srv.submit(r["L"], r["N"], r["vmax"], r["p"], r["seed"], r["T"], init_v=r["init_v"],
+                      want_grid=True) for r in reqs]
+    saw_pending = srv.stats()["pending"] > 0
+    res = _drain(srv, len(ids))
+    assert saw_pending
+    st = srv.stats()
+    assert st["done"] == len(reqs) and st["bytes_in_use"] == 0 and st["running"] == 0
+    srv.close()
+    for rid, r in list(zip(ids, reqs))[::6]:
+        s = Sim(r["L"], r["N"], r["vmax"], r["p"], r["seed"], init_v=r["init_v"])
+        s.step(r["T"])
+        g, _ = s.snapshot()
+        np.testing.assert_array_equal(res[rid]["grid"], g)
+        np.testing.assert_array_equal(res[rid]["flux"], s.flux(0, r["T"]))
+        s.close()
+
+
+def test_cancel_and_invalid_requests():
+    srv = Server(k=32)
+    with pytest.raises(NaschError):
+        srv.submit(100, 200, 5, 0.1, 1, 10)        # N > L
+    with pytest.raises(NaschError):
+        srv.submit(100, 20, 5, 0.1, 1, 0)          # T = 0
+    big = srv.submit(2_000_000, 400_000, 5, 0.2, 1, 20000, want_flux=True)
+    small = srv.submit(1000, 200, 5, 0.13, 1, 50)
+    srv.cancel(big)
+    res = _drain(srv, 2)
+    assert res[small]["status"] == 0
+    assert res[big]["status"] == -5
+    srv.close()
