@@ -45,9 +45,10 @@ def _src_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(launch_cells_steps):
-    """Counter-measured HBM bytes per launch of the k-step kernel, if the
-    committed counter summary was taken on the current kernel source."""
+def _traffic(k, q, launch_cell_updates):
+    """Counter-measured HBM bytes of one launch of the k-step kernel, scaled from
+    the committed counter summary (bytes per cell-update at the same (k, q)), if
+    it was taken on the current kernel source; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -55,7 +56,9 @@ def _traffic(launch_cells_steps):
         return None
     if rec.get("kernel_src_sha256_16") != _src_hash(KSTEP_SRC):
         return None
-    return rec.get("bytes_per_launch")
+    if rec.get("k") != k or rec.get("q") != q:
+        return None
+    return rec["bytes_per_cell_update"] * launch_cell_updates
 
 
 def cpu_baseline_ensemble(reps, budget_s=15.0, steps=100):
@@ -90,8 +93,13 @@ def bench_ensemble(args):
     cells = sum(r["L"] for r in reps)
     _log(f"ensemble: {len(reps)} replicas, sum L = {cells:.4g}, T = {args.T}")
     b = Batch(reps, use_graph=True)
-    k, q = b.autotune()
-    _log(f"autotuned k={k} q={q}")
+    if args.k and args.q:
+        b.set_tuning(args.k, args.q)
+        k, q = args.k, args.q
+        _log(f"fixed k={k} q={q}")
+    else:
+        k, q = b.autotune()
+        _log(f"autotuned k={k} q={q}")
     launches = (args.T + k - 1) // k
 
     def one_pass():
@@ -115,7 +123,7 @@ def bench_ensemble(args):
     value = cell_updates / (ms_per_step * 1e-3)
     kernel_ms = float(np.mean(step_ms)) / launches      # average k-step launch
     achieved = BYTES_PER_CELL_UPDATE * cell_updates / launches / (kernel_ms * 1e-3)
-    traffic = _traffic(cells * k)
+    traffic = _traffic(k, q, cells * k)
 
     extra = {"batched_kernel_cups": cell_updates / (np.mean(step_ms) * 1e-3),
              "k": k, "q": q, "launches_per_pass": launches,
@@ -210,6 +218,8 @@ def main():
     ap.add_argument("--T", type=int, default=5000)
     ap.add_argument("--warmup-steps", type=int, default=1000)
     ap.add_argument("--T-single", type=int, default=None)
+    ap.add_argument("--k", type=int, default=0, help="steps per launch (0: autotune)")
+    ap.add_argument("--q", type=int, default=0, help="words per lane (0: autotune)")
     ap.add_argument("--plain-stride", type=int, default=8)
     ap.add_argument("--plain-T", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)

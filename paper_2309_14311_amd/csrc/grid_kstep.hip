@@ -70,9 +70,12 @@ __device__ __forceinline__ Word4 planes_unaligned(uint32_t x0, uint32_t t, uint3
     return r;
 }
 
-// Rule 3 mask for the moving cars of one word (ring cells x0 .. x0+31, mod L).
-__device__ __forceinline__ uint32_t slow_mask(uint32_t moving, uint32_t x0, bool aligned,
-                                              uint32_t t, uint32_t L, const SlowParams& sp) {
+// Rule 3, first stage, for the moving cars of one word (ring cells x0 .. x0+31,
+// mod L): S = cars whose top nibble of R is below thr's (slow), U = cars whose
+// top nibble ties with thr's (decided by the low 28 bits).
+__device__ __forceinline__ void slow_hi(uint32_t moving, uint32_t x0, bool aligned, uint32_t t,
+                                        uint32_t L, const SlowParams& sp, uint32_t& S,
+                                        uint32_t& U) {
     const Word4 hp = aligned ? slow_hi_planes(x0 >> 5, t, sp) : planes_unaligned(x0, t, L, sp);
     const uint32_t th = sp.thr >> 28;
     uint32_t lt = 0u, eq = 0xFFFFFFFFu;
@@ -81,19 +84,74 @@ __device__ __forceinline__ uint32_t slow_mask(uint32_t moving, uint32_t x0, bool
     if (th & 4u) { lt |= eq & ~hp.w1; eq &= hp.w1; } else { eq &= ~hp.w1; }
     if (th & 2u) { lt |= eq & ~hp.w2; eq &= hp.w2; } else { eq &= ~hp.w2; }
     if (th & 1u) { lt |= eq & ~hp.w3; eq &= hp.w3; } else { eq &= ~hp.w3; }
-    uint32_t S = moving & lt;
+    S = moving & lt;
+    U = moving & eq;
+}
+
+// Rule 3, second stage, shared by the whole wave.  The tied cars of every lane
+// (bits of U, word by word, in order) are numbered with a wave prefix sum and
+// their ring cells queued in LDS; the wave then draws their low 28 bits 64 at
+// a time, so a lane with many tied cars does not hold the others back.  Cars
+// numbered beyond the queue's capacity are drawn by their own lane.
+constexpr uint32_t kRefineCap = 256;
+
+template <int Q>
+__device__ __forceinline__ void slow_lo_wave(uint32_t (&S)[Q], const uint32_t (&U)[Q],
+                                             const uint32_t (&xw)[Q], uint32_t L, uint32_t t,
+                                             const SlowParams& sp, uint32_t* queue,
+                                             uint8_t* res, uint32_t lane) {
     const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
-    if (lo_thr != 0u) {
-        uint32_t u = moving & eq;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) cnt += __popc(U[q]);
+    const uint32_t incl = wave_scan_incl(cnt);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    if (total == 0u) return;
+    const uint32_t nq = min(total, kRefineCap);
+    uint32_t idx = incl - cnt;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        uint32_t u = U[q];
         while (u) {
-            const uint32_t j = __builtin_ctz(u);
+            const uint32_t b = __builtin_ctz(u);
             u &= u - 1u;
-            uint32_t x = x0 + j;
-            if (x >= L) x %= L;
-            if (slow_lo28(x, t, sp) < lo_thr) S |= 1u << j;
+            if (idx < kRefineCap) {
+                uint32_t x = xw[q] + b;
+                if (x >= L) x %= L;
+                queue[idx] = x;
+            }
+            ++idx;
         }
     }
-    return S;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t p = lane; p < nq; p += 64u) res[p] = slow_lo28(queue[p], t, sp) < lo_thr ? 1 : 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    idx = incl - cnt;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        uint32_t u = U[q];
+        while (u) {
+            const uint32_t b = __builtin_ctz(u);
+            u &= u - 1u;
+            bool slow;
+            if (idx < kRefineCap) {
+                slow = res[idx] != 0;
+            } else {
+                uint32_t x = xw[q] + b;
+                if (x >= L) x %= L;
+                slow = slow_lo28(x, t, sp) < lo_thr;
+            }
+            if (slow) S[q] |= 1u << b;
+            ++idx;
+        }
+    }
+    // the queue is rewritten at the next step only after every lane has read it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
 // (P3 P2 P1 P0) >= M for a constant M, bit-sliced over 32 cells.
@@ -137,7 +195,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                                            uint32_t n_items, uint32_t* __restrict__ partials,
                                            uint32_t lane, uint32_t k,
                                            const Clock* __restrict__ clk, uint32_t s_off,
-                                           uint32_t launch_idx) {
+                                           uint32_t launch_idx, uint32_t* queue, uint8_t* res) {
     const uint32_t L = R.L;
     const SlowParams sp = R.sp;
     const uint32_t t0 = clk->t + R.t + s_off;
@@ -214,28 +272,35 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
         uint32_t fl = 0;
         if constexpr (VMAX > 0) {
             const uint32_t occ_next = from_next_lane(T[0][0]);
-            uint32_t Eq[Q][VMAX + 1];
+            uint32_t T2[Q][VMAX + 2];
+            uint32_t S[Q], U[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const uint32_t occ = T[q][0];
                 const uint32_t nxt = (q + 1 < Q) ? T[(q + 1) % Q][0] : occ_next;
-                uint32_t T2[VMAX + 2];
-                uint32_t U = 0u;
+                uint32_t A = 0u;
 #pragma unroll
                 for (int g = 1; g <= VMAX; ++g) {
-                    U |= __builtin_amdgcn_alignbit(nxt, occ, g);   // car in cell i+g
-                    T2[g] = T[q][g - 1] & ~U;                       // rules 1 and 2
+                    A |= __builtin_amdgcn_alignbit(nxt, occ, g);   // car in cell i+g
+                    T2[q][g] = T[q][g - 1] & ~A;                    // rules 1 and 2
                 }
-                T2[VMAX + 1] = 0u;
-                uint32_t S = 0u;
+                T2[q][VMAX + 1] = 0u;
+                S[q] = 0u;
+                U[q] = 0u;
                 if (sp.thr != 0u) {
-                    const uint32_t moving = T2[1];
-                    if (moving) S = slow_mask(moving, xw[q], aligned[q], t, L, sp);  // rule 3
+                    const uint32_t moving = T2[q][1];
+                    if (moving) slow_hi(moving, xw[q], aligned[q], t, L, sp, S[q], U[q]);  // rule 3
                 }
-                uint32_t T3[VMAX + 2];
-                T3[0] = occ;
+            }
+            if ((sp.thr & 0x0FFFFFFFu) != 0u) slow_lo_wave<Q>(S, U, xw, L, t, sp, queue, res, lane);
+            uint32_t Eq[Q][VMAX + 1];
 #pragma unroll
-                for (int m = 1; m <= VMAX; ++m) T3[m] = (T2[m] & ~S) | (T2[m + 1] & S);
+            for (int q = 0; q < Q; ++q) {
+                uint32_t T3[VMAX + 2];
+                T3[0] = T[q][0];
+#pragma unroll
+                for (int m = 1; m <= VMAX; ++m)
+                    T3[m] = (T2[q][m] & ~S[q]) | (T2[q][m + 1] & S[q]);
                 T3[VMAX + 1] = 0u;
                 if (own[q]) {
 #pragma unroll
@@ -315,11 +380,14 @@ __global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restr
                                                          uint32_t n_items, uint32_t* partials,
                                                          uint32_t k, const Clock* __restrict__ clk,
                                                          uint32_t s_off, uint32_t launch_idx) {
-    const uint32_t wave = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ uint32_t s_queue[4][kRefineCap];
+    __shared__ uint8_t s_res[4][kRefineCap];
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t wave = blockIdx.x * 4u + wib;
     if (wave >= n_items) return;
     const TileItem it = items[wave];
     kstep_tile<VMAX, Q>(rings[it.ring], it, wave, n_items, partials, threadIdx.x & 63u, k, clk,
-                        s_off, launch_idx);
+                        s_off, launch_idx, s_queue[wib], s_res[wib]);
 }
 
 // Items of different vmax in one launch: the branch on the ring's vmax is
@@ -332,21 +400,26 @@ __global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* _
                                                                const Clock* __restrict__ clk,
                                                                uint32_t s_off,
                                                                uint32_t launch_idx) {
-    const uint32_t wave = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ uint32_t s_queue[4][kRefineCap];
+    __shared__ uint8_t s_res[4][kRefineCap];
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t wave = blockIdx.x * 4u + wib;
     if (wave >= n_items) return;
     const TileItem it = items[wave];
     const RingDesc& R = rings[it.ring];
     const uint32_t lane = threadIdx.x & 63u;
+    uint32_t* queue = s_queue[wib];
+    uint8_t* res = s_res[wib];
     switch (R.vmax) {
-        case 0: kstep_tile<0, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
-        case 1: kstep_tile<1, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
-        case 2: kstep_tile<2, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
-        case 3: kstep_tile<3, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
-        case 4: kstep_tile<4, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
-        case 5: kstep_tile<5, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
-        case 6: kstep_tile<6, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
-        case 7: kstep_tile<7, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
-        case 8: kstep_tile<8, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx); break;
+        case 0: kstep_tile<0, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 1: kstep_tile<1, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 2: kstep_tile<2, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 3: kstep_tile<3, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 4: kstep_tile<4, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 5: kstep_tile<5, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 6: kstep_tile<6, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 7: kstep_tile<7, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 8: kstep_tile<8, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
         default: break;
     }
 }
