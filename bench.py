@@ -175,6 +175,74 @@ def bench_ensemble(args):
     return line
 
 
+def bench_serving(args):
+    """Continuous batching: Poisson arrivals of requests (L log-uniform in
+    [1e3, 1e7], density U[0.05, 0.6], p U[0, 0.5], vmax U{1..8}, T log-uniform
+    in [1e2, 1e4]) at a fraction of the capacity measured on a short ensemble
+    run; reports p50/p99 latency (arrival to result on the host) and the
+    aggregate cell-updates/s over the whole stream."""
+    import threading
+    import torch
+    from paper_2309_14311_amd import Batch, Server, workloads
+    # capacity: cell-updates/s of the batched kernel on an ensemble shaped like the requests
+    cal = workloads.requests(512, seed=99, rate=1.0)
+    b = Batch([dict(r, warmup=0) for r in cal], k=32, q=4, use_graph=True)
+    b.step(64)
+    ms = b.timed_step(256)
+    cap_cups = sum(r["L"] for r in cal) * 256 / (ms * 1e-3)
+    b.close()
+    mean_work = float(np.mean([r["L"] * r["T"] for r in workloads.requests(20000, seed=98)]))
+    rate = args.rate_frac * cap_cups / mean_work
+    reqs = workloads.requests(args.requests, seed=7, rate=rate)
+    _log(f"serving: capacity {cap_cups:.3g} cell-updates/s, mean work {mean_work:.3g}, "
+         f"rate {rate:.1f}/s x {len(reqs)} requests")
+    srv = Server(k=32, q=4)
+    results = {}
+    submitted = {}
+    t0 = time.perf_counter()
+    s0 = srv.now()
+
+    def producer():
+        for r in reqs:
+            delay = r["arrival"] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            rid = srv.submit(r["L"], r["N"], r["vmax"], r["p"], r["seed"], r["T"],
+                             init_v=r["init_v"], want_flux=False)
+            submitted[rid] = r
+
+    th = threading.Thread(target=producer)
+    th.start()
+    while len(results) < len(reqs):
+        for res in srv.poll(max_results=1024, wait_ms=20):
+            results[res["id"]] = res
+    th.join()
+    st = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in results.values()])
+    first = min(r["t_submit"] for r in results.values())
+    last = max(r["t_done"] for r in results.values())
+    work = sum(r["L"] * r["T"] for r in reqs)
+    bad = sum(1 for r in results.values() if r["status"] != 0)
+    value = work / (last - first)
+    return {
+        "metric": "cell-updates/s and % HBM roofline, batched vs plain on 1 GPU, bit-exact",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": len(reqs),
+        "warmup": 0, "ms_per_step": (last - first) * 1e3 / len(reqs),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"serving: Poisson arrivals at {args.rate_frac} x capacity "
+                               f"({rate:.1f} requests/s), {len(reqs)} requests"},
+        "hbm_roofline_frac": value * BYTES_PER_CELL_UPDATE / HBM_PEAK,
+        "extra": {"latency_p50_s": float(np.percentile(lat, 50)),
+                  "latency_p99_s": float(np.percentile(lat, 99)),
+                  "latency_mean_s": float(lat.mean()), "failed": bad,
+                  "capacity_cups": cap_cups, "rate_per_s": rate, "launches": st["launches"],
+                  "makespan_s": last - first, "server_clock_origin": s0},
+    }
+
+
 def bench_single(args, cfg, rep, kernels):
     """One ring: value = k-step (autotuned) CUPS; the one-step kernel beside it."""
     import torch
@@ -213,7 +281,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ensemble",
-                    choices=["ensemble", "large_ring", "agent", "reference"])
+                    choices=["ensemble", "large_ring", "agent", "reference", "serving"])
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--rate-frac", type=float, default=0.5)
     ap.add_argument("--replicas", type=int, default=4096)
     ap.add_argument("--T", type=int, default=5000)
     ap.add_argument("--warmup-steps", type=int, default=1000)
@@ -235,6 +305,8 @@ def main():
     from paper_2309_14311_amd import workloads
     if args.workload == "ensemble":
         line = bench_ensemble(args)
+    elif args.workload == "serving":
+        line = bench_serving(args)
     elif args.workload == "large_ring":
         line = bench_single(args, workloads.LARGE_RING, "grid", ["kstep", "onestep"])
     elif args.workload == "agent":

@@ -55,7 +55,9 @@ __global__ __launch_bounds__(256) void agent_onestep_kernel(const AgentDesc* __r
             d = xn >= xi ? xn - xi : xn + L - xi;
         }
         nv = accel_brake(v[i], d, vmax);
-        if (nv > 0 && sp.thr != 0 && rand32(xi, t, sp) < sp.thr) --nv;   // rule 3
+        if (nv > 0 && sp.thr != 0 &&                                        // rule 3
+            slow_from_hi(hi_nibble(slow_hi_planes(xi >> 5, t, sp), xi), xi, t, sp))
+            --nv;
         uint32_t xn = xi + nv;                                             // rule 4
         if (xn >= L) xn -= L;
         xo[i] = (int32_t)xn;

@@ -117,6 +117,7 @@ struct GridEngine {
     uint32_t* d_log_rings = nullptr;
     size_t log_rings_cap = 0;
     uint32_t n_log_rings = 0;
+    uint32_t max_log_tiles = 0;   // most tiles of any ring that keeps a log
 
     ~GridEngine() { release(); }
     void release() {
@@ -190,8 +191,12 @@ struct GridEngine {
 
     hipError_t upload_rings(hipStream_t s) {
         std::vector<uint32_t> logs;
+        max_log_tiles = 0;
         for (uint32_t i = 0; i < rings.size(); ++i)
-            if (rings[i].flux_log) logs.push_back(i);
+            if (rings[i].flux_log) {
+                logs.push_back(i);
+                max_log_tiles = std::max(max_log_tiles, rings[i].ntiles);
+            }
         n_log_rings = (uint32_t)logs.size();
         if (logs.size() > log_rings_cap) {
             if (d_log_rings) (void)hipFree(d_log_rings);
@@ -232,8 +237,8 @@ struct GridEngine {
                                              (uint32_t)items.size(), d_partials, ki, d_clk, i * k,
                                              i, s);
             if (e == hipSuccess && n_log_rings)
-                e = launch_fold_ring_flux(d_rings, d_log_rings, n_log_rings, d_partials,
-                                          (uint32_t)items.size(), ki, d_clk, i * k, s);
+                e = launch_fold_ring_flux(d_rings, d_log_rings, n_log_rings, max_log_tiles,
+                                          d_partials, (uint32_t)items.size(), ki, d_clk, i * k, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;

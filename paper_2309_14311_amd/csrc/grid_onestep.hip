@@ -3,37 +3,42 @@
 // vmax halo on each side (rules 1-4 of the Handout, applied car by car).
 //
 // Each thread owns 32 consecutive cells (one aligned rule-3 block, so one
-// Philox call covers them), computes the new velocity of every car it owns and
-// scatters the car into a cleared LDS copy of the tile.  Cars up to vmax cells
-// left of the tile can land inside it; thread 0 recomputes those as well.  The
-// tile is then written back with 16-byte stores.  F(t) counts owned cars only.
+// Philox call covers them).  It builds the occupancy mask of its cells and the
+// 8 after them, visits its cars through the mask (the distance to the car in
+// front is a trailing-zero count), and scatters each car into a cleared LDS
+// copy of the tile.  Cars up to vmax cells left of the tile can land inside
+// it; lanes 0..vmax-1 recompute those.  The tile is then written back with
+// 16-byte stores.  F(t) counts owned cars only.
 #include "launchers.hpp"
 
 namespace nasch {
 
 namespace {
 constexpr uint32_t kThreads = 256;
-constexpr uint32_t kHalo = 16;  // >= vmax
+constexpr uint32_t kHalo = 16;  // >= vmax, keeps the LDS copy 16-byte aligned
 constexpr uint32_t kTile = kOneStepTile;
 static_assert(kTile == kThreads * 32, "one 32-cell block per thread");
 
-// New velocity of the car at tile-local cell c (rules 1-3); `in` is the LDS
-// copy indexed by tile-local cell + kHalo.
-__device__ __forceinline__ uint32_t car_velocity(const uint8_t* in, int c, uint32_t vmax,
-                                                 uint32_t hi4, bool hi_known, uint32_t x,
-                                                 uint32_t t, const SlowParams& sp) {
-    const uint32_t v = in[kHalo + c];
-    uint32_t d = 1;
-    while (d <= vmax && in[kHalo + c + d] == kEmpty) ++d;
+// bit 7 of each byte of w -> bits 0..3
+__device__ __forceinline__ uint32_t byte_msbs(uint32_t w) {
+    return (((w >> 7) & 0x01010101u) * 0x00204081u) >> 21 & 0xFu;
+}
+
+// Rules 1-3 for one car: v its velocity, d the distance to the car in front
+// (capped at vmax + 1, which rule 2 cannot tell from farther), hi4 the top
+// nibble of its R (the low bits are drawn only on a tie).
+__device__ __forceinline__ uint32_t new_velocity(uint32_t v, uint32_t d, uint32_t vmax,
+                                                 uint32_t hi4, uint32_t x, uint32_t t,
+                                                 const SlowParams& sp) {
     uint32_t nv = min(v + 1u, vmax);       // rule 1
     if (nv >= d) nv = d - 1u;              // rule 2
-    if (nv > 0 && sp.thr != 0) {           // rule 3
-        bool slow;
-        if (hi_known) slow = slow_from_hi(hi4, x, t, sp);
-        else slow = rand32(x, t, sp) < sp.thr;
-        if (slow) --nv;
-    }
+    if (nv > 0 && sp.thr != 0 && slow_from_hi(hi4, x, t, sp)) --nv;   // rule 3
     return nv;
+}
+
+__device__ __forceinline__ uint32_t nibble(const Word4& w, uint32_t j) {
+    return (((w.w0 >> j) & 1u) << 3) | (((w.w1 >> j) & 1u) << 2) | (((w.w2 >> j) & 1u) << 1) |
+           ((w.w3 >> j) & 1u);
 }
 }  // namespace
 
@@ -83,34 +88,46 @@ __global__ __launch_bounds__(kThreads) void grid_onestep_kernel(const RingDesc* 
     }
     __syncthreads();
 
-    // ---- owned cars
+    // ---- owned cars: occupancy of the thread's 32 cells and the 8 after them
     uint32_t flux = 0;
     const uint32_t c0 = tid * 32u;
     if (c0 < len) {
+        const uint4* in4 = reinterpret_cast<const uint4*>(s_in + kHalo + c0);
+        const uint4 a = in4[0], b = in4[1];
+        const uint2 c = *reinterpret_cast<const uint2*>(s_in + kHalo + c0 + 32);
+        const uint32_t w[10] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y};
+        uint64_t occ = 0;
+#pragma unroll
+        for (int d = 0; d < 10; ++d) occ |= (uint64_t)byte_msbs(~w[d]) << (4 * d);
         const uint32_t n = min(32u, len - c0);
-        bool any = false;
-        for (uint32_t j = 0; j < n; ++j) any |= (s_in[kHalo + c0 + j] != kEmpty);
-        if (any) {
+        uint32_t cars = (uint32_t)occ & (n >= 32u ? 0xFFFFFFFFu : ((1u << n) - 1u));
+        if (cars) {
             Word4 hp{0, 0, 0, 0};
             if (sp.thr != 0) hp = slow_hi_planes((start + c0) >> 5, t, sp);
-            for (uint32_t j = 0; j < n; ++j) {
-                const int c = (int)(c0 + j);
-                if (s_in[kHalo + c] == kEmpty) continue;
-                const uint32_t hi4 = (((hp.w0 >> j) & 1u) << 3) | (((hp.w1 >> j) & 1u) << 2) |
-                                     (((hp.w2 >> j) & 1u) << 1) | ((hp.w3 >> j) & 1u);
-                const uint32_t v = car_velocity(s_in, c, vmax, hi4, true, start + c0 + j, t, sp);
-                if ((uint32_t)c + v < len) s_out[c + v] = (uint8_t)v;
+            while (cars) {
+                const uint32_t j = __builtin_ctz(cars);
+                cars &= cars - 1u;
+                const uint64_t ahead = occ >> (j + 1);
+                const uint32_t d = ahead ? min((uint32_t)__builtin_ctzll(ahead) + 1u, vmax + 1u)
+                                         : vmax + 1u;
+                const uint32_t v = new_velocity(s_in[kHalo + c0 + j], d, vmax, nibble(hp, j),
+                                                start + c0 + j, t, sp);
+                if (c0 + j + v < len) s_out[c0 + j + v] = (uint8_t)v;
                 flux += v;
             }
         }
     }
-    // ---- cars up to vmax cells left of the tile that may land inside it
-    if (tid == 0) {
-        for (int c = -(int)vmax; c < 0; ++c) {
-            if (s_in[kHalo + c] == kEmpty) continue;
+    // ---- the cars up to vmax cells left of the tile may land inside it: one lane each
+    if (tid < vmax) {
+        const int c = -1 - (int)tid;
+        if (s_in[kHalo + c] != kEmpty) {
+            uint32_t d = 1;
+            while (d <= vmax && s_in[kHalo + c + d] == kEmpty) ++d;
             int64_t pos = ((int64_t)start + c) % (int64_t)L;
             if (pos < 0) pos += L;
-            const uint32_t v = car_velocity(s_in, c, vmax, 0, false, (uint32_t)pos, t, sp);
+            const uint32_t x = (uint32_t)pos;
+            const Word4 hb = sp.thr != 0 ? slow_hi_planes(x >> 5, t, sp) : Word4{0, 0, 0, 0};
+            const uint32_t v = new_velocity(s_in[kHalo + c], d, vmax, nibble(hb, x & 31u), x, t, sp);
             const int dstc = c + (int)v;
             if (dstc >= 0 && (uint32_t)dstc < len) s_out[dstc] = (uint8_t)v;
         }
@@ -129,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void grid_onestep_kernel(const RingDesc* 
     }
     if (tid == 0) {
         uint32_t total = 0;
-        for (uint32_t w = 0; w < kThreads / 64; ++w) total += s_flux[w];
+        for (uint32_t wv = 0; wv < kThreads / 64; ++wv) total += s_flux[wv];
         if (R.flux_log) partials[blockIdx.x] = total;
         if (R.flux_acc && (uint64_t)t >= R.warmup && total)
             atomicAdd(R.flux_acc, (unsigned long long)total);

@@ -160,13 +160,17 @@ hipError_t launch_agent_to_grid(const int32_t* x, const uint8_t* v, uint32_t N, 
 }
 
 // ---- flux folding -------------------------------------------------------------
-// Block (r, s): F(t0 + s) of ring log_rings[r] = sum of its items' partials of step s.
+// The kernels leave F(t) per item and step in partials[s * n_items + item]; the
+// fold adds them up.  Block (r, s, c) sums chunk c (kFoldChunk items) of ring
+// log_rings[r] for step s and adds it to the ring's (zero-initialised) log
+// entry: a handful of atomics per step instead of one per item.
+constexpr uint32_t kFoldChunk = 4096;
+
 __device__ __forceinline__ unsigned long long block_sum(const uint32_t* p, uint32_t n) {
     __shared__ unsigned long long part[4];
     unsigned long long v = 0;
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
-    // 64-bit sum of the wave: two 32-bit wave totals (partials fit 32 bits each,
-    // a wave's sum of up to n/64 of them may not)
+    // 64-bit wave sum from two 32-bit wave totals of the halves of v
     const uint32_t lo = wave_total((uint32_t)(v & 0xFFFFFFFFull));
     const uint32_t hi = wave_total((uint32_t)(v >> 32));
     const unsigned long long w = ((unsigned long long)hi << 32) + lo;
@@ -186,19 +190,22 @@ __global__ __launch_bounds__(256) void fold_ring_flux_kernel(const RingDesc* __r
                                                              uint32_t s_off) {
     const RingDesc& R = rings[log_rings[blockIdx.x]];
     const uint32_t s = blockIdx.y;
+    const uint32_t first = blockIdx.z * kFoldChunk;
     const uint32_t t = clk->t + R.t + s_off + s;
-    if (s >= k || (R.t_end != 0xFFFFFFFFu && t >= R.t_end)) return;
+    if (s >= k || first >= R.ntiles || (R.t_end != 0xFFFFFFFFu && t >= R.t_end)) return;
+    const uint32_t n = min(kFoldChunk, R.ntiles - first);
     const unsigned long long total =
-        block_sum(partials + (size_t)s * n_items + R.first_item, R.ntiles);
-    if (threadIdx.x == 0) R.flux_log[(uint64_t)t - R.log_t0] = total;
+        block_sum(partials + (size_t)s * n_items + R.first_item + first, n);
+    if (threadIdx.x == 0 && total) atomicAdd(&R.flux_log[(uint64_t)t - R.log_t0], total);
 }
 
 hipError_t launch_fold_ring_flux(const RingDesc* rings, const uint32_t* log_rings, uint32_t n_log,
-                                 const uint32_t* partials, uint32_t n_items, uint32_t k,
-                                 const Clock* clk, uint32_t s_off, hipStream_t s) {
-    if (n_log == 0 || k == 0) return hipSuccess;
-    NASCH_LAUNCH(fold_ring_flux_kernel, dim3(n_log, k), dim3(256), 0, s, rings, log_rings, partials,
-                 n_items, k, clk, s_off);
+                                 uint32_t max_tiles, const uint32_t* partials, uint32_t n_items,
+                                 uint32_t k, const Clock* clk, uint32_t s_off, hipStream_t s) {
+    if (n_log == 0 || k == 0 || max_tiles == 0) return hipSuccess;
+    const uint32_t chunks = (max_tiles + kFoldChunk - 1) / kFoldChunk;
+    NASCH_LAUNCH(fold_ring_flux_kernel, dim3(n_log, k, chunks), dim3(256), 0, s, rings, log_rings,
+                 partials, n_items, k, clk, s_off);
     return hipGetLastError();
 }
 
@@ -208,16 +215,20 @@ __global__ __launch_bounds__(256) void fold_agent_flux_kernel(const AgentDesc* _
                                                               const Clock* __restrict__ clk,
                                                               uint32_t s_off) {
     const uint32_t s = blockIdx.x;
+    const uint32_t first = blockIdx.y * kFoldChunk;
     const uint32_t t = clk->t + A->t + s_off + s;
-    const unsigned long long total = block_sum(partials + (size_t)s * n_items, n_items);
-    if (threadIdx.x == 0 && A->flux_log) A->flux_log[(uint64_t)t - A->log_t0] = total;
+    const uint32_t n = min(kFoldChunk, n_items - first);
+    const unsigned long long total = block_sum(partials + (size_t)s * n_items + first, n);
+    if (threadIdx.x == 0 && A->flux_log && total)
+        atomicAdd(&A->flux_log[(uint64_t)t - A->log_t0], total);
 }
 
 hipError_t launch_fold_agent_flux(const AgentDesc* a, const uint32_t* partials, uint32_t n_items,
                                   uint32_t k, const Clock* clk, uint32_t s_off, hipStream_t s) {
-    if (k == 0) return hipSuccess;
-    NASCH_LAUNCH(fold_agent_flux_kernel, dim3(k), dim3(256), 0, s, a, partials, n_items, k, clk,
-                 s_off);
+    if (k == 0 || n_items == 0) return hipSuccess;
+    const uint32_t chunks = (n_items + kFoldChunk - 1) / kFoldChunk;
+    NASCH_LAUNCH(fold_agent_flux_kernel, dim3(k, chunks), dim3(256), 0, s, a, partials, n_items, k,
+                 clk, s_off);
     return hipGetLastError();
 }
 

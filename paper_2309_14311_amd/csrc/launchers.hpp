@@ -39,10 +39,11 @@ hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t value, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, hipStream_t s);
 hipError_t launch_clock_advance(Clock* clk, uint32_t T, uint32_t nlaunch, hipStream_t s);
 // F(t) of each step of a launch from the per-item partials it wrote:
-// partials[s * n_items + item], items of a ring contiguous from ring.first_item.
+// partials[s * n_items + item], items of a ring contiguous from ring.first_item;
+// added into the ring's zero-initialised flux log.  max_tiles bounds ring.ntiles.
 hipError_t launch_fold_ring_flux(const RingDesc* rings, const uint32_t* log_rings, uint32_t n_log,
-                                 const uint32_t* partials, uint32_t n_items, uint32_t k,
-                                 const Clock* clk, uint32_t s_off, hipStream_t s);
+                                 uint32_t max_tiles, const uint32_t* partials, uint32_t n_items,
+                                 uint32_t k, const Clock* clk, uint32_t s_off, hipStream_t s);
 hipError_t launch_fold_agent_flux(const AgentDesc* a, const uint32_t* partials, uint32_t n_items,
                                   uint32_t k, const Clock* clk, uint32_t s_off, hipStream_t s);
 

@@ -191,8 +191,8 @@ int nasch_sim::enqueue_steps(uint64_t T) {
                     hipError_t e = launch_grid_onestep(d_onestep, (uint32_t)L, os_partials, d_clk,
                                                        (uint32_t)i, (uint32_t)i, stream);
                     if (e == hipSuccess)
-                        e = launch_fold_ring_flux(d_onestep, d_zero, 1, os_partials, nb, 1, d_clk,
-                                                  (uint32_t)i, stream);
+                        e = launch_fold_ring_flux(d_onestep, d_zero, 1, nb, os_partials, nb, 1,
+                                                  d_clk, (uint32_t)i, stream);
                     if (e != hipSuccess) return e;
                 }
                 nl = (uint32_t)T;
