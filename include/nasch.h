@@ -80,6 +80,8 @@ extern "C" {
 #define NASCH_KERNEL_AUTO    0u /* autotuned: the temporal-blocked kernel, (k, q) chosen by timing */
 #define NASCH_KERNEL_ONESTEP 1u /* grid: one byte-wise step per launch (k = 1, no blocking) */
 #define NASCH_KERNEL_KSTEP   2u /* grid: k steps per launch, bit-sliced, k*vmax halo; agent: k steps per launch */
+#define NASCH_RNG_KEYED      0u /* rule 3 draws R(seed, replica, t, x), see above */
+#define NASCH_RNG_STREAM     1u /* agent form only: the paper's one shared stream, see below */
 
 typedef struct nasch_sim nasch_sim;
 
@@ -91,9 +93,22 @@ typedef struct {
     uint32_t k;        /* steps per launch for NASCH_KERNEL_KSTEP; 0 = default             */
     uint32_t q;        /* 32-cell words per lane for the bit-sliced kernel (1, 2 or 4); 0 = default */
     uint32_t use_graph;/* 1: replay nasch_step_n launch sequences from a captured hipGraph */
-    uint32_t reserved;
+    uint32_t rng;      /* NASCH_RNG_KEYED (default) or NASCH_RNG_STREAM (agent form only)   */
     void*    stream;   /* hipStream_t to run on; NULL = a stream owned by the handle        */
 } nasch_opts;
+
+/*
+ * NASCH_RNG_STREAM reproduces the paper's own approach to random numbers
+ * (Concepts Covered: one sequence shared by all threads, reached by "moving
+ * ahead"; Handout "IMPORTANT" box: a multiplicative linear congruential
+ * generator): one minstd_rand stream, x <- 48271 x mod (2^31 - 1), seeded
+ * with seed mod (2^31 - 1) (1 if that is 0).  Every car draws one number per
+ * step in car order: car i (agent index, numbered from the lowest cell at
+ * t = 0) at step t takes output number t N + i + 1 and slows iff
+ * x < ceil(p (2^31 - 1)) (binary64).  GPU lanes jump ahead to their numbers
+ * (a^n mod m by a table of powers).  The initial state is the same as in the
+ * keyed mode.
+ */
 
 typedef struct {
     uint64_t L, N, t;
@@ -150,6 +165,11 @@ int nasch_agent_state(nasch_sim* h, int32_t* x, uint8_t* v);
  * restored snapshot gives the same results as the uninterrupted run, because
  * R depends only on (seed, replica, t, x).  Synchronises. */
 int nasch_restore(nasch_sim* h, const uint8_t* grid, uint64_t t);
+
+/* Checkpoint restore in the agent form, keeping car identity (which the
+ * shared-stream mode needs): x[N] int32 positions in road order (cyclically
+ * sorted, distinct, < L), v[N] <= vmax, at step count t.  Synchronises. */
+int nasch_restore_agent(nasch_sim* h, const int32_t* x, const uint8_t* v, uint64_t t);
 
 /* Choose the kernel and its tuning explicitly (values as in nasch_opts).
  * k = 0 or q = 0 keeps the current value.  Takes effect at the next step call. */

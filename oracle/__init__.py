@@ -57,6 +57,10 @@ def _load():
         "oracle_step_agent": (U64, [U64, U64, U32, U32, U64, U32, U32, i32p, u8p, i32p, u8p]),
         "oracle_run_agent": (I32, [U64, U64, U32, DBL, U64, U32, U64, U64, i32p, u8p, u64p]),
         "oracle_grid_to_agent": (U64, [U64, u8p, i32p, u8p]),
+        "oracle_mlcg_seed": (U32, [U64]),
+        "oracle_mlcg_next": (U32, [U32]),
+        "oracle_mlcg_threshold": (U32, [DBL]),
+        "oracle_run_agent_mlcg": (I32, [U64, U64, U32, DBL, u32p, U64, i32p, u8p, u64p]),
         "oracle_advance_segment": (I32, [U64, U32, DBL, U64, U32, U64, U64, U64, U64, u8p,
                                          u8p]),
         "oracle_window_from_init": (I32, [U64, U64, U32, DBL, U64, U32, U32, U64, U64, U64,
@@ -157,6 +161,36 @@ def run_agent(L, x, v, vmax, p, seed, T, t0=0, replica=0):
                                   _ptr(x, i32p), _ptr(v, u8p), _ptr(flux, u64p))
     if rc:
         raise MemoryError("oracle_run_agent")
+    return x, v, flux[:T]
+
+
+def mlcg_seed(seed: int) -> int:
+    return int(_load().oracle_mlcg_seed(seed))
+
+
+def mlcg_next(x: int) -> int:
+    return int(_load().oracle_mlcg_next(x))
+
+
+def mlcg_threshold(p: float) -> int:
+    return int(_load().oracle_mlcg_threshold(float(p)))
+
+
+def run_agent_mlcg(L, x, v, vmax, p, seed, T, t0=0):
+    """T steps with the shared minstd stream, starting at step t0 (the stream
+    is first advanced serially past the t0 * N draws of the earlier steps).
+    Returns (x, v, flux[T])."""
+    x = np.array(x, dtype=np.int32, copy=True, order="C")
+    v = np.array(v, dtype=np.uint8, copy=True, order="C")
+    lib = _load()
+    st = ctypes.c_uint32(lib.oracle_mlcg_seed(seed))
+    for _ in range(t0 * x.size):
+        st.value = lib.oracle_mlcg_next(st.value)
+    flux = np.zeros(max(T, 1), np.uint64)
+    rc = lib.oracle_run_agent_mlcg(L, x.size, vmax, float(p), ctypes.byref(st), T,
+                                   _ptr(x, i32p), _ptr(v, u8p), _ptr(flux, u64p))
+    if rc:
+        raise MemoryError("oracle_run_agent_mlcg")
     return x, v, flux[:T]
 
 

@@ -222,6 +222,33 @@ void oracle_init_window(uint64_t L, uint64_t N, uint32_t vmax, uint32_t init_v,
 }
 
 /* ------------------------------------------------------------------------- */
+/* The paper's own random numbers (Concepts Covered; Handout "IMPORTANT" box):  */
+/* one multiplicative linear congruential stream shared by all cars.  Here it */
+/* is the C++ minstd_rand engine, x <- 48271 x mod (2^31 - 1), seeded with    */
+/* seed mod m (1 if that is 0).  Every car draws one number per step, in car  */
+/* order: car i at step t uses output number t N + i + 1 of the stream.  The  */
+/* uniform r = x / m is below p iff x < ceil(p m) (binary64).                  */
+/* ------------------------------------------------------------------------- */
+#define MLCG_A 48271u
+#define MLCG_M 2147483647u
+
+uint32_t oracle_mlcg_seed(uint64_t seed)
+{
+    uint32_t x0 = (uint32_t)(seed % MLCG_M);
+    return x0 ? x0 : 1u;
+}
+
+uint32_t oracle_mlcg_next(uint32_t x)
+{
+    return (uint32_t)(((uint64_t)MLCG_A * x) % MLCG_M);
+}
+
+uint32_t oracle_mlcg_threshold(double p)
+{
+    return (uint32_t)ceil(p * 2147483647.0);
+}
+
+/* ------------------------------------------------------------------------- */
 /* One car, rules 1-4.  v is the car's velocity at the start of step t, d its */
 /* distance to the car in front.  Returns the velocity after the step; the    */
 /* car then advances by that many cells.                                      */
@@ -304,6 +331,43 @@ uint64_t oracle_step_agent(uint64_t L, uint64_t N, uint32_t vmax, uint32_t thr, 
         flux += vn;
     }
     return flux;
+}
+
+/* Agent representation with the shared stream: *state is the stream state after
+ * the draws of steps before t0 (oracle_mlcg_seed(seed) at t = 0); it is
+ * advanced by N draws per step, strictly one after another. */
+int oracle_run_agent_mlcg(uint64_t L, uint64_t N, uint32_t vmax, double p, uint32_t *state,
+                          uint64_t T, int32_t *x, uint8_t *v, uint64_t *flux)
+{
+    uint32_t thr = oracle_mlcg_threshold(p);
+    int32_t *xt = (int32_t *)malloc((N ? N : 1) * sizeof(int32_t));
+    uint8_t *vt = (uint8_t *)malloc(N ? N : 1);
+    if (!xt || !vt) { free(xt); free(vt); return -1; }
+    for (uint64_t s = 0; s < T; s++) {
+        uint64_t f = 0;
+        for (uint64_t i = 0; i < N; i++) {
+            uint64_t d;
+            if (N == 1) d = L;
+            else d = ((uint64_t)x[(i + 1) % N] + L - (uint64_t)x[i]) % L;
+            uint32_t vn = v[i];
+            /* rule 1 */
+            if (vn < vmax) vn = vn + 1;
+            /* rule 2 */
+            if ((uint64_t)vn >= d) vn = (uint32_t)(d - 1);
+            /* rule 3: this car's number of the shared stream */
+            *state = oracle_mlcg_next(*state);
+            if (vn > 0 && *state < thr) vn = vn - 1;
+            /* rule 4 */
+            xt[i] = (int32_t)(((uint64_t)x[i] + vn) % L);
+            vt[i] = (uint8_t)vn;
+            f += vn;
+        }
+        if (flux) flux[s] = f;
+        memcpy(x, xt, N * sizeof(int32_t));
+        memcpy(v, vt, N);
+    }
+    free(xt); free(vt);
+    return 0;
 }
 
 int oracle_run_agent(uint64_t L, uint64_t N, uint32_t vmax, double p, uint64_t seed,

@@ -55,9 +55,14 @@ __global__ __launch_bounds__(256) void agent_onestep_kernel(const AgentDesc* __r
             d = xn >= xi ? xn - xi : xn + L - xi;
         }
         nv = accel_brake(v[i], d, vmax);
-        if (nv > 0 && sp.thr != 0 &&                                        // rule 3
-            slow_from_hi(hi_nibble(slow_hi_planes(xi >> 5, t, sp), xi), xi, t, sp))
+        if (A->rng) {                                                        // rule 3
+            const uint64_t n = (uint64_t)t * N + i + 1u;
+            const uint32_t r = mlcg_mul(mlcg_pow(A->mlcg_pow, n), A->mlcg_x0);
+            if (nv > 0 && r < A->mlcg_thr) --nv;
+        } else if (nv > 0 && sp.thr != 0 &&
+                   slow_from_hi(hi_nibble(slow_hi_planes(xi >> 5, t, sp), xi), xi, t, sp)) {
             --nv;
+        }
         uint32_t xn = xi + nv;                                             // rule 4
         if (xn >= L) xn -= L;
         xo[i] = (int32_t)xn;
@@ -129,6 +134,12 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
     uint32_t acc = 0u;
     const bool log = A->flux_log != nullptr;
     const uint32_t ntiles = A->ntiles;
+    // shared stream: the number of the lane's first car at step t0, advanced
+    // by a^N per step; car q adds a factor a, and a^-N when its index wraps.
+    const uint32_t idx0 = (uint32_t)((uint64_t)first % N);
+    uint32_t xs_first = 0u;
+    if (A->rng)
+        xs_first = mlcg_mul(mlcg_pow(A->mlcg_pow, (uint64_t)t0 * N + idx0 + 1u), A->mlcg_x0);
     for (uint32_t s = 0; s < k; ++s) {
         const uint32_t t = t0 + s;
         const uint32_t x_next_lane = from_next_lane(x[0]);
@@ -142,7 +153,23 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
             }
             nv[q] = accel_brake(v[q], d, vmax);
         }
-        if (sp.thr != 0u) {
+        if (A->rng) {
+            // rule 3 from the shared stream
+            uint32_t r = xs_first;
+            uint32_t idx = idx0;
+#pragma unroll
+            for (int q = 0; q < (int)CPL; ++q) {
+                if (q > 0) {
+                    r = mlcg_mul(r, kMlcgA);
+                    if (++idx == N) {
+                        idx = 0;
+                        r = mlcg_mul(r, A->mlcg_inv_aN);
+                    }
+                }
+                if (nv[q] > 0u && r < A->mlcg_thr) --nv[q];
+            }
+            xs_first = mlcg_mul(xs_first, A->mlcg_aN);
+        } else if (sp.thr != 0u) {
             // rule 3: one Philox block call serves every car of the lane in that block
             uint32_t pending = 0u;
 #pragma unroll

@@ -198,6 +198,31 @@ struct Clock {
     uint32_t parity;
 };
 
+// ---- the shared-stream generator ------------------------------------------------
+// minstd_rand: x <- 48271 x mod (2^31 - 1).  Car i at step t takes output number
+// t N + i + 1 of one stream, x_n = a^n x_0 mod m.
+constexpr uint32_t kMlcgA = 48271u;
+constexpr uint32_t kMlcgM = 0x7FFFFFFFu;
+
+// a * b mod (2^31 - 1) for a, b < 2^31, by folding (2^31 = 1 mod m).
+__host__ __device__ inline uint32_t mlcg_mul(uint32_t a, uint32_t b) {
+    const uint64_t z = (uint64_t)a * b;
+    uint32_t r = (uint32_t)(z & kMlcgM) + (uint32_t)(z >> 31);
+    r = (r & kMlcgM) + (r >> 31);
+    return r >= kMlcgM ? r - kMlcgM : r;
+}
+
+// a^n mod m from pow_tab[16 j + d] = a^(d 16^j) mod m.
+__device__ __forceinline__ uint32_t mlcg_pow(const uint32_t* __restrict__ pow_tab, uint64_t n) {
+    uint32_t r = 1u;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t d = (uint32_t)(n >> (4 * j)) & 15u;
+        if (d) r = mlcg_mul(r, pow_tab[16 * j + d]);
+    }
+    return r;
+}
+
 // One ring in the agent representation.
 struct AgentDesc {
     int32_t* x[2];           // ping-pong positions, road order
@@ -210,8 +235,14 @@ struct AgentDesc {
     uint32_t N, L, vmax;
     uint32_t own;            // cars written back per tile by the k-step kernel
     uint32_t ntiles;
-    uint32_t pad;
+    uint32_t rng;            // 0: keyed Philox draw; 1: shared minstd stream
     SlowParams sp;
+    // shared stream (rng == 1)
+    const uint32_t* mlcg_pow;   // 256-entry jump table
+    uint32_t mlcg_x0;           // stream state before the first draw
+    uint32_t mlcg_thr;          // slow iff x < ceil(p m)
+    uint32_t mlcg_aN;           // a^N mod m: one step of every car
+    uint32_t mlcg_inv_aN;       // its inverse mod m
 };
 
 // ---- cross-lane helpers (gfx9 DPP) ----------------------------------------------

@@ -55,6 +55,8 @@ struct nasch_sim {
     AgentDesc h_agent{};
     AgentDesc* d_agent = nullptr;
     uint8_t* agent_grid = nullptr;  // scratch grid for snapshots
+    uint32_t* mlcg_pow = nullptr;   // jump table of the shared stream
+    uint32_t rng = NASCH_RNG_KEYED;
     // F(t) log: flux[t - log_t0]
     unsigned long long* flux = nullptr;
     uint64_t flux_cap = 0, log_t0 = 0;
@@ -90,7 +92,7 @@ nasch_sim::~nasch_sim() {
     eng.release();
     // agent_grid aliases grid[0]
     void* ps[] = {d_clk, grid[0], grid[1], d_onestep, ax[0], ax[1], av[0], av[1], d_agent, flux,
-                  os_partials, d_zero};
+                  os_partials, d_zero, mlcg_pow};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -317,8 +319,10 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
     nasch_opts o;
     nasch_default_opts(&o);
     if (opts) o = *opts;
-    if (o.rep > NASCH_REP_AGENT || o.init_v > NASCH_INIT_V_UNIFORM || o.kernel > NASCH_KERNEL_KSTEP)
+    if (o.rep > NASCH_REP_AGENT || o.init_v > NASCH_INIT_V_UNIFORM || o.kernel > NASCH_KERNEL_KSTEP ||
+        o.rng > NASCH_RNG_STREAM)
         return NASCH_EINVAL;
+    if (o.rng == NASCH_RNG_STREAM && o.rep != NASCH_REP_AGENT) return NASCH_EINVAL;
     std::unique_ptr<nasch_sim> h(new (std::nothrow) nasch_sim());
     if (!h) return NASCH_ENOMEM;
     h->L = L; h->N = N; h->vmax = vmax; h->p = p; h->seed = seed;
@@ -386,6 +390,37 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
         a.N = (uint32_t)N; a.L = (uint32_t)L; a.vmax = vmax;
         a.sp = sp;
         a.warmup = ~0ull;
+        a.rng = o.rng;
+        h->rng = o.rng;
+        if (o.rng == NASCH_RNG_STREAM) {
+            // stream constants: x0, threshold, a^N and its inverse, jump table
+            auto mpow = [](uint32_t b, uint64_t e) {
+                uint32_t r = 1u;
+                while (e) {
+                    if (e & 1u) r = mlcg_mul(r, b);
+                    b = mlcg_mul(b, b);
+                    e >>= 1;
+                }
+                return r;
+            };
+            a.mlcg_x0 = (uint32_t)(seed % kMlcgM);
+            if (!a.mlcg_x0) a.mlcg_x0 = 1u;
+            a.mlcg_thr = (uint32_t)std::ceil(p * 2147483647.0);
+            a.mlcg_aN = mpow(kMlcgA, N);
+            a.mlcg_inv_aN = mpow(a.mlcg_aN, kMlcgM - 2u);
+            std::vector<uint32_t> tab(256);
+            uint32_t base = kMlcgA;   // a^(16^j)
+            for (int j = 0; j < 16; ++j) {
+                tab[16 * j] = 1u;
+                for (int d = 1; d < 16; ++d) tab[16 * j + d] = mlcg_mul(tab[16 * j + d - 1], base);
+                base = mlcg_mul(tab[16 * j + 15], base);
+            }
+            if (!h->ok(dev_alloc(&h->mlcg_pow, 256))) return NASCH_ENOMEM;
+            if (!h->ok(hipMemcpy(h->mlcg_pow, tab.data(), 256 * sizeof(uint32_t),
+                                 hipMemcpyHostToDevice)))
+                return NASCH_EDEVICE;
+            a.mlcg_pow = h->mlcg_pow;
+        }
         uint32_t kk = o.k ? o.k : kDefaultAgentK;
         if (!agent_geometry((uint32_t)N, kk, &a.own, &a.ntiles)) return NASCH_EINVAL;
         rc = h->ensure_os_partials(std::max<size_t>((size_t)a.ntiles * kk, h->agent_onestep_waves()));
@@ -523,6 +558,34 @@ int nasch_restore(nasch_sim* h, const uint8_t* grid, uint64_t t) {
     int rc = h->refresh_descs();
     if (rc) return rc;
     return NASCH_OK;
+}
+
+int nasch_restore_agent(nasch_sim* h, const int32_t* x, const uint8_t* v, uint64_t t) {
+    if (!h || (h->N && (!x || !v))) return NASCH_EINVAL;
+    if (h->rep != NASCH_REP_AGENT) return NASCH_ESTATE;
+    if (t > 0xFFFFFFFFull) return NASCH_ERANGE;
+    uint64_t descents = 0;
+    std::vector<uint8_t> seen(h->L, 0);
+    for (uint64_t i = 0; i < h->N; ++i) {
+        if (x[i] < 0 || (uint64_t)x[i] >= h->L || v[i] > h->vmax || seen[x[i]]) return NASCH_EINVAL;
+        seen[x[i]] = 1;
+        if (i + 1 < h->N && x[i + 1] < x[i]) ++descents;
+    }
+    if (descents > 1) return NASCH_EINVAL;
+    if (!h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
+    h->parity = 0;
+    h->t = t;
+    const Clock c{(uint32_t)t, 0u};
+    if (!h->ok(hipMemcpyAsync(h->d_clk, &c, sizeof(Clock), hipMemcpyHostToDevice, h->stream)))
+        return NASCH_EDEVICE;
+    if (h->N && (!h->ok(hipMemcpyAsync(h->ax[0], x, h->N * sizeof(int32_t), hipMemcpyHostToDevice,
+                                       h->stream)) ||
+                 !h->ok(hipMemcpyAsync(h->av[0], v, h->N, hipMemcpyHostToDevice, h->stream))))
+        return NASCH_EDEVICE;
+    if (!h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
+    h->log_t0 = t;
+    if (h->flux && !h->ok(launch_fill_u64(h->flux, h->flux_cap, h->stream))) return NASCH_EDEVICE;
+    return h->refresh_descs();
 }
 
 int nasch_set_tuning(nasch_sim* h, uint32_t kernel, uint32_t k, uint32_t q) {

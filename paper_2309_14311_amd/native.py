@@ -19,6 +19,7 @@ NASCH_OK, NASCH_EINVAL, NASCH_ENOMEM, NASCH_EDEVICE = 0, -1, -2, -3
 NASCH_ERANGE, NASCH_ESTATE, NASCH_EBUSY, NASCH_ENOTFOUND = -4, -5, -6, -7
 REP = {"grid": 0, "agent": 1}
 KERNEL = {"auto": 0, "onestep": 1, "kstep": 2}
+RNG = {"keyed": 0, "stream": 1}
 EMPTY = 0xFF
 
 u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -32,7 +33,7 @@ U32, U64, I32, DBL, VP = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.
 
 class Opts(ctypes.Structure):
     _fields_ = [("replica", U32), ("rep", U32), ("init_v", U32), ("kernel", U32), ("k", U32),
-                ("q", U32), ("use_graph", U32), ("reserved", U32), ("stream", VP)]
+                ("q", U32), ("use_graph", U32), ("rng", U32), ("stream", VP)]
 
 
 class Info(ctypes.Structure):
@@ -78,6 +79,7 @@ _SIGS = {
     "nasch_snapshot_range": (I32, [VP, U64, U64, u8p]),
     "nasch_agent_state": (I32, [VP, i32p, u8p]),
     "nasch_restore": (I32, [VP, u8p, U64]),
+    "nasch_restore_agent": (I32, [VP, i32p, u8p, U64]),
     "nasch_set_tuning": (I32, [VP, U32, U32, U32]),
     "nasch_autotune": (I32, [VP]),
     "nasch_get_info": (I32, [VP, ctypes.POINTER(Info)]),
@@ -166,11 +168,11 @@ class Sim:
     """One ring (nasch_init ... nasch_free)."""
 
     def __init__(self, L, N, vmax, p, seed, *, replica=0, rep="grid", init_v=0, kernel="auto",
-                 k=0, q=0, use_graph=False, stream=None):
+                 k=0, q=0, use_graph=False, stream=None, rng="keyed"):
         lib = load()
         o = Opts()
         lib.nasch_default_opts(ctypes.byref(o))
-        o.replica, o.rep, o.init_v = replica, REP[rep], int(init_v)
+        o.replica, o.rep, o.init_v, o.rng = replica, REP[rep], int(init_v), RNG[rng]
         o.kernel, o.k, o.q, o.use_graph = KERNEL[kernel], k, q, int(bool(use_graph))
         o.stream = _stream_ptr(stream)
         h = VP()
@@ -223,6 +225,12 @@ class Sim:
     def restore(self, grid: np.ndarray, t: int):
         g = np.ascontiguousarray(grid, dtype=np.uint8)
         self._check(_lib.nasch_restore(self._h, _u8(g), t), "nasch_restore")
+
+    def restore_agent(self, x: np.ndarray, v: np.ndarray, t: int):
+        xa = np.ascontiguousarray(x, dtype=np.int32)
+        va = np.ascontiguousarray(v, dtype=np.uint8)
+        self._check(_lib.nasch_restore_agent(self._h, xa.ctypes.data_as(i32p), _u8(va), t),
+                    "nasch_restore_agent")
 
     def set_tuning(self, kernel="kstep", k=0, q=0):
         self._check(_lib.nasch_set_tuning(self._h, KERNEL[kernel], k, q), "nasch_set_tuning")

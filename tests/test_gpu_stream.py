@@ -1,0 +1,57 @@
+"""GPU parity of the shared-stream mode (the paper's one generator for all
+cars, reached by jump-ahead on the GPU) against the oracle, which runs the
+stream strictly serially."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_14311_amd import NaschError, Sim
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(L, N, vmax, p, seed, T, init_v=1):
+    g0 = oracle.init_grid(L, N, vmax, seed, init_v=init_v)
+    x, v = oracle.grid_to_agent(g0)
+    return oracle.run_agent_mlcg(L, x, v, vmax, p, seed, T)
+
+
+@pytest.mark.parametrize("kernel,k", [("onestep", 0), ("kstep", 1), ("kstep", 7), ("kstep", 32),
+                                      ("kstep", 100)])
+@pytest.mark.parametrize("L,N", [(1000, 200), (30011, 9000), (40, 3), (5000, 513)])
+def test_stream_mode_matches_serial_oracle(kernel, k, L, N):
+    vmax, p, seed, T = 5, 0.13, 77, 150
+    xo, vo, fo = _oracle(L, N, vmax, p, seed, T)
+    s = Sim(L, N, vmax, p, seed, rep="agent", rng="stream", init_v=1, kernel=kernel,
+            k=k if k else 0)
+    s.step(T)
+    x, v = s.agent_state()
+    np.testing.assert_array_equal(x, xo)
+    np.testing.assert_array_equal(v, vo)
+    np.testing.assert_array_equal(s.flux(0, T), fo)
+    s.close()
+
+
+def test_stream_mode_restore_agent_resumes_exactly():
+    L, N, vmax, p, seed = 20000, 5000, 5, 0.25, 5
+    a = Sim(L, N, vmax, p, seed, rep="agent", rng="stream", init_v=1)
+    a.step(120)
+    xm, vm = a.agent_state()
+    a.step(80)
+    xe, ve = a.agent_state()
+    b = Sim(L, N, vmax, p, seed + 1, rep="agent", rng="stream")
+    with pytest.raises(NaschError):
+        b.restore_agent(xm[::-1].copy(), vm, 120)   # not in road order
+    b2 = Sim(L, N, vmax, p, seed, rep="agent", rng="stream")
+    b2.restore_agent(xm, vm, 120)
+    b2.step(80)
+    x, v = b2.agent_state()
+    np.testing.assert_array_equal(x, xe)
+    np.testing.assert_array_equal(v, ve)
+    for s in (a, b, b2):
+        s.close()
+
+
+def test_stream_mode_only_in_agent_form():
+    with pytest.raises(NaschError):
+        Sim(1000, 100, 5, 0.1, 1, rep="grid", rng="stream")

@@ -329,3 +329,56 @@ def test_light_cone_window_matches_full_ring(orc):
     out = orc.advance_segment(L, seg, vmax, p, 6, t0, T2, a, w)
     full2, _ = orc.run_grid(full, vmax, p, 6, T2, t0=t0)
     assert np.array_equal(out, full2[a:a + w])
+
+
+# --------------------------------------------------------------------------- shared stream
+def test_minstd_rand_known_answer(orc):
+    """The shared-stream generator is minstd_rand: its 10000th output from the
+    default seed is the value the C++ standard requires."""
+    with open(os.path.join(GOLDEN, "minstd_rand_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            seed, n, want = (int(v) for v in line.split())
+            x = orc.mlcg_seed(seed)
+            for _ in range(n):
+                x = orc.mlcg_next(x)
+            assert x == want
+
+
+def test_mlcg_threshold_is_ceil_p_m(orc):
+    m = 2**31 - 1
+    for p in (0.0, 0.13, 0.25, 0.5, 0.999):
+        assert orc.mlcg_threshold(p) == math.ceil(Fraction(p) * m)
+    assert orc.mlcg_seed(0) == 1 and orc.mlcg_seed(m) == 1 and orc.mlcg_seed(5) == 5
+
+
+def test_stream_mode_without_rule3_equals_keyed_mode(orc):
+    """With p = 0 no draw matters: the shared-stream agent run equals the keyed
+    agent run step for step."""
+    L, N, vmax = 3000, 700, 5
+    g = orc.init_grid(L, N, vmax, seed=4, init_v=1)
+    x, v = orc.grid_to_agent(g)
+    xa, va, fa = orc.run_agent(L, x, v, vmax, 0.0, 4, 300)
+    xb, vb, fb = orc.run_agent_mlcg(L, x, v, vmax, 0.0, 4, 300)
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(fa, fb)
+
+
+def test_stream_mode_invariants_and_rate(orc):
+    """Invariants hold with the shared stream, and a free car drives vmax - p
+    on average (the stream's numbers are uniform)."""
+    L, vmax, p, T = 100000, 5, 0.13, 20000
+    xs, vs, flux = orc.run_agent_mlcg(L, np.array([0]), np.array([vmax]), vmax, p, 3, T)
+    mean = flux.mean()
+    assert abs(mean - (vmax - p)) < 5 * math.sqrt(p * (1 - p) / T)
+    rng = np.random.default_rng(2)
+    L, N = 500, 120
+    g = _random_grid(rng, L, N, vmax)
+    x, v = orc.grid_to_agent(g)
+    for t in range(30):
+        x2, v2, f = orc.run_agent_mlcg(L, x, v, vmax, 0.3, 9, 1, t0=t)
+        gap = (np.roll(x, -1) - x - 1) % L
+        disp = (x2 - x) % L
+        assert np.array_equal(disp, v2) and (disp <= gap).all() and int(f[0]) == int(disp.sum())
+        assert len(set(x2.tolist())) == N
+        x, v = x2, v2
