@@ -311,6 +311,40 @@ double nasch_server_now(nasch_server* s);
 /* Stop the scheduling thread and release everything; unfinished requests are dropped. */
 void nasch_server_destroy(nasch_server* s);
 
+/* ======================================================================= */
+/* Parameter file and output of the paper's starter code (Handout, "Starter */
+/* Code"): a plain-text file of `key = value` lines (L, T, N, p, vmax, seed  */
+/* required; outputprefix, per optional; '#' or ';' start a comment), and    */
+/* three numpy files <prefix>-dens.npy (uint8 [frames, L]: 1 where a car is), */
+/* <prefix>-velo.npy (uint8 [frames, L]: the car's velocity, else 0) and     */
+/* <prefix>-time.npy (int64 [frames]: the step of each frame).              */
+/* ======================================================================= */
+typedef struct {
+    uint64_t L, T, N;
+    double   p;
+    uint32_t vmax, reserved;
+    uint64_t seed, per;         /* per = 0: no output */
+    char     outputprefix[256]; /* default "traffic" */
+} nasch_ini;
+
+/* Parse a parameter file; NASCH_EINVAL on a missing required key, a malformed
+ * value or parameters nasch_init would reject. */
+int nasch_ini_read(const char* path, nasch_ini* out);
+
+typedef struct nasch_writer nasch_writer;
+
+/* Create the three output files for a road of L cells (overwriting them). */
+int nasch_writer_open(nasch_writer** out, const char* prefix, uint64_t L);
+/* Append the simulation's current road as one frame.  The device-to-host copy
+ * is enqueued on the simulation's stream into a pinned staging buffer and the
+ * call returns; a writer thread converts and writes it while the simulation
+ * continues (it blocks only when all staging buffers are in flight). */
+int nasch_writer_frame(nasch_writer* w, nasch_sim* h);
+/* Append a frame from a host grid (L bytes, 0xFF = empty) at step t. */
+int nasch_writer_frame_host(nasch_writer* w, const uint8_t* grid, uint64_t t);
+/* Write every pending frame, finish the headers and close the files. */
+int nasch_writer_close(nasch_writer* w);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,6 +3,8 @@
 The simulation runs in libnasch.so (hand-written HIP); `native` is its ctypes
 binding.  Build with `paper_2309_14311_amd.build.build()`.
 """
-from .native import (Batch, NaschError, Server, Sim, load, LIB_PATH, SYMBOLS)  # noqa: F401
+from .native import (Batch, NaschError, Server, Sim, Writer, ini_read, load, LIB_PATH,  # noqa: F401
+                     SYMBOLS)
 
-__all__ = ["Sim", "Batch", "Server", "NaschError", "load", "LIB_PATH", "SYMBOLS"]
+__all__ = ["Sim", "Batch", "Server", "Writer", "ini_read", "NaschError", "load", "LIB_PATH",
+           "SYMBOLS"]

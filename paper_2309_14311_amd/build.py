@@ -19,7 +19,9 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnasch.so")
 
 SOURCES = ["init.hip", "grid_onestep.hip", "grid_kstep.hip", "agent.hip", "runtime.hip",
-           "batch.hip", "server.hip"]
+           "batch.hip", "server.hip", "output.hip"]
+CLI_SRC = "traffic_main.cpp"
+CLI = os.path.join(PKG, "nasch_traffic")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -51,6 +53,13 @@ def build(jobs: int | None = None) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # the command-line driver, linked against the library next to it
+    cmd = [HIPCC, "-O2", "-std=c++17", "-I", INCLUDE, os.path.join(CSRC, CLI_SRC), "-o",
+           CLI + ".tmp", "-L", PKG, "-lnasch", "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"nasch_traffic build failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(CLI + ".tmp", CLI)
     return LIB
 
 

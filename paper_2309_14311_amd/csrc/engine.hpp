@@ -14,6 +14,10 @@
 #include "launchers.hpp"
 #include "nasch.h"
 
+// Output writer internals shared with the simulation entry points.
+int nasch_writer_enqueue_device(nasch_writer* w, const uint8_t* d_grid, uint64_t t, hipStream_t s);
+uint64_t nasch_writer_length(const nasch_writer* w);
+
 namespace nasch {
 
 // The last failing HIP call of this thread, for failures that leave no handle.

@@ -588,6 +588,14 @@ int nasch_restore_agent(nasch_sim* h, const int32_t* x, const uint8_t* v, uint64
     return h->refresh_descs();
 }
 
+int nasch_writer_frame(nasch_writer* w, nasch_sim* h) {
+    if (!w || !h) return NASCH_EINVAL;
+    if (nasch_writer_length(w) != h->L) return NASCH_EINVAL;
+    const uint8_t* g = h->current_grid_device();
+    if (!g) return NASCH_EDEVICE;
+    return nasch_writer_enqueue_device(w, g, h->t, h->stream);
+}
+
 int nasch_set_tuning(nasch_sim* h, uint32_t kernel, uint32_t k, uint32_t q) {
     if (!h) return NASCH_EINVAL;
     return h->set_tuning(kernel, k, q);

@@ -63,6 +63,12 @@ class Request(ctypes.Structure):
                 ("flux_out", u64p), ("grid_out", u8p)]
 
 
+class Ini(ctypes.Structure):
+    _fields_ = [("L", U64), ("T", U64), ("N", U64), ("p", DBL), ("vmax", U32),
+                ("reserved", U32), ("seed", U64), ("per", U64),
+                ("outputprefix", ctypes.c_char * 256)]
+
+
 class Result(ctypes.Structure):
     _fields_ = [("id", U64), ("status", ctypes.c_int32), ("reserved", U32), ("flux_sum", U64),
                 ("t_submit", DBL), ("t_admit", DBL), ("t_done", DBL)]
@@ -107,6 +113,11 @@ _SIGS = {
     "nasch_server_stats": (I32, [VP, u64p, u64p, u64p, u64p, u64p]),
     "nasch_server_now": (DBL, [VP]),
     "nasch_server_destroy": (None, [VP]),
+    "nasch_ini_read": (I32, [ctypes.c_char_p, ctypes.POINTER(Ini)]),
+    "nasch_writer_open": (I32, [vpp, ctypes.c_char_p, U64]),
+    "nasch_writer_frame": (I32, [VP, VP]),
+    "nasch_writer_frame_host": (I32, [VP, u8p, U64]),
+    "nasch_writer_close": (I32, [VP]),
 }
 
 SYMBOLS = tuple(_SIGS)
@@ -409,6 +420,56 @@ class Server:
         if getattr(self, "_h", None):
             _lib.nasch_server_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ini_read(path: str) -> dict:
+    """Parse a starter-code parameter file (nasch_ini_read)."""
+    lib = load()
+    ini = Ini()
+    rc = lib.nasch_ini_read(os.fsencode(path), ctypes.byref(ini))
+    if rc:
+        raise NaschError(rc, f"nasch_ini_read({path})")
+    d = {f: getattr(ini, f) for f, _ in Ini._fields_ if f not in ("reserved",)}
+    d["outputprefix"] = ini.outputprefix.decode()
+    return d
+
+
+class Writer:
+    """<prefix>-dens/velo/time.npy output (nasch_writer_*)."""
+
+    def __init__(self, prefix: str, L: int):
+        lib = load()
+        h = VP()
+        rc = lib.nasch_writer_open(ctypes.byref(h), os.fsencode(prefix), L)
+        if rc:
+            raise NaschError(rc, "nasch_writer_open")
+        self._h = h
+        self.L = L
+
+    def frame(self, sim: "Sim"):
+        rc = _lib.nasch_writer_frame(self._h, sim._h)
+        if rc:
+            raise NaschError(rc, "nasch_writer_frame")
+
+    def frame_host(self, grid: np.ndarray, t: int):
+        g = np.ascontiguousarray(grid, dtype=np.uint8)
+        assert g.size == self.L
+        rc = _lib.nasch_writer_frame_host(self._h, _u8(g), t)
+        if rc:
+            raise NaschError(rc, "nasch_writer_frame_host")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            rc = _lib.nasch_writer_close(self._h)
+            self._h = None
+            if rc:
+                raise NaschError(rc, "nasch_writer_close")
 
     def __del__(self):
         try:
