@@ -5,8 +5,11 @@
 //   1. admits queued requests in arrival order while their footprint fits the
 //      HBM budget and a slot is free (state allocated from a device arena,
 //      initialised by the init kernel);
-//   2. runs one launch of the temporal-blocked grid kernel over every live slot,
-//      each slot advancing min(k, steps left) steps from its own step counter;
+//   2. runs a burst of launches of the temporal-blocked grid kernel over every
+//      live slot, each slot advancing from its own step counter (the burst
+//      stops where the first slot finishes, and is a single launch while
+//      requests wait for admission); the tile items are rebuilt only when
+//      the set of live slots changes;
 //   3. hands finished slots back: flux log and final grid are copied to the
 //      caller's buffers, the result is queued for nasch_server_poll, and the
 //      slot's memory is returned to the arena.
@@ -91,6 +94,9 @@ struct Job {
 };
 
 // Device bytes of one slot: two grids and the flux log, each rounded to 256 bytes.
+// Launches run back to back before the host looks at the slots again.
+constexpr uint32_t kMaxBurst = 8;
+
 uint64_t footprint(const nasch_request& r) {
     return 2 * ((r.L + 255) / 256 * 256) + (8 * r.T + 255) / 256 * 256;
 }
@@ -163,11 +169,13 @@ void nasch_server::finish(std::unique_ptr<Job> j, int status, uint64_t flux_sum)
 void nasch_server::loop() {
     const uint32_t k = opts.k, q = opts.q;
     std::vector<uint64_t> flux_host;
+    bool dirty = true;   // the set of live slots changed: rebuild the tile items
     for (;;) {
         // ---- admission and cancellation
         std::vector<std::unique_ptr<Job>> admitted;
         std::vector<std::unique_ptr<Job>> cancelled_pending;
         std::vector<uint64_t> cancels;
+        bool waiting;
         {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] { return stop || !pending.empty() || !running.empty() || !cancel_ids.empty(); });
@@ -188,58 +196,73 @@ void nasch_server::loop() {
                 admitted.push_back(std::move(pending.front()));
                 pending.pop_front();
             }
+            waiting = !pending.empty();
         }
         for (auto& j : cancelled_pending) finish(std::move(j), NASCH_ESTATE, 0);
+        if (!admitted.empty()) dirty = true;
         for (auto& j : admitted) running.push_back(std::move(j));
         for (uint64_t id : cancels)
             for (auto& j : running)
                 if (j && j->id == id) j->cancelled = true;
         if (running.empty()) continue;
 
-        // ---- one launch over every live slot
-        eng.rings.clear();
-        for (auto& jp : running) {
-            Job& j = *jp;
+        // ---- descriptors of the live slots (each at its own step and parity)
+        eng.rings.resize(running.size());
+        for (size_t i = 0; i < running.size(); ++i) {
+            const Job& j = *running[i];
             const nasch_request& r = j.req;
             const uint64_t sz = (r.L + 255) / 256 * 256;
-            RingDesc d{};
-            d.buf[0] = arena_base + j.off;
-            d.buf[1] = arena_base + j.off + sz;
-            d.flux_log = reinterpret_cast<unsigned long long*>(arena_base + j.off + 2 * sz);
-            d.flux_acc = nullptr;
-            d.log_t0 = 0;
-            d.warmup = ~0ull;
+            RingDesc& d = eng.rings[i];
+            if (dirty) {
+                d = RingDesc{};
+                d.buf[0] = arena_base + j.off;
+                d.buf[1] = arena_base + j.off + sz;
+                d.flux_log = reinterpret_cast<unsigned long long*>(arena_base + j.off + 2 * sz);
+                d.flux_acc = nullptr;
+                d.log_t0 = 0;
+                d.warmup = ~0ull;
+                d.L = (uint32_t)r.L;
+                d.vmax = r.vmax;
+                d.t_end = (uint32_t)r.T;
+                d.sp = slow_params(r.seed, r.replica, r.p);
+            }
             d.t = j.t;
             d.parity = j.parity;
-            d.L = (uint32_t)r.L;
-            d.vmax = r.vmax;
-            d.t_end = (uint32_t)r.T;
-            d.sp = slow_params(r.seed, r.replica, r.p);
-            eng.rings.push_back(d);
         }
-        if (!st.ok(eng.set_geometry(k, q, stream)) ||
-            !st.ok(eng.enqueue(k, d_clk, stream)) || !st.ok(hipStreamSynchronize(stream))) {
+        // ---- a burst of launches: none of them runs past the first slot to
+        // finish, and only one while requests wait for admission
+        uint32_t m = kMaxBurst;
+        for (const auto& jp : running)
+            m = std::min<uint64_t>(m, (jp->req.T - jp->t + k - 1) / k);
+        if (waiting) m = 1;
+        const hipError_t e_geo = dirty ? eng.set_geometry(k, q, stream) : eng.upload_rings(stream);
+        dirty = false;
+        if (!st.ok(e_geo) || !st.ok(eng.enqueue((uint64_t)m * k, d_clk, stream)) ||
+            !st.ok(hipStreamSynchronize(stream))) {
             // a device failure ends every running request with an error
             for (auto& j : running) finish(std::move(j), NASCH_EDEVICE, 0);
             running.clear();
+            dirty = true;
             continue;
         }
-        ++launches;
+        launches += m;
         // ---- bookkeeping and completions
         std::vector<std::unique_ptr<Job>> still;
         for (auto& jp : running) {
             Job& j = *jp;
-            const uint32_t ran = std::min<uint32_t>(k, (uint32_t)j.req.T - j.t);
-            j.t += ran;
-            j.parity ^= 1u;
+            const uint64_t ran = std::min<uint64_t>((uint64_t)m * k, j.req.T - j.t);
+            j.t += (uint32_t)ran;
+            j.parity ^= m & 1u;
             if (j.cancelled) {
                 finish(std::move(jp), NASCH_ESTATE, 0);
+                dirty = true;
                 continue;
             }
             if (j.t < j.req.T) {
                 still.push_back(std::move(jp));
                 continue;
             }
+            dirty = true;
             const nasch_request& r = j.req;
             const uint64_t sz = (r.L + 255) / 256 * 256;
             flux_host.resize(r.T);
