@@ -17,17 +17,115 @@
 namespace nasch {
 
 namespace {
-__device__ __forceinline__ uint32_t hi_nibble(const Word4& w, uint32_t x) {
-    const uint32_t s = x & 31u;
-    return (((w.w0 >> s) & 1u) << 3) | (((w.w1 >> s) & 1u) << 2) | (((w.w2 >> s) & 1u) << 1) |
-           ((w.w3 >> s) & 1u);
+// rules 1 and 2.  A real car always has d >= 1; the unsigned min leaves a car
+// of a k-step halo that has caught up with its leader (d == 0, possible only
+// for cars whose results are discarded) at its rule-1 speed instead of
+// wrapping below zero.
+__device__ __forceinline__ uint32_t accel_brake(uint32_t v, uint32_t d, uint32_t vmax) {
+    return min(min(v + 1u, vmax), d - 1u);
 }
 
-// rules 1 and 2
-__device__ __forceinline__ uint32_t accel_brake(uint32_t v, uint32_t d, uint32_t vmax) {
-    uint32_t nv = min(v + 1u, vmax);
-    if (nv >= d) nv = d - 1u;
-    return nv;
+constexpr uint32_t kBlockSlots = 256;   // rule-3 blocks tabulated per wave and step
+constexpr uint32_t kTieCap = 256;       // tied cars queued per wave
+
+// LDS scratch of one wave for rule 3.
+struct AgentLds {
+    uint4 blk[kBlockSlots];
+    uint32_t tie_x[kTieCap];
+    uint8_t tie_r[kTieCap];
+};
+
+// Rule 3 for C consecutive cars per lane (keyed draw), shared by the wave.
+// The wave's cars are cyclically sorted, so the 32-cell blocks they start in
+// form one run of blocks from the block of lane 0's first car (mod the number
+// of blocks).  The lanes draw the first kBlockSlots blocks of that run
+// together (one Philox call per lane and 64 blocks) into LDS and every car
+// there reads the top nibble of its R from its block's entry; a car further
+// along (a sparse road) draws its own block.  The cars whose nibble ties with
+// thr's are then numbered across the wave and have their low 28 bits drawn
+// 64 at a time.  `nv` holds each car's velocity after rules 1-2 and receives
+// the result of rule 3.  All 64 lanes must be active; cars with nv == 0 draw
+// nothing.
+template <int C>
+__device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&x)[C],
+                                            uint32_t L, uint32_t t, const SlowParams& sp,
+                                            AgentLds& lds, uint32_t lane) {
+    const uint32_t nblk = (L + 31u) >> 5;
+    const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(x[0] >> 5));
+    const uint32_t cap = min(kBlockSlots, nblk);
+    uint32_t slot[C];
+    uint32_t top = 0;
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        const int32_t dlt = (int32_t)(x[q] >> 5) - (int32_t)b0;
+        slot[q] = dlt < 0 ? (uint32_t)(dlt + (int32_t)nblk) : (uint32_t)dlt;
+        if (nv[q] > 0u && slot[q] < cap) top = max(top, slot[q] + 1u);
+    }
+    const uint32_t n = wave_max(top);   // table entries used, <= cap
+    const uint32_t th = sp.thr >> 28;
+    for (uint32_t j = lane; j < n; j += 64u) {
+        uint32_t blk = b0 + j;
+        if (blk >= nblk) blk -= nblk;
+        const Word4 w = slow_hi_planes(blk, t, sp);
+        lds.blk[j] = make_uint4(w.w0, w.w1, w.w2, w.w3);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t tie = 0;
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        if (nv[q] > 0u) {
+            uint4 e;
+            if (slot[q] < n) {
+                e = lds.blk[slot[q]];
+            } else {
+                const Word4 w = slow_hi_planes(x[q] >> 5, t, sp);
+                e = make_uint4(w.w0, w.w1, w.w2, w.w3);
+            }
+            const uint32_t sh = x[q] & 31u;
+            const uint32_t hi4 = (((e.x >> sh) & 1u) << 3) | (((e.y >> sh) & 1u) << 2) |
+                                 (((e.z >> sh) & 1u) << 1) | ((e.w >> sh) & 1u);
+            if (hi4 < th) --nv[q];
+            else if (hi4 == th) tie |= 1u << q;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
+    if (lo_thr == 0u) return;   // a tie then never slows (the low bits cannot be below 0)
+    const uint32_t cnt = __popc(tie);
+    const uint32_t incl = wave_scan_incl(cnt);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    if (total == 0u) return;
+    const uint32_t nq = min(total, kTieCap);
+    uint32_t idx = incl - cnt;
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        if ((tie >> q) & 1u) {
+            if (idx < kTieCap) lds.tie_x[idx] = x[q];
+            ++idx;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t j = lane; j < nq; j += 64u)
+        lds.tie_r[j] = slow_lo28(lds.tie_x[j], t, sp) < lo_thr ? 1 : 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    idx = incl - cnt;
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        if ((tie >> q) & 1u) {
+            const bool slow = idx < kTieCap ? lds.tie_r[idx] != 0 : slow_lo28(x[q], t, sp) < lo_thr;
+            if (slow) --nv[q];
+            ++idx;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 }  // namespace
 
@@ -59,11 +157,14 @@ __global__ __launch_bounds__(256) void agent_onestep_kernel(const AgentDesc* __r
             const uint64_t n = (uint64_t)t * N + i + 1u;
             const uint32_t r = mlcg_mul(mlcg_pow(A->mlcg_pow, n), A->mlcg_x0);
             if (nv > 0 && r < A->mlcg_thr) --nv;
-        } else if (nv > 0 && sp.thr != 0 &&
-                   slow_from_hi(hi_nibble(slow_hi_planes(xi >> 5, t, sp), xi), xi, t, sp)) {
-            --nv;
+        } else if (nv > 0 && sp.thr != 0) {
+            const Word4 w = slow_hi_planes(xi >> 5, t, sp);
+            const uint32_t sh = xi & 31u;
+            const uint32_t hi4 = (((w.w0 >> sh) & 1u) << 3) | (((w.w1 >> sh) & 1u) << 2) |
+                                 (((w.w2 >> sh) & 1u) << 1) | ((w.w3 >> sh) & 1u);
+            if (slow_from_hi(hi4, xi, t, sp)) --nv;
         }
-        uint32_t xn = xi + nv;                                             // rule 4
+        uint32_t xn = xi + nv;                                               // rule 4
         if (xn >= L) xn -= L;
         xo[i] = (int32_t)xn;
         vo[i] = (uint8_t)nv;
@@ -94,9 +195,12 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
                                                           uint32_t k,
                                                           const Clock* __restrict__ clk,
                                                           uint32_t s_off, uint32_t launch_idx) {
+    __shared__ AgentLds s_lds[4];
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t wave = blockIdx.x * 4u + wib;
     if (wave >= A->ntiles) return;
+    AgentLds& lds = s_lds[wib];
     const uint32_t N = A->N, L = A->L, vmax = A->vmax, own = A->own;
     const SlowParams sp = A->sp;
     const uint32_t t0 = clk->t + A->t + s_off;
@@ -170,25 +274,7 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
             }
             xs_first = mlcg_mul(xs_first, A->mlcg_aN);
         } else if (sp.thr != 0u) {
-            // rule 3: one Philox block call serves every car of the lane in that block
-            uint32_t pending = 0u;
-#pragma unroll
-            for (int q = 0; q < (int)CPL; ++q) pending |= (nv[q] > 0u ? 1u : 0u) << q;
-            while (pending) {
-                uint32_t blk = 0u;
-                bool found = false;
-#pragma unroll
-                for (int q = 0; q < (int)CPL; ++q)
-                    if (!found && ((pending >> q) & 1u)) { blk = x[q] >> 5; found = true; }
-                const Word4 w = slow_hi_planes(blk, t, sp);
-#pragma unroll
-                for (int q = 0; q < (int)CPL; ++q) {
-                    if (((pending >> q) & 1u) && (x[q] >> 5) == blk) {
-                        pending &= ~(1u << q);
-                        if (slow_from_hi(hi_nibble(w, x[q]), x[q], t, sp)) --nv[q];
-                    }
-                }
-            }
+            agent_rule3<(int)CPL>(nv, x, L, t, sp, lds, lane);   // rule 3
         }
         uint32_t fl = 0u;
 #pragma unroll

@@ -106,7 +106,7 @@ def test_tiny_and_ragged_rings(L):
             _run_and_compare(L, N, 5, 0.3, L + 17, 40, rep="agent", init_v=1)
 
 
-@pytest.mark.parametrize("rho", [0.02, 0.2, 0.5, 0.9, 1.0])
+@pytest.mark.parametrize("rho", [0.02, 0.05, 0.2, 0.5, 0.9, 1.0])
 def test_densities_grid_and_agent(rho):
     L = 50000
     N = int(rho * L)
