@@ -247,8 +247,9 @@ def bench_single(args, cfg, rep, kernels):
     """One ring: value = k-step (autotuned) CUPS; the one-step kernel beside it."""
     import torch
     from paper_2309_14311_amd import Sim
+    rng = getattr(args, "rng", "keyed") if rep == "agent" else "keyed"
     s = Sim(cfg["L"], cfg["N"], cfg["vmax"], cfg["p"], cfg["seed"], rep=rep,
-            init_v=cfg["init_v"], use_graph=True)
+            init_v=cfg["init_v"], use_graph=True, rng=rng)
     s.autotune()
     info = s.info()
     T = cfg["T"] if args.T_single is None else args.T_single
@@ -269,7 +270,9 @@ def bench_single(args, cfg, rep, kernels):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": f"{rep} ring L={cfg['L']} N={cfg['N']} vmax={cfg['vmax']} "
-                               f"p={cfg['p']} T={T}", "k": info["k"], "q": info["q"]},
+                               f"p={cfg['p']} T={T}" + (" shared-stream rng" if rng == "stream"
+                                                        else ""),
+                   "k": info["k"], "q": info["q"]},
         "hbm_roofline_frac": value * BYTES_PER_CELL_UPDATE / HBM_PEAK,
         "extra": {f"{k}_cups": v for k, v in res.items()},
     }
@@ -295,6 +298,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rng", default="keyed", choices=["keyed", "stream"],
+                    help="rule-3 numbers of the agent workload: keyed draws or the shared "
+                         "minstd stream")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the NaSch hot path here is measured per GPU "
