@@ -65,6 +65,14 @@ def _load():
                                          u8p]),
         "oracle_window_from_init": (I32, [U64, U64, U32, DBL, U64, U32, U32, U64, U64, U64,
                                           u8p]),
+        "oracle_gate_threshold": (U64, [DBL]),
+        "oracle_gate_words": (None, [U64, U32, U32, u32p, u32p]),
+        "oracle_step_open": (U64, [U64, U64, U64, U32, U32, U64, U64, U64, U32, U32, u8p, u8p,
+                                   u64p, u64p]),
+        "oracle_run_open": (I32, [U64, U64, U64, U32, DBL, DBL, DBL, U64, U32, U64, U64, u8p,
+                                  u64p, u64p, u64p]),
+        "oracle_open_window_from_init": (I32, [U64, U64, U32, DBL, DBL, DBL, U64, U32, U32,
+                                               U64, U64, U64, u8p]),
         "oracle_num_threads_available": (I32, []),
     }
     for name, (res, args) in sig.items():
@@ -226,6 +234,57 @@ def window_from_init(L, N, vmax, p, seed, T, a, w, replica=0, init_v=0) -> np.nd
                                          _ptr(out, u8p))
     if rc:
         raise MemoryError("oracle_window_from_init")
+    return out
+
+
+# --------------------------------------------------------------------------- open road
+def gate_threshold(a: float) -> int:
+    return int(_load().oracle_gate_threshold(float(a)))
+
+
+def gate_words(seed: int, t: int, replica=0):
+    """(entry word, exit word) of the gate draw of step t."""
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    _load().oracle_gate_words(seed, replica, t, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def step_open(g, vmax, p, alpha, beta, seed, t, replica=0, L=None, lo=0):
+    """One step of cells [lo, lo + len(g)) of an open road of L cells (default:
+    the whole road).  Returns (new cells, F(t), entered, left)."""
+    g = np.ascontiguousarray(g, dtype=np.uint8)
+    L = g.size if L is None else L
+    out = np.empty_like(g)
+    e, l = ctypes.c_uint64(), ctypes.c_uint64()
+    f = _load().oracle_step_open(L, lo, g.size, vmax, threshold(p), gate_threshold(alpha),
+                                 gate_threshold(beta), seed, replica, t, _ptr(g, u8p),
+                                 _ptr(out, u8p), ctypes.byref(e), ctypes.byref(l))
+    return out, int(f), e.value, l.value
+
+
+def run_open(g, vmax, p, alpha, beta, seed, T, t0=0, replica=0, L=None, lo=0):
+    """T steps of an open road (or of cells [lo, lo + len(g)) of one of L
+    cells) from step t0.  Returns (cells, flux[T], entered[T], left[T])."""
+    g = np.array(g, dtype=np.uint8, copy=True, order="C")
+    L = g.size if L is None else L
+    flux = np.zeros(max(T, 1), np.uint64)
+    ent = np.zeros(max(T, 1), np.uint64)
+    lft = np.zeros(max(T, 1), np.uint64)
+    rc = _load().oracle_run_open(L, lo, g.size, vmax, float(p), float(alpha), float(beta), seed,
+                                 replica, t0, T, _ptr(g, u8p), _ptr(flux, u64p),
+                                 _ptr(ent, u64p), _ptr(lft, u64p))
+    if rc:
+        raise MemoryError("oracle_run_open")
+    return g, flux[:T], ent[:T], lft[:T]
+
+
+def open_window_from_init(L, N, vmax, p, alpha, beta, seed, T, a, w, replica=0, init_v=0):
+    """Cells [a, a+w) of an open road after T steps from its initial state."""
+    out = np.empty(w, np.uint8)
+    rc = _load().oracle_open_window_from_init(L, N, vmax, float(p), float(alpha), float(beta),
+                                              seed, replica, init_v, T, a, w, _ptr(out, u8p))
+    if rc:
+        raise MemoryError("oracle_open_window_from_init")
     return out
 
 

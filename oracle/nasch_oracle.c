@@ -463,6 +463,138 @@ int oracle_window_from_init(uint64_t L, uint64_t N, uint32_t vmax, double p, uin
     return rc;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Open road (the paper's "Variations": change the boundary conditions).      */
+/* Readings, since the paper gives no details:                                */
+/*   - the road is cells 0 .. L-1 and cars drive toward L-1; nothing wraps;   */
+/*   - at each step t one gate draw G = Philox((0, t, replica, 5)) decides   */
+/*     the ends: a car enters iff word 0 < floor(alpha 2^32), the exit is   */
+/*     open iff word 1 < floor(beta 2^32) (alpha = 1 or beta = 1: always);   */
+/*   - a closed exit acts as a stopped car in cell L for that step, an open  */
+/*     exit as an empty road beyond L-1; rules 1-3 are otherwise unchanged,  */
+/*     and a car whose move ends at or beyond L leaves the road;             */
+/*   - the entering car appears in cell 0 with v = 0 at the end of the step, */
+/*     provided cell 0 was empty at its start (no car can move into cell 0); */
+/*   - F(t) sums the velocities after rules 1-3 of every car that was on the */
+/*     road at the start of the step, so a leaving car counts its whole move. */
+/* For vmax = 1 this is the totally asymmetric exclusion process with        */
+/* parallel update: entry alpha, exit beta (1 - p), hop probability 1 - p.   */
+/* ------------------------------------------------------------------------- */
+#define TAG_GATE 5u
+
+/* floor(a 2^32) for 0 <= a <= 1, in [0, 2^32]: exact, since a * 2^32 only
+ * changes the exponent of a binary64 number. */
+uint64_t oracle_gate_threshold(double a)
+{
+    return (uint64_t)floor(ldexp(a, 32));
+}
+
+/* The two gate words of step t. */
+void oracle_gate_words(uint64_t seed, uint32_t replica, uint32_t t, uint32_t *in_word,
+                       uint32_t *out_word)
+{
+    uint32_t o[4];
+    philox(0u, t, replica, TAG_GATE, seed, o);
+    *in_word = o[0];
+    *out_word = o[1];
+}
+
+/* One synchronous step t of cells [lo, lo+n) of an open road of L cells.
+ * With lo = 0 and n = L this is the whole road.  A sub-range (for light-cone
+ * windows) keeps the real boundary only at the ends it shares with the road:
+ * a cut end takes no car in and treats what lies beyond as empty road, so
+ * only cells far enough from it are exact after several steps.  Returns F(t);
+ * *entered and *left (may be NULL) count the car that came in and the cars
+ * that went out of the road in this step. */
+uint64_t oracle_step_open(uint64_t L, uint64_t lo, uint64_t n, uint32_t vmax, uint32_t thr,
+                          uint64_t thr_in, uint64_t thr_out, uint64_t seed, uint32_t replica,
+                          uint32_t t, const uint8_t *gin, uint8_t *gout, uint64_t *entered,
+                          uint64_t *left)
+{
+    uint32_t in_word, out_word;
+    oracle_gate_words(seed, replica, t, &in_word, &out_word);
+    int at_entry = (lo == 0);
+    int at_exit = (lo + n == L);
+    int enter = at_entry && (uint64_t)in_word < thr_in;
+    int exit_closed = at_exit && !((uint64_t)out_word < thr_out);
+    uint64_t flux = 0, went = 0, came = 0;
+    memset(gout, EMPTY, n);
+    for (uint64_t i = 0; i < n; i++) {
+        if (gin[i] == EMPTY) continue;
+        /* distance to what is in front: the next car within vmax cells, else
+         * the closed exit (a stopped car in cell L), else nothing (vmax + 1
+         * is as good as infinity for rule 2) */
+        uint64_t d = 1;
+        while (d <= vmax && i + d < n && gin[i + d] == EMPTY) d++;
+        if (d <= vmax && i + d >= n) {           /* ran off the end of the cells */
+            if (exit_closed && i + d == n) {
+                /* cell L holds the stopped car: d is its distance */
+            } else {
+                d = (uint64_t)vmax + 1;
+            }
+        }
+        uint32_t v = nasch_rules(gin[i], d, vmax, thr, seed, replica, t, (uint32_t)(lo + i));
+        flux += v;
+        if (i + v < n) gout[i + v] = (uint8_t)v;
+        else if (at_exit) went++;             /* rule 4 took it past cell L-1 */
+    }
+    if (enter && gin[0] == EMPTY) {
+        gout[0] = 0;
+        came = 1;
+    }
+    if (entered) *entered = came;
+    if (left) *left = went;
+    return flux;
+}
+
+/* T steps from step t0 of cells [lo, lo+n) of an open road (see
+ * oracle_step_open); g is updated in place; flux[s], entered[s] and left[s]
+ * (each may be NULL) receive step t0 + s. */
+int oracle_run_open(uint64_t L, uint64_t lo, uint64_t n, uint32_t vmax, double p, double alpha,
+                    double beta, uint64_t seed, uint32_t replica, uint64_t t0, uint64_t T,
+                    uint8_t *g, uint64_t *flux, uint64_t *entered, uint64_t *left)
+{
+    uint32_t thr = oracle_threshold(p);
+    uint64_t thr_in = oracle_gate_threshold(alpha), thr_out = oracle_gate_threshold(beta);
+    uint8_t *tmp = (uint8_t *)malloc(n ? n : 1);
+    if (!tmp) return -1;
+    for (uint64_t s = 0; s < T; s++) {
+        uint64_t e = 0, l = 0;
+        uint64_t f = oracle_step_open(L, lo, n, vmax, thr, thr_in, thr_out, seed, replica,
+                                      (uint32_t)(t0 + s), g, tmp, &e, &l);
+        if (flux) flux[s] = f;
+        if (entered) entered[s] = e;
+        if (left) left[s] = l;
+        memcpy(g, tmp, n);
+    }
+    free(tmp);
+    return 0;
+}
+
+/* Cells [a, a+w) of an open road after T steps from its initial state (the
+ * same placement as the ring), evaluated on the light cone: the cells
+ * [a - T vmax, a + w + T vmax) clipped to the road, run as a sub-range. */
+int oracle_open_window_from_init(uint64_t L, uint64_t N, uint32_t vmax, double p, double alpha,
+                                 double beta, uint64_t seed, uint32_t replica, uint32_t init_v,
+                                 uint64_t T, uint64_t a, uint64_t w, uint8_t *out)
+{
+    uint64_t r = T * (uint64_t)vmax;
+    uint64_t lo = a > r ? a - r : 0;
+    uint64_t hi = a + w + r < L ? a + w + r : L;
+    uint64_t n = hi - lo;
+    uint8_t *g = (uint8_t *)malloc(n ? n : 1);
+    if (!g) return -1;
+    oracle_init_window(L, N, vmax, init_v, replica, seed, lo, n, g);
+    if (oracle_run_open(L, lo, n, vmax, p, alpha, beta, seed, replica, 0, T, g, NULL, NULL,
+                        NULL)) {
+        free(g);
+        return -1;
+    }
+    memcpy(out, g + (a - lo), w);
+    free(g);
+    return 0;
+}
+
 int oracle_num_threads_available(void)
 {
 #ifdef _OPENMP
