@@ -248,8 +248,11 @@ def bench_single(args, cfg, rep, kernels):
     import torch
     from paper_2309_14311_amd import Sim
     rng = getattr(args, "rng", "keyed") if rep == "agent" else "keyed"
+    road = {}
+    if "alpha" in cfg:
+        road = dict(boundary="open", alpha=cfg["alpha"], beta=cfg["beta"])
     s = Sim(cfg["L"], cfg["N"], cfg["vmax"], cfg["p"], cfg["seed"], rep=rep,
-            init_v=cfg["init_v"], use_graph=True, rng=rng)
+            init_v=cfg["init_v"], use_graph=True, rng=rng, **road)
     s.autotune()
     info = s.info()
     T = cfg["T"] if args.T_single is None else args.T_single
@@ -269,7 +272,9 @@ def bench_single(args, cfg, rep, kernels):
         "warmup": args.warmup, "ms_per_step": cfg["L"] * T / value * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"{rep} ring L={cfg['L']} N={cfg['N']} vmax={cfg['vmax']} "
+        "config": {"workload": (f"open road alpha={cfg['alpha']} beta={cfg['beta']}" if road
+                                else f"{rep} ring") +
+                               f" L={cfg['L']} N={cfg['N']} vmax={cfg['vmax']} "
                                f"p={cfg['p']} T={T}" + (" shared-stream rng" if rng == "stream"
                                                         else ""),
                    "k": info["k"], "q": info["q"]},
@@ -284,7 +289,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ensemble",
-                    choices=["ensemble", "large_ring", "agent", "reference", "serving"])
+                    choices=["ensemble", "large_ring", "agent", "reference", "serving",
+                             "open_road"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate-frac", type=float, default=0.5)
     ap.add_argument("--replicas", type=int, default=4096)
@@ -315,6 +321,8 @@ def main():
         line = bench_serving(args)
     elif args.workload == "large_ring":
         line = bench_single(args, workloads.LARGE_RING, "grid", ["kstep", "onestep"])
+    elif args.workload == "open_road":
+        line = bench_single(args, workloads.OPEN_ROAD, "grid", ["kstep", "onestep"])
     elif args.workload == "agent":
         line = bench_single(args, workloads.AGENT_RING, "agent", ["kstep", "onestep"])
     else:

@@ -23,11 +23,11 @@
  * block depth, representation or batch composition (the reproducibility the
  * paper demands in "Concepts Covered" and assignment item 1).
  *
- * Initial state (the paper only says "random positions", Handout "Starter
- * Code"): car i < N starts in cell pi(i), where pi is a 4-round balanced
- * Feistel permutation on b bits (b = ceil(log2 L) rounded up to even, >= 2),
- * round function word 0 of Philox((half, round, replica, 3)) masked to b/2
- * bits, restricted to [0, L) by cycle-walking.  Initial velocity: 0, or
+ * Initial state (the paper asks for random positions but gives no method,
+ * Handout "Starter Code"): car i < N starts in cell pi(i), where pi is a
+ * 4-round balanced Feistel permutation on b bits (b = ceil(log2 L) rounded
+ * up to even, >= 2), round function word 0 of Philox((half, round, replica,
+ * 3)) masked to b/2 bits, restricted to [0, L) by cycle-walking.  Initial velocity: 0, or
  * floor(w * (vmax+1) / 2^32) with w = word 0 of Philox((x, 0, replica, 4)).
  *
  * Grid representation ("Concepts Covered"): one uint8 per cell, 0xFF = empty,
@@ -82,6 +82,8 @@ extern "C" {
 #define NASCH_KERNEL_KSTEP   2u /* grid: k steps per launch, bit-sliced, k*vmax halo; agent: k steps per launch */
 #define NASCH_RNG_KEYED      0u /* rule 3 draws R(seed, replica, t, x), see above */
 #define NASCH_RNG_STREAM     1u /* agent form only: the paper's one shared stream, see below */
+#define NASCH_BOUNDARY_RING  0u /* the circular road (periodic boundary)                    */
+#define NASCH_BOUNDARY_OPEN  1u /* grid form only: an open road with entry and exit, below   */
 
 typedef struct nasch_sim nasch_sim;
 
@@ -95,13 +97,38 @@ typedef struct {
     uint32_t use_graph;/* 1: replay nasch_step_n launch sequences from a captured hipGraph */
     uint32_t rng;      /* NASCH_RNG_KEYED (default) or NASCH_RNG_STREAM (agent form only)   */
     void*    stream;   /* hipStream_t to run on; NULL = a stream owned by the handle        */
+    uint32_t boundary; /* NASCH_BOUNDARY_RING (default) or NASCH_BOUNDARY_OPEN              */
+    uint32_t reserved; /* must be 0                                                         */
+    double   alpha;    /* open road: entry probability per step, 0 <= alpha <= 1            */
+    double   beta;     /* open road: exit probability per step, 0 <= beta <= 1             */
 } nasch_opts;
 
 /*
+ * NASCH_BOUNDARY_OPEN: the boundary-condition variation the paper suggests
+ * (section "Variations"), which it does not specify further; this library's
+ * reading.  Cars drive from cell 0 toward cell L-1 and nothing wraps.  At each
+ * step t one gate draw G = Philox(counter = (0, t, replica, 5)) (same key as R)
+ * decides both ends:
+ *   - entry: if cell 0 is empty at the start of the step and word 0 of G is
+ *     below floor(alpha 2^32), a car with v = 0 is in cell 0 after the step;
+ *   - exit: unless word 1 of G is below floor(beta 2^32), a stopped car sits
+ *     in cell L for the step (rule 2 sees it); otherwise the road ahead of the
+ *     front car is free.  A car whose move ends at or past L leaves the road.
+ * Rules 1-4 are otherwise those of the ring, with the same R(seed, replica,
+ * t, x).  F(t) sums the velocities after rules 1-3 of every car that was on
+ * the road at the start of the step, so a leaving car counts its whole move.
+ * The car count changes; the initial state is the ring's (N cars placed on
+ * [0, L)).  For vmax = 1 this is the totally asymmetric exclusion process with
+ * parallel update (entry alpha, exit beta (1 - p), hop probability 1 - p).
+ * Grid representation only (nasch_init returns NASCH_EINVAL for the agent
+ * form); nasch_restore accepts any number of cars.
+ */
+
+/*
  * NASCH_RNG_STREAM reproduces the paper's own approach to random numbers
- * (Concepts Covered: one sequence shared by all threads, reached by "moving
- * ahead"; Handout "IMPORTANT" box: a multiplicative linear congruential
- * generator): one minstd_rand stream, x <- 48271 x mod (2^31 - 1), seeded
+ * (Concepts Covered: one sequence shared by all threads, each thread jumping
+ * ahead to its own numbers; Handout "IMPORTANT" box: a multiplicative linear
+ * congruential generator): one minstd_rand stream, x <- 48271 x mod (2^31 - 1), seeded
  * with seed mod (2^31 - 1) (1 if that is 0).  Every car draws one number per
  * step in car order: car i (agent index, numbered from the lowest cell at
  * t = 0) at step t takes output number t N + i + 1 and slows iff

@@ -114,6 +114,7 @@ struct GridEngine {
     size_t d_items_cap = 0;
     uint32_t k = 0, q = 0;
     uint32_t launch_vmax = kMixedVmax;  // single specialisation when all rings agree
+    bool launch_open = false;           // the rings are open roads (all or none)
     uint32_t version = 0;               // bumped whenever d_items / geometry change
     // per-launch F(t) partials of every item and step, and the rings that keep a log
     uint32_t* d_partials = nullptr;
@@ -152,12 +153,15 @@ struct GridEngine {
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
             return rings[a].vmax > rings[b].vmax;
         });
-        uint32_t vmin = 0xFF, vmaxx = 0;
+        uint32_t vmin = 0xFF, vmaxx = 0, n_open = 0;
         for (RingDesc& r : rings) {
             kstep_geometry(r.L, r.vmax, kk, qq, &r.own, &r.halo, &r.ntiles);
             vmin = std::min(vmin, r.vmax);
             vmaxx = std::max(vmaxx, r.vmax);
+            n_open += r.open ? 1u : 0u;
         }
+        if (n_open != 0 && (n_open != rings.size() || vmin != vmaxx)) return hipErrorInvalidValue;
+        launch_open = n_open != 0;
         for (uint32_t ri : order) {
             rings[ri].first_item = (uint32_t)items.size();
             for (uint32_t t = 0; t < rings[ri].ntiles; ++t) items.push_back(TileItem{ri, t});
@@ -237,7 +241,7 @@ struct GridEngine {
         const uint32_t n = launches_for(T);
         for (uint32_t i = 0; i < n; ++i) {
             const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
-            hipError_t e = launch_grid_kstep(launch_vmax, q, d_rings, d_items,
+            hipError_t e = launch_grid_kstep(launch_vmax, launch_open, q, d_rings, d_items,
                                              (uint32_t)items.size(), d_partials, ki, d_clk, i * k,
                                              i, s);
             if (e == hipSuccess && n_log_rings)

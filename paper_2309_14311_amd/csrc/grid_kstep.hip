@@ -25,6 +25,16 @@
 // one Philox call, bit-sliced already, so one call serves 32 cells; a lane
 // compares them with the top nibble of thr bit-sliced as well.  Only cars whose
 // top nibble ties (1 in 16) need the per-cell low 28 bits.
+//
+// Open road (OPEN = true).  Segment cell j is road cell own_start - H + j,
+// which may lie before 0 or past L-1; such cells load as empty and words stay
+// aligned to the road's 32-cell blocks.  A segment that reaches past L-1
+// clears those cells at the start of every step (cars there have left) and,
+// when the step's gate keeps the exit closed, puts a stopped car in cell L,
+// which rules 1-2 then see like any car.  A segment that contains cell 0 adds
+// the entering car (v = 0) after rule 4 if the gate lets one in and the cell
+// was empty at the start of the step.  Both branches are uniform over the wave
+// and cost nothing in the other segments.
 #include "launchers.hpp"
 
 namespace nasch {
@@ -190,7 +200,7 @@ struct Thermo<VMAX, VMAX + 1> {
 // One wave advances one tile item by up to k steps.  F(t) of a ring with a
 // flux log goes to partials[s * n_items + item] (summed per ring and step by
 // the fold kernel); flux_acc gets one atomic per wave.
-template <int VMAX, int Q>
+template <int VMAX, int Q, bool OPEN>
 __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it, uint32_t item,
                                            uint32_t n_items, uint32_t* __restrict__ partials,
                                            uint32_t lane, uint32_t k,
@@ -210,24 +220,65 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     const uint32_t H = R.halo;
     const uint32_t seg_len = own_len + 2u * H;
     const uint32_t s0 = (own_start + L - (H % L)) % L;  // ring cell of segment cell 0
+    const int64_t base = (int64_t)own_start - (int64_t)H;  // open road: cell of segment cell 0
+    // open road: does the segment hold cell 0 / cells at or past L (wave-uniform)
+    const bool edge_l = OPEN && base <= 0;
+    const bool edge_r = OPEN && base + (int64_t)seg_len > (int64_t)L;
 
     uint32_t T[Q][VMAX + 1];
     uint32_t xw[Q];       // ring cell of each word's first cell
     bool aligned[Q];      // word is one aligned rule-3 block
     uint32_t own[Q];      // owned cells of each word
+    uint32_t keep[Q];     // open road: cells before L
+    uint32_t obst[Q];     // open road: cell L
+    uint32_t inj[Q];      // open road: cell 0
 
     // ---- load: bytes -> bit planes
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const uint32_t j0 = 32u * (lane * Q + q);
-        const uint32_t x0 = (uint32_t)(((uint64_t)s0 + j0) % L);
+        const int64_t p0 = base + j0;   // open road: cell of the word's first cell
+        uint32_t x0;
+        if constexpr (OPEN) {
+            // words before cell 0 hold no car; their draws are never used
+            x0 = p0 < 0 ? 0u : (uint32_t)p0;
+            aligned[q] = true;
+            keep[q] = p0 >= (int64_t)L ? 0u
+                      : (p0 + 32 <= (int64_t)L ? 0xFFFFFFFFu : (1u << (uint32_t)(L - p0)) - 1u);
+            obst[q] = (p0 <= (int64_t)L && (int64_t)L < p0 + 32) ? 1u << (uint32_t)(L - p0) : 0u;
+            inj[q] = p0 == 0 ? 1u : 0u;
+        } else {
+            x0 = (uint32_t)(((uint64_t)s0 + j0) % L);
+            aligned[q] = ((x0 & 31u) == 0u) && (x0 + 32u <= L);
+            keep[q] = obst[q] = inj[q] = 0u;
+        }
         xw[q] = x0;
-        aligned[q] = ((x0 & 31u) == 0u) && (x0 + 32u <= L);
         const uint32_t lo = max(H, j0), hi = min(H + own_len, j0 + 32u);
         own[q] = lo < hi ? bit_range(lo - j0, hi - j0) : 0u;
 
         uint32_t by[8];
-        if (j0 + 32u <= seg_len && (x0 & 15u) == 0u && x0 + 32u <= L) {
+        if constexpr (OPEN) {
+            if (j0 + 32u <= seg_len && p0 >= 0 && p0 + 32 <= (int64_t)L) {
+                const uint4* p = reinterpret_cast<const uint4*>(src + p0);
+                const uint4 a = p[0], b = p[1];
+                by[0] = a.x; by[1] = a.y; by[2] = a.z; by[3] = a.w;
+                by[4] = b.x; by[5] = b.y; by[6] = b.z; by[7] = b.w;
+            } else {
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    uint32_t w = 0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const uint32_t jj = j0 + (uint32_t)(4 * d + e);
+                        const int64_t pos = p0 + (4 * d + e);
+                        uint32_t val = kEmpty;
+                        if (jj < seg_len && pos >= 0 && pos < (int64_t)L) val = src[pos];
+                        w |= val << (8 * e);
+                    }
+                    by[d] = w;
+                }
+            }
+        } else if (j0 + 32u <= seg_len && (x0 & 15u) == 0u && x0 + 32u <= L) {
             const uint4* p = reinterpret_cast<const uint4*>(src + x0);
             const uint4 a = p[0], b = p[1];
             by[0] = a.x; by[1] = a.y; by[2] = a.z; by[3] = a.w;
@@ -270,6 +321,24 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     for (uint32_t s = 0; s < nsteps; ++s) {
         const uint32_t t = t0 + s;
         uint32_t fl = 0;
+        bool enter = false;
+        uint32_t empty0[Q];   // open road: cell 0, if it is empty at the start of the step
+        if constexpr (OPEN) {
+            if (edge_l || edge_r) {
+                bool exit_open;
+                gate_draw(t, sp, R.thr_in, R.thr_out, enter, exit_open);
+                if (edge_r) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+#pragma unroll
+                        for (int m = 0; m <= VMAX; ++m) T[q][m] &= keep[q];
+                        if (!exit_open) T[q][0] |= obst[q];   // stopped car, v = 0
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) empty0[q] = inj[q] & ~T[q][0];
+        }
         if constexpr (VMAX > 0) {
             const uint32_t occ_next = from_next_lane(T[0][0]);
             uint32_t T2[Q][VMAX + 2];
@@ -325,6 +394,12 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                 T[q][0] = accm | Eq[q][0];
             }
         }
+        if constexpr (OPEN) {
+            if (edge_l && enter) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) T[q][0] |= empty0[q];   // entering car, v = 0
+            }
+        }
         if (log) {
             const uint32_t total = wave_total(fl);
             if (lane == 0u) partials[(size_t)s * n_items + item] = total;
@@ -373,8 +448,8 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     }
 }
 
-// All items of a launch share vmax: one specialisation.
-template <int VMAX, int Q>
+// All items of a launch share vmax (and the boundary): one specialisation.
+template <int VMAX, int Q, bool OPEN>
 __global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restrict__ rings,
                                                          const TileItem* __restrict__ items,
                                                          uint32_t n_items, uint32_t* partials,
@@ -386,8 +461,8 @@ __global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restr
     const uint32_t wave = blockIdx.x * 4u + wib;
     if (wave >= n_items) return;
     const TileItem it = items[wave];
-    kstep_tile<VMAX, Q>(rings[it.ring], it, wave, n_items, partials, threadIdx.x & 63u, k, clk,
-                        s_off, launch_idx, s_queue[wib], s_res[wib]);
+    kstep_tile<VMAX, Q, OPEN>(rings[it.ring], it, wave, n_items, partials, threadIdx.x & 63u, k,
+                              clk, s_off, launch_idx, s_queue[wib], s_res[wib]);
 }
 
 // Items of different vmax in one launch: the branch on the ring's vmax is
@@ -411,28 +486,32 @@ __global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* _
     uint32_t* queue = s_queue[wib];
     uint8_t* res = s_res[wib];
     switch (R.vmax) {
-        case 0: kstep_tile<0, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 1: kstep_tile<1, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 2: kstep_tile<2, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 3: kstep_tile<3, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 4: kstep_tile<4, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 5: kstep_tile<5, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 6: kstep_tile<6, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 7: kstep_tile<7, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 8: kstep_tile<8, Q>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 0: kstep_tile<0, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 1: kstep_tile<1, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 2: kstep_tile<2, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 3: kstep_tile<3, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 4: kstep_tile<4, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 5: kstep_tile<5, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 6: kstep_tile<6, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 7: kstep_tile<7, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 8: kstep_tile<8, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
         default: break;
     }
 }
 
 namespace {
 template <int Q>
-hipError_t launch_q(uint32_t vmax, dim3 grid, hipStream_t s, const RingDesc* rings,
+hipError_t launch_q(uint32_t vmax, bool open, dim3 grid, hipStream_t s, const RingDesc* rings,
                     const TileItem* items, uint32_t n_items, uint32_t* partials, uint32_t k,
                     const Clock* clk, uint32_t s_off, uint32_t launch_idx) {
 #define NASCH_KSTEP_CASE(V)                                                                      \
     case V:                                                                                      \
-        NASCH_LAUNCH((grid_kstep_kernel<V, Q>), grid, dim3(256), 0, s, rings, items,      \
-                           n_items, partials, k, clk, s_off, launch_idx);                        \
+        if (open)                                                                                \
+            NASCH_LAUNCH((grid_kstep_kernel<V, Q, true>), grid, dim3(256), 0, s, rings, items,   \
+                         n_items, partials, k, clk, s_off, launch_idx);                          \
+        else                                                                                     \
+            NASCH_LAUNCH((grid_kstep_kernel<V, Q, false>), grid, dim3(256), 0, s, rings, items,  \
+                         n_items, partials, k, clk, s_off, launch_idx);                          \
         break;
     switch (vmax) {
         NASCH_KSTEP_CASE(0)
@@ -445,6 +524,7 @@ hipError_t launch_q(uint32_t vmax, dim3 grid, hipStream_t s, const RingDesc* rin
         NASCH_KSTEP_CASE(7)
         NASCH_KSTEP_CASE(8)
         case kMixedVmax:
+            if (open) return hipErrorInvalidValue;   // open roads are single-ring launches
             NASCH_LAUNCH((grid_kstep_mixed_kernel<Q>), grid, dim3(256), 0, s, rings, items,
                                n_items, partials, k, clk, s_off, launch_idx);
             break;
@@ -456,16 +536,16 @@ hipError_t launch_q(uint32_t vmax, dim3 grid, hipStream_t s, const RingDesc* rin
 }
 }  // namespace
 
-hipError_t launch_grid_kstep(uint32_t vmax, uint32_t q, const RingDesc* rings,
+hipError_t launch_grid_kstep(uint32_t vmax, bool open, uint32_t q, const RingDesc* rings,
                              const TileItem* items, uint32_t n_items, uint32_t* partials,
                              uint32_t k, const Clock* clk, uint32_t s_off, uint32_t launch_idx,
                              hipStream_t s) {
     if (n_items == 0) return hipSuccess;
     const dim3 grid((n_items + 3u) / 4u);
     switch (q) {
-        case 1: return launch_q<1>(vmax, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
-        case 2: return launch_q<2>(vmax, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
-        case 4: return launch_q<4>(vmax, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
+        case 1: return launch_q<1>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
+        case 2: return launch_q<2>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
+        case 4: return launch_q<4>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         default: return hipErrorInvalidValue;
     }
 }

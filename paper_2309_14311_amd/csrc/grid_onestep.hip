@@ -9,6 +9,10 @@
 // copy of the tile.  Cars up to vmax cells left of the tile can land inside
 // it; lanes 0..vmax-1 recompute those.  The tile is then written back with
 // 16-byte stores.  F(t) counts owned cars only.
+//
+// Open road: cells outside [0, L) load as empty, except cell L, which holds a
+// stopped car when the step's gate keeps the exit closed; cars moving past
+// L-1 are not written (they leave); the tile of cell 0 adds the entering car.
 #include "launchers.hpp"
 
 namespace nasch {
@@ -63,6 +67,10 @@ __global__ __launch_bounds__(kThreads) void grid_onestep_kernel(const RingDesc* 
     const uint32_t start = blockIdx.x * kTile;
     const uint32_t len = min(kTile, L - start);
     const uint32_t tid = threadIdx.x;
+    const bool open = R.open != 0;
+    bool enter = false, exit_open = true;
+    if (open && (start == 0 || (uint64_t)start + len + kHalo > L))   // uniform per block
+        gate_draw(t, sp, R.thr_in, R.thr_out, enter, exit_open);
 
     // ---- load the tile and its halos (cells start-kHalo .. start+len+kHalo, mod L)
     if (start >= kHalo && (uint64_t)start + kTile + kHalo <= L) {
@@ -74,9 +82,15 @@ __global__ __launch_bounds__(kThreads) void grid_onestep_kernel(const RingDesc* 
             const int64_t c = (int64_t)i - kHalo;
             uint8_t val = (uint8_t)kEmpty;
             if (c < (int64_t)len + kHalo) {
-                int64_t pos = ((int64_t)start + c) % (int64_t)L;
-                if (pos < 0) pos += L;
-                val = src[pos];
+                int64_t pos = (int64_t)start + c;
+                if (open) {
+                    if (pos >= 0 && pos < (int64_t)L) val = src[pos];
+                    else if (pos == (int64_t)L && !exit_open) val = 0;   // closed exit
+                } else {
+                    pos %= (int64_t)L;
+                    if (pos < 0) pos += L;
+                    val = src[pos];
+                }
             }
             s_in[i] = val;
         }
@@ -132,6 +146,8 @@ __global__ __launch_bounds__(kThreads) void grid_onestep_kernel(const RingDesc* 
             if (dstc >= 0 && (uint32_t)dstc < len) s_out[dstc] = (uint8_t)v;
         }
     }
+    // ---- open road: the entering car (no other car can land in cell 0)
+    if (open && start == 0 && tid == 0 && enter && s_in[kHalo] == kEmpty) s_out[0] = 0;
     const uint32_t wsum = wave_total(flux);
     if ((tid & 63u) == 0) s_flux[tid >> 6] = wsum;
     __syncthreads();

@@ -62,9 +62,10 @@ hipError_t launch_grid_onestep(const RingDesc* ring, uint32_t L, uint32_t* parti
 // Cells per wave segment for q words of 32 cells per lane.
 constexpr uint32_t kstep_segment(uint32_t q) { return 64u * 32u * q; }
 // vmax = kMixedVmax launches the kernel that branches on each ring's vmax;
-// otherwise every item's ring must have this vmax.
+// otherwise every item's ring must have this vmax.  open selects the open-road
+// specialisation (every ring open, one vmax).
 constexpr uint32_t kMixedVmax = 0xFFu;
-hipError_t launch_grid_kstep(uint32_t vmax, uint32_t q, const RingDesc* rings,
+hipError_t launch_grid_kstep(uint32_t vmax, bool open, uint32_t q, const RingDesc* rings,
                              const TileItem* items, uint32_t n_items, uint32_t* partials,
                              uint32_t k, const Clock* clk, uint32_t s_off, uint32_t launch_idx,
                              hipStream_t s);

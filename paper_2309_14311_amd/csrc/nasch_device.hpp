@@ -13,6 +13,7 @@ constexpr uint32_t kTagSlowHi = 1u;  // rule 3: top 4 bits of R, one block per 3
 constexpr uint32_t kTagSlowLo = 2u;  // rule 3: low 28 bits of R, one block per cell
 constexpr uint32_t kTagPlace = 3u;   // initial placement (Feistel round function)
 constexpr uint32_t kTagVel0 = 4u;    // initial velocities
+constexpr uint32_t kTagGate = 5u;    // open road: entry and exit gates, one block per step
 
 struct Word4 {
     uint32_t w0, w1, w2, w3;
@@ -80,6 +81,16 @@ __device__ __forceinline__ bool slow_from_hi(uint32_t hi4, uint32_t x, uint32_t 
     const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
     if (lo_thr == 0) return false;
     return slow_lo28(x, t, sp) < lo_thr;
+}
+
+// Open road: the gate draw of step t.  A car enters empty cell 0 iff word 0 is
+// below thr_in = floor(alpha 2^32); the exit is open iff word 1 is below
+// thr_out = floor(beta 2^32) (both thresholds in [0, 2^32]).
+__device__ __forceinline__ void gate_draw(uint32_t t, const SlowParams& sp, uint64_t thr_in,
+                                          uint64_t thr_out, bool& enter, bool& exit_open) {
+    const Word4 g = philox(0u, t, sp.replica, kTagGate, sp.k0, sp.k1);
+    enter = (uint64_t)g.w0 < thr_in;
+    exit_open = (uint64_t)g.w1 < thr_out;
 }
 
 // ---- initial placement --------------------------------------------------------
@@ -150,7 +161,9 @@ __device__ __forceinline__ uint32_t initial_velocity(uint32_t x, uint32_t vmax, 
 // ---- descriptors --------------------------------------------------------------
 // One ring as the temporal-blocked grid kernel sees it.  Tiles own `own` cells
 // each (the last one the remainder); a tile's segment is its owned cells plus
-// `halo` cells on each side, read modulo L.
+// `halo` cells on each side, read modulo L.  With `open` set the road is not a
+// ring: cells outside [0, L) are empty, a car enters cell 0 and the exit at
+// cell L opens by the gate draw of each step (see gate_draw).
 struct RingDesc {
     uint8_t* buf[2];         // ping-pong grids, L bytes each
     unsigned long long* flux_log;  // F(t) at flux_log[t - log_t0] (may be null)
@@ -164,8 +177,9 @@ struct RingDesc {
     uint32_t ntiles;
     uint32_t t_end;          // no step t >= t_end is run (serving); 0xFFFFFFFF = none
     uint32_t first_item;     // index of the ring's first item in the launch
-    uint32_t pad;
+    uint32_t open;           // 1: open road (entry at cell 0, exit after cell L-1)
     SlowParams sp;
+    uint64_t thr_in, thr_out;  // open road: gate thresholds floor(alpha 2^32), floor(beta 2^32)
 };
 
 // Initial placement of one ring: cars [0, N) scattered into g (already EMPTY).

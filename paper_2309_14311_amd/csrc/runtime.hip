@@ -32,6 +32,7 @@ struct nasch_sim {
     uint64_t L = 0, N = 0, seed = 0;
     uint32_t vmax = 0, thr = 0, replica = 0, rep = 0, init_v = 0;
     double p = 0;
+    bool open = false;        // open road (grid form only)
     // tuning
     uint32_t kernel = NASCH_KERNEL_KSTEP, k = kDefaultK, q = kDefaultQ, use_graph = 0;
     // stream and status
@@ -323,12 +324,21 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
         o.rng > NASCH_RNG_STREAM)
         return NASCH_EINVAL;
     if (o.rng == NASCH_RNG_STREAM && o.rep != NASCH_REP_AGENT) return NASCH_EINVAL;
+    if (o.boundary > NASCH_BOUNDARY_OPEN || o.reserved != 0) return NASCH_EINVAL;
+    const bool open = o.boundary == NASCH_BOUNDARY_OPEN;
+    if (open) {
+        // alpha, beta in [0, 1] (NaN fails both comparisons)
+        if (o.rep != NASCH_REP_GRID || !(o.alpha >= 0.0 && o.alpha <= 1.0) ||
+            !(o.beta >= 0.0 && o.beta <= 1.0))
+            return NASCH_EINVAL;
+    }
     std::unique_ptr<nasch_sim> h(new (std::nothrow) nasch_sim());
     if (!h) return NASCH_ENOMEM;
     h->L = L; h->N = N; h->vmax = vmax; h->p = p; h->seed = seed;
     h->thr = threshold_of(p);
     h->replica = o.replica; h->rep = o.rep; h->init_v = o.init_v;
     h->use_graph = o.use_graph;
+    h->open = open;
     if (o.stream) {
         h->stream = (hipStream_t)o.stream;
     } else {
@@ -361,6 +371,12 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
         r.sp = sp;
         r.t_end = 0xFFFFFFFFu;
         r.warmup = ~0ull;
+        if (open) {
+            // gate thresholds floor(alpha 2^32), floor(beta 2^32): exact in binary64
+            r.open = 1u;
+            r.thr_in = (uint64_t)std::floor(std::ldexp(o.alpha, 32));
+            r.thr_out = (uint64_t)std::floor(std::ldexp(o.beta, 32));
+        }
         h->eng.rings.push_back(r);
         if (!h->ok(dev_alloc(&h->d_onestep, 1))) return NASCH_ENOMEM;
         rc = h->ensure_os_partials(onestep_blocks((uint32_t)L));
@@ -537,7 +553,7 @@ int nasch_restore(nasch_sim* h, const uint8_t* grid, uint64_t t) {
         if (grid[i] > h->vmax) return NASCH_EINVAL;
         ++cars;
     }
-    if (cars != h->N) return NASCH_EINVAL;
+    if (!h->open && cars != h->N) return NASCH_EINVAL;   // an open road changes its car count
     if (!h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
     h->parity = 0;
     h->t = t;

@@ -20,6 +20,7 @@ NASCH_ERANGE, NASCH_ESTATE, NASCH_EBUSY, NASCH_ENOTFOUND = -4, -5, -6, -7
 REP = {"grid": 0, "agent": 1}
 KERNEL = {"auto": 0, "onestep": 1, "kstep": 2}
 RNG = {"keyed": 0, "stream": 1}
+BOUNDARY = {"ring": 0, "open": 1}
 EMPTY = 0xFF
 
 u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -33,7 +34,8 @@ U32, U64, I32, DBL, VP = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.
 
 class Opts(ctypes.Structure):
     _fields_ = [("replica", U32), ("rep", U32), ("init_v", U32), ("kernel", U32), ("k", U32),
-                ("q", U32), ("use_graph", U32), ("rng", U32), ("stream", VP)]
+                ("q", U32), ("use_graph", U32), ("rng", U32), ("stream", VP),
+                ("boundary", U32), ("reserved", U32), ("alpha", DBL), ("beta", DBL)]
 
 
 class Info(ctypes.Structure):
@@ -179,11 +181,13 @@ class Sim:
     """One ring (nasch_init ... nasch_free)."""
 
     def __init__(self, L, N, vmax, p, seed, *, replica=0, rep="grid", init_v=0, kernel="auto",
-                 k=0, q=0, use_graph=False, stream=None, rng="keyed"):
+                 k=0, q=0, use_graph=False, stream=None, rng="keyed", boundary="ring",
+                 alpha=0.0, beta=0.0):
         lib = load()
         o = Opts()
         lib.nasch_default_opts(ctypes.byref(o))
         o.replica, o.rep, o.init_v, o.rng = replica, REP[rep], int(init_v), RNG[rng]
+        o.boundary, o.alpha, o.beta = BOUNDARY[boundary], float(alpha), float(beta)
         o.kernel, o.k, o.q, o.use_graph = KERNEL[kernel], k, q, int(bool(use_graph))
         o.stream = _stream_ptr(stream)
         h = VP()
@@ -193,6 +197,7 @@ class Sim:
         self._h = h
         self.L, self.N, self.vmax, self.p, self.seed = L, N, vmax, p, seed
         self.replica, self.rep = replica, rep
+        self.boundary, self.alpha, self.beta = boundary, alpha, beta
 
     def _check(self, rc, where):
         if rc:

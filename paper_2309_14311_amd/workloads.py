@@ -20,6 +20,10 @@ LARGE_RING = dict(L=2**30, N=int(math.floor(0.2 * 2**30)), vmax=5, p=0.13, seed=
 # Agent form: 2^26 cars on 2^28 cells.
 AGENT_RING = dict(L=2**28, N=2**26, vmax=5, p=0.25, seed=1, replica=0, init_v=1, T=1000)
 
+# The large ring's road opened at both ends: entry probability 0.3, exit 0.9.
+OPEN_ROAD = dict(L=2**30, N=int(math.floor(0.2 * 2**30)), vmax=5, p=0.13, seed=1, replica=0,
+                 init_v=1, T=1000, alpha=0.3, beta=0.9)
+
 
 def ensemble(n_replicas: int = 4096, seed: int = 1, T: int = 5000, warmup: int = 1000,
              L_lo_exp: float = 3.0, L_hi_exp: float = 6.0) -> list[dict]:

@@ -79,3 +79,23 @@ def test_strerror_and_missing_library(tmp_path):
             native_mod.load(str(tmp_path / "nope.so"))
     finally:
         native_mod._lib = saved
+
+
+def test_open_road_options_are_checked_before_any_device_call():
+    """nasch_init rejects a bad boundary, an open agent road and gate
+    probabilities outside [0, 1] (NaN included) with NASCH_EINVAL; the checks
+    come before any HIP call, so they run without a GPU."""
+    from paper_2309_14311_amd import native
+    lib = native.load()
+    o = native.Opts()
+    lib.nasch_default_opts(ctypes.byref(o))
+    assert (o.boundary, o.reserved, o.alpha, o.beta) == (0, 0, 0.0, 0.0)
+    nan = float("nan")
+    for boundary, rep, alpha, beta, reserved in [(2, 0, 0.5, 0.5, 0), (1, 1, 0.5, 0.5, 0),
+                                                 (1, 0, 1.5, 0.5, 0), (1, 0, 0.5, -0.1, 0),
+                                                 (1, 0, nan, 0.5, 0), (1, 0, 0.5, nan, 0),
+                                                 (1, 0, 0.5, 0.5, 7)]:
+        o.boundary, o.rep, o.alpha, o.beta, o.reserved = boundary, rep, alpha, beta, reserved
+        h = ctypes.c_void_p(1)
+        assert lib.nasch_init(ctypes.byref(h), 100, 10, 5, 0.1, 1, ctypes.byref(o)) == -1
+        assert not h.value

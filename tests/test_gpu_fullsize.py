@@ -58,6 +58,36 @@ def test_large_ring_kstep_onestep_and_oracle_windows():
     assert np.array_equal(ga, gb)
 
 
+def test_open_road_kstep_onestep_and_oracle_windows():
+    """The 2^30-cell open road: windows at both ends (where cars enter and
+    leave) and inside against the oracle's light cone; k-step (autotuned, as
+    benchmarked) and one-step agree on the whole road and the flux log; the
+    last step's flux covers the final velocities plus at most vmax^2 for the
+    cars that left in it."""
+    cfg = workloads.OPEN_ROAD
+    L, N, T, vmax = cfg["L"], cfg["N"], cfg["T"], cfg["vmax"]
+    kw = dict(init_v=cfg["init_v"], boundary="open", alpha=cfg["alpha"], beta=cfg["beta"])
+    a = Sim(L, N, vmax, cfg["p"], cfg["seed"], use_graph=True, **kw)
+    a.autotune()
+    a.step(T)
+    for s0, w in [(0, 512), (L - 512, 512), (L // 2, 192), (123456789, 192), (L - 6000, 300)]:
+        want = oracle.open_window_from_init(L, N, vmax, cfg["p"], cfg["alpha"], cfg["beta"],
+                                            cfg["seed"], T, s0, w, init_v=cfg["init_v"])
+        np.testing.assert_array_equal(a.snapshot_range(s0, w), want, err_msg=f"window at {s0}")
+    ga, _ = a.snapshot()
+    fa = a.flux(0, T)
+    a.close()
+    b = Sim(L, N, vmax, cfg["p"], cfg["seed"], kernel="onestep", **kw)
+    b.step(T)
+    gb, _ = b.snapshot()
+    np.testing.assert_array_equal(b.flux(0, T), fa)
+    b.close()
+    assert np.array_equal(ga, gb)
+    occ = ga != EMPTY
+    extra = int(fa[-1]) - int(ga[occ].astype(np.int64).sum())
+    assert 0 <= extra <= vmax * vmax
+
+
 def test_agent_ring_equals_grid_and_oracle_windows():
     cfg = workloads.AGENT_RING
     L, N, T = cfg["L"], cfg["N"], cfg["T"]

@@ -1,0 +1,140 @@
+"""GPU parity of the open road (entry at cell 0, exit after cell L-1) against the
+CPU oracle, element by element: every kernel (byte-wise one-step, bit-sliced
+k-step for every (k, q)), tiny and ragged roads, every vmax, the gate
+extremes (alpha, beta in {0, 1}), flux logs, snapshots, split launch
+sequences, graph replay, checkpoint restore, and windows of a 2^30-cell road.
+Integer work: the bar is bit-exact equality."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_14311_amd import NaschError, Sim
+
+pytestmark = pytest.mark.gpu
+EMPTY = 0xFF
+
+
+def _open_sim(L, N, vmax, p, seed, alpha, beta, **kw):
+    return Sim(L, N, vmax, p, seed, rep="grid", boundary="open", alpha=alpha, beta=beta, **kw)
+
+
+def _run_and_compare(L, N, vmax, p, seed, T, alpha, beta, *, kernel="kstep", k=0, q=0,
+                     init_v=1, replica=0, use_graph=False):
+    g0 = oracle.init_grid(L, N, vmax, seed, replica=replica, init_v=init_v)
+    want, want_flux, _, _ = oracle.run_open(g0, vmax, p, alpha, beta, seed, T, replica=replica)
+    s = _open_sim(L, N, vmax, p, seed, alpha, beta, kernel=kernel, k=k, q=q, init_v=init_v,
+                  replica=replica, use_graph=use_graph)
+    try:
+        g, t = s.snapshot()
+        assert t == 0
+        np.testing.assert_array_equal(g, g0)
+        s.step(T)
+        g, t = s.snapshot()
+        assert t == T
+        np.testing.assert_array_equal(g, want)
+        np.testing.assert_array_equal(s.flux(0, T), want_flux)
+    finally:
+        s.close()
+
+
+GATES = [(0.5, 0.5), (1.0, 1.0), (0.0, 0.3), (0.7, 0.0)]
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 5, 31, 32, 33, 63, 64, 100, 2047, 2048, 2049, 5000,
+                               70001])
+def test_tiny_and_ragged_roads(L):
+    for alpha, beta in GATES:
+        for kernel in ("kstep", "onestep"):
+            _run_and_compare(L, L // 3, 5, 0.3, L + 5, 50, alpha, beta, kernel=kernel)
+
+
+@pytest.mark.parametrize("vmax", range(0, 9))
+@pytest.mark.parametrize("kernel", ["onestep", "kstep"])
+def test_every_vmax(vmax, kernel):
+    _run_and_compare(3000, 700, vmax, 0.2, 40 + vmax, 60, 0.6, 0.4, kernel=kernel)
+
+
+@pytest.mark.parametrize("q", [1, 2, 4])
+@pytest.mark.parametrize("k", [1, 2, 7, 16, 32, 50])
+def test_kstep_tilings(k, q):
+    """Several tiles, so tiles whose segments hold cell 0 or cell L sit beside
+    tiles that hold neither."""
+    try:
+        _run_and_compare(20000, 5000, 5, 0.25, 3, 101, 0.4, 0.6, k=k, q=q)
+    except NaschError as e:
+        assert k * 5 > (2048 * q - 32) // 2, e   # only geometries that cannot fit may fail
+
+
+@pytest.mark.parametrize("p", [0.0, 0.13, 0.5, 0.999])
+@pytest.mark.parametrize("alpha,beta", [(0.0, 0.0), (1.0, 0.0), (0.0, 1.0), (1.0, 1.0),
+                                        (0.25, 0.75)])
+def test_gate_extremes_and_probabilities(p, alpha, beta):
+    for kernel in ("kstep", "onestep"):
+        _run_and_compare(4099, 1000, 4, p, 17, 80, alpha, beta, kernel=kernel)
+
+
+def test_filling_and_draining_roads():
+    """A closed exit fills the road; no entry drains it (long runs, k-step)."""
+    L, N = 3000, 900
+    for alpha, beta, T in ((0.8, 0.0, 4000), (0.0, 1.0, 1500)):
+        _run_and_compare(L, N, 5, 0.3, 8, T, alpha, beta)
+
+
+def test_split_steps_equal_one_call_and_graph_replay():
+    L, N, vmax, p, seed, alpha, beta = 70000, 14000, 5, 0.13, 21, 0.35, 0.8
+    g0 = oracle.init_grid(L, N, vmax, seed, init_v=1)
+    want, want_flux, _, _ = oracle.run_open(g0, vmax, p, alpha, beta, seed, 230)
+    for use_graph in (False, True):
+        s = _open_sim(L, N, vmax, p, seed, alpha, beta, init_v=1, use_graph=use_graph)
+        try:
+            for T in (37, 64, 1, 64, 64):
+                s.step(T)
+            g, t = s.snapshot()
+            assert t == 230
+            np.testing.assert_array_equal(g, want)
+            np.testing.assert_array_equal(s.flux(0, 230), want_flux)
+        finally:
+            s.close()
+
+
+def test_checkpoint_restore_resumes_exactly():
+    """Restore accepts any car count on an open road and continues the
+    uninterrupted run bit for bit."""
+    L, N, vmax, p, seed, alpha, beta = 9000, 3000, 5, 0.25, 5, 0.6, 0.3
+    g0 = oracle.init_grid(L, N, vmax, seed, init_v=1)
+    mid, _, _, _ = oracle.run_open(g0, vmax, p, alpha, beta, seed, 70)
+    want, want_flux, _, _ = oracle.run_open(mid, vmax, p, alpha, beta, seed, 90, t0=70)
+    assert (mid != EMPTY).sum() != N
+    s = _open_sim(L, N, vmax, p, seed, alpha, beta, init_v=1)
+    try:
+        s.restore(mid, 70)
+        s.step(90)
+        g, t = s.snapshot()
+        assert t == 160
+        np.testing.assert_array_equal(g, want)
+        np.testing.assert_array_equal(s.flux(70, 90), want_flux)
+    finally:
+        s.close()
+
+
+def test_autotune_keeps_results():
+    L, N, vmax, p, seed, alpha, beta = 300000, 60000, 5, 0.13, 2, 0.3, 0.9
+    g0 = oracle.init_grid(L, N, vmax, seed, init_v=1)
+    want, want_flux, _, _ = oracle.run_open(g0, vmax, p, alpha, beta, seed, 150)
+    s = _open_sim(L, N, vmax, p, seed, alpha, beta, init_v=1)
+    try:
+        s.autotune()
+        s.step(150)
+        g, _ = s.snapshot()
+        np.testing.assert_array_equal(g, want)
+        np.testing.assert_array_equal(s.flux(0, 150), want_flux)
+    finally:
+        s.close()
+
+
+def test_invalid_open_road_options():
+    with pytest.raises(NaschError):
+        Sim(100, 10, 5, 0.1, 1, rep="agent", boundary="open", alpha=0.5, beta=0.5)
+    for alpha, beta in ((1.5, 0.5), (0.5, -0.1), (float("nan"), 0.5), (0.5, float("inf"))):
+        with pytest.raises(NaschError):
+            _open_sim(100, 10, 5, 0.1, 1, alpha, beta)
