@@ -80,36 +80,85 @@ __device__ __forceinline__ Word4 planes_unaligned(uint32_t x0, uint32_t t, uint3
     return r;
 }
 
+// The bit-sliced nibble (w0 w1 w2 w3), w0 most significant, compared with the
+// constant TH: lt = nibble < TH, eq = nibble == TH.  With TH known the chain
+// folds into a few three-input bitwise operations.
+template <int TH>
+__device__ __forceinline__ void nibble_cmp(const Word4& w, uint32_t& lt, uint32_t& eq) {
+    const uint32_t P[4] = {w.w0, w.w1, w.w2, w.w3};
+    uint32_t l = 0u, e = 0xFFFFFFFFu;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        if ((TH >> (3 - b)) & 1) {
+            l |= e & ~P[b];
+            e &= P[b];
+        } else {
+            e &= ~P[b];
+        }
+    }
+    lt = l;
+    eq = e;
+}
+
 // Rule 3, first stage, for the moving cars of one word (ring cells x0 .. x0+31,
 // mod L): S = cars whose top nibble of R is below thr's (slow), U = cars whose
-// top nibble ties with thr's (decided by the low 28 bits).
+// top nibble ties with thr's (decided by the low 28 bits).  The comparison is
+// specialised on thr's top nibble, which is uniform over the wave.
 __device__ __forceinline__ void slow_hi(uint32_t moving, uint32_t x0, bool aligned, uint32_t t,
                                         uint32_t L, const SlowParams& sp, uint32_t& S,
                                         uint32_t& U) {
     const Word4 hp = aligned ? slow_hi_planes(x0 >> 5, t, sp) : planes_unaligned(x0, t, L, sp);
-    const uint32_t th = sp.thr >> 28;
-    uint32_t lt = 0u, eq = 0xFFFFFFFFu;
-    // compare the nibble (w0 w1 w2 w3) with th, most significant plane first
-    if (th & 8u) { lt |= eq & ~hp.w0; eq &= hp.w0; } else { eq &= ~hp.w0; }
-    if (th & 4u) { lt |= eq & ~hp.w1; eq &= hp.w1; } else { eq &= ~hp.w1; }
-    if (th & 2u) { lt |= eq & ~hp.w2; eq &= hp.w2; } else { eq &= ~hp.w2; }
-    if (th & 1u) { lt |= eq & ~hp.w3; eq &= hp.w3; } else { eq &= ~hp.w3; }
+    uint32_t lt = 0u, eq = 0u;
+    switch (sp.thr >> 28) {
+        case 0: nibble_cmp<0>(hp, lt, eq); break;
+        case 1: nibble_cmp<1>(hp, lt, eq); break;
+        case 2: nibble_cmp<2>(hp, lt, eq); break;
+        case 3: nibble_cmp<3>(hp, lt, eq); break;
+        case 4: nibble_cmp<4>(hp, lt, eq); break;
+        case 5: nibble_cmp<5>(hp, lt, eq); break;
+        case 6: nibble_cmp<6>(hp, lt, eq); break;
+        case 7: nibble_cmp<7>(hp, lt, eq); break;
+        case 8: nibble_cmp<8>(hp, lt, eq); break;
+        case 9: nibble_cmp<9>(hp, lt, eq); break;
+        case 10: nibble_cmp<10>(hp, lt, eq); break;
+        case 11: nibble_cmp<11>(hp, lt, eq); break;
+        case 12: nibble_cmp<12>(hp, lt, eq); break;
+        case 13: nibble_cmp<13>(hp, lt, eq); break;
+        case 14: nibble_cmp<14>(hp, lt, eq); break;
+        default: nibble_cmp<15>(hp, lt, eq); break;
+    }
     S = moving & lt;
     U = moving & eq;
 }
 
 // Rule 3, second stage, shared by the whole wave.  The tied cars of every lane
 // (bits of U, word by word, in order) are numbered with a wave prefix sum and
-// their ring cells queued in LDS; the wave then draws their low 28 bits 64 at
-// a time, so a lane with many tied cars does not hold the others back.  Cars
-// numbered beyond the queue's capacity are drawn by their own lane.
+// queued in LDS as (word, bit) codes; the wave then draws their low 28 bits 64
+// at a time, reading the word's first ring cell from a table written once per
+// launch, and ORs each slow car into an LDS mask of its word.  Every lane then
+// takes its words' masks (and clears them for the next step): one LDS read per
+// word instead of a loop over the lane's tied cars.  Cars numbered beyond the
+// queue's capacity are drawn by their own lane.
 constexpr uint32_t kRefineCap = 256;
+
+template <int Q>
+struct RefineLds {
+    uint32_t code[kRefineCap];   // (lane Q + q) << 5 | bit of each queued car
+    uint32_t xw[64 * Q];         // ring cell of the first cell of every word
+    uint32_t slow[64 * Q];       // slow cars found by the draws, per word
+};
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int Q>
 __device__ __forceinline__ void slow_lo_wave(uint32_t (&S)[Q], const uint32_t (&U)[Q],
                                              const uint32_t (&xw)[Q], uint32_t L, uint32_t t,
-                                             const SlowParams& sp, uint32_t* queue,
-                                             uint8_t* res, uint32_t lane) {
+                                             const SlowParams& sp, RefineLds<Q>& lds,
+                                             uint32_t lane) {
     const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
     uint32_t cnt = 0;
 #pragma unroll
@@ -122,42 +171,33 @@ __device__ __forceinline__ void slow_lo_wave(uint32_t (&S)[Q], const uint32_t (&
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         uint32_t u = U[q];
+        const uint32_t wcode = (lane * Q + q) << 5;
         while (u) {
             const uint32_t b = __builtin_ctz(u);
             u &= u - 1u;
             if (idx < kRefineCap) {
+                lds.code[idx] = wcode | b;
+            } else {
                 uint32_t x = xw[q] + b;
                 if (x >= L) x %= L;
-                queue[idx] = x;
+                if (slow_lo28(x, t, sp) < lo_thr) S[q] |= 1u << b;
             }
             ++idx;
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (uint32_t p = lane; p < nq; p += 64u) res[p] = slow_lo28(queue[p], t, sp) < lo_thr ? 1 : 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    idx = incl - cnt;
+    wave_sync_lds();
+    for (uint32_t p = lane; p < nq; p += 64u) {
+        const uint32_t c = lds.code[p];
+        const uint32_t w = c >> 5, b = c & 31u;
+        uint32_t x = lds.xw[w] + b;
+        if (x >= L) x %= L;   // a word across the end of a short ring
+        if (slow_lo28(x, t, sp) < lo_thr) atomicOr(&lds.slow[w], 1u << b);
+    }
+    wave_sync_lds();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        uint32_t u = U[q];
-        while (u) {
-            const uint32_t b = __builtin_ctz(u);
-            u &= u - 1u;
-            bool slow;
-            if (idx < kRefineCap) {
-                slow = res[idx] != 0;
-            } else {
-                uint32_t x = xw[q] + b;
-                if (x >= L) x %= L;
-                slow = slow_lo28(x, t, sp) < lo_thr;
-            }
-            if (slow) S[q] |= 1u << b;
-            ++idx;
-        }
+        S[q] |= lds.slow[lane * Q + q];
+        lds.slow[lane * Q + q] = 0u;
     }
     // the queue is rewritten at the next step only after every lane has read it
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -205,7 +245,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                                            uint32_t n_items, uint32_t* __restrict__ partials,
                                            uint32_t lane, uint32_t k,
                                            const Clock* __restrict__ clk, uint32_t s_off,
-                                           uint32_t launch_idx, uint32_t* queue, uint8_t* res) {
+                                           uint32_t launch_idx, RefineLds<Q>& rl) {
     const uint32_t L = R.L;
     const SlowParams sp = R.sp;
     const uint32_t t0 = clk->t + R.t + s_off;
@@ -315,6 +355,14 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
         Thermo<VMAX, 1>::fill(T[q], occ, P0, P1, P2, P3);
     }
 
+    // rule-3 tables of this wave
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        rl.xw[lane * Q + q] = xw[q];
+        rl.slow[lane * Q + q] = 0u;
+    }
+    wave_sync_lds();
+
     // ---- k steps
     uint32_t acc = 0u;
     const bool log = R.flux_log != nullptr;
@@ -361,7 +409,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                     if (moving) slow_hi(moving, xw[q], aligned[q], t, L, sp, S[q], U[q]);  // rule 3
                 }
             }
-            if ((sp.thr & 0x0FFFFFFFu) != 0u) slow_lo_wave<Q>(S, U, xw, L, t, sp, queue, res, lane);
+            if ((sp.thr & 0x0FFFFFFFu) != 0u) slow_lo_wave<Q>(S, U, xw, L, t, sp, rl, lane);
             uint32_t Eq[Q][VMAX + 1];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
@@ -371,7 +419,10 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                 for (int m = 1; m <= VMAX; ++m)
                     T3[m] = (T2[q][m] & ~S[q]) | (T2[q][m + 1] & S[q]);
                 T3[VMAX + 1] = 0u;
-                if (own[q]) {
+                if (own[q] == 0xFFFFFFFFu) {
+#pragma unroll
+                    for (int m = 1; m <= VMAX; ++m) fl += __popc(T3[m]);
+                } else if (own[q]) {
 #pragma unroll
                     for (int m = 1; m <= VMAX; ++m) fl += __popc(T3[m] & own[q]);
                 }
@@ -455,14 +506,13 @@ __global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restr
                                                          uint32_t n_items, uint32_t* partials,
                                                          uint32_t k, const Clock* __restrict__ clk,
                                                          uint32_t s_off, uint32_t launch_idx) {
-    __shared__ uint32_t s_queue[4][kRefineCap];
-    __shared__ uint8_t s_res[4][kRefineCap];
+    __shared__ RefineLds<Q> s_ref[4];
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t wave = blockIdx.x * 4u + wib;
     if (wave >= n_items) return;
     const TileItem it = items[wave];
     kstep_tile<VMAX, Q, OPEN>(rings[it.ring], it, wave, n_items, partials, threadIdx.x & 63u, k,
-                              clk, s_off, launch_idx, s_queue[wib], s_res[wib]);
+                              clk, s_off, launch_idx, s_ref[wib]);
 }
 
 // Items of different vmax in one launch: the branch on the ring's vmax is
@@ -475,26 +525,24 @@ __global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* _
                                                                const Clock* __restrict__ clk,
                                                                uint32_t s_off,
                                                                uint32_t launch_idx) {
-    __shared__ uint32_t s_queue[4][kRefineCap];
-    __shared__ uint8_t s_res[4][kRefineCap];
+    __shared__ RefineLds<Q> s_ref[4];
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t wave = blockIdx.x * 4u + wib;
     if (wave >= n_items) return;
     const TileItem it = items[wave];
     const RingDesc& R = rings[it.ring];
     const uint32_t lane = threadIdx.x & 63u;
-    uint32_t* queue = s_queue[wib];
-    uint8_t* res = s_res[wib];
+    RefineLds<Q>& rl = s_ref[wib];
     switch (R.vmax) {
-        case 0: kstep_tile<0, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 1: kstep_tile<1, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 2: kstep_tile<2, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 3: kstep_tile<3, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 4: kstep_tile<4, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 5: kstep_tile<5, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 6: kstep_tile<6, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 7: kstep_tile<7, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
-        case 8: kstep_tile<8, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, queue, res); break;
+        case 0: kstep_tile<0, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 1: kstep_tile<1, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 2: kstep_tile<2, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 3: kstep_tile<3, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 4: kstep_tile<4, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 5: kstep_tile<5, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 6: kstep_tile<6, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 7: kstep_tile<7, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 8: kstep_tile<8, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
         default: break;
     }
 }

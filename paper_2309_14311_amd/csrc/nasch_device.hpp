@@ -260,13 +260,14 @@ struct AgentDesc {
 };
 
 // ---- cross-lane helpers (gfx9 DPP) ----------------------------------------------
-// Lane i receives lane i+1's value; lane 63 receives 0.
+// Lane i receives lane i+1's value; lane 63 receives 0 (bound_ctrl writes 0
+// where the source lane does not exist, so no old value has to be set up).
 __device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
 }
 // Lane i receives lane i-1's value; lane 0 receives 0.
 __device__ __forceinline__ uint32_t from_prev_lane(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
 }
 // Inclusive prefix sum over the lanes of a wave (all lanes active): DPP row
 // shifts 1, 2, 4, 8 scan each row of 16 lanes, then the row broadcasts of
