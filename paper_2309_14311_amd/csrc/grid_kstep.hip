@@ -100,35 +100,41 @@ __device__ __forceinline__ void nibble_cmp(const Word4& w, uint32_t& lt, uint32_
     eq = e;
 }
 
-// Rule 3, first stage, for the moving cars of one word (ring cells x0 .. x0+31,
-// mod L): S = cars whose top nibble of R is below thr's (slow), U = cars whose
-// top nibble ties with thr's (decided by the low 28 bits).  The comparison is
-// specialised on thr's top nibble, which is uniform over the wave.
-__device__ __forceinline__ void slow_hi(uint32_t moving, uint32_t x0, bool aligned, uint32_t t,
-                                        uint32_t L, const SlowParams& sp, uint32_t& S,
-                                        uint32_t& U) {
-    const Word4 hp = aligned ? slow_hi_planes(x0 >> 5, t, sp) : planes_unaligned(x0, t, L, sp);
-    uint32_t lt = 0u, eq = 0u;
+// Rule 3, first stage, for the moving cars of the lane's Q words (word q covers
+// ring cells xw[q] .. xw[q]+31, mod L): S = cars whose top nibble of R is below
+// thr's (slow), U = cars whose top nibble ties with thr's (decided by the low
+// 28 bits).  The Q block draws are independent, so their Philox chains
+// interleave; the comparison is specialised on thr's top nibble, which is
+// uniform over the wave.
+template <int Q>
+__device__ __forceinline__ void slow_hi(const uint32_t (&moving)[Q], const uint32_t (&xw)[Q],
+                                        const bool (&aligned)[Q], uint32_t t, uint32_t L,
+                                        const SlowParams& sp, uint32_t (&S)[Q],
+                                        uint32_t (&U)[Q]) {
+    Word4 hp[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        hp[q] = aligned[q] ? slow_hi_planes(xw[q] >> 5, t, sp) : planes_unaligned(xw[q], t, L, sp);
+    uint32_t lt[Q], eq[Q];
+#define NASCH_NIBBLE_CASE(TH)                                             \
+    case TH:                                                              \
+        for (int q = 0; q < Q; ++q) nibble_cmp<TH>(hp[q], lt[q], eq[q]); \
+        break;
     switch (sp.thr >> 28) {
-        case 0: nibble_cmp<0>(hp, lt, eq); break;
-        case 1: nibble_cmp<1>(hp, lt, eq); break;
-        case 2: nibble_cmp<2>(hp, lt, eq); break;
-        case 3: nibble_cmp<3>(hp, lt, eq); break;
-        case 4: nibble_cmp<4>(hp, lt, eq); break;
-        case 5: nibble_cmp<5>(hp, lt, eq); break;
-        case 6: nibble_cmp<6>(hp, lt, eq); break;
-        case 7: nibble_cmp<7>(hp, lt, eq); break;
-        case 8: nibble_cmp<8>(hp, lt, eq); break;
-        case 9: nibble_cmp<9>(hp, lt, eq); break;
-        case 10: nibble_cmp<10>(hp, lt, eq); break;
-        case 11: nibble_cmp<11>(hp, lt, eq); break;
-        case 12: nibble_cmp<12>(hp, lt, eq); break;
-        case 13: nibble_cmp<13>(hp, lt, eq); break;
-        case 14: nibble_cmp<14>(hp, lt, eq); break;
-        default: nibble_cmp<15>(hp, lt, eq); break;
+        NASCH_NIBBLE_CASE(0) NASCH_NIBBLE_CASE(1) NASCH_NIBBLE_CASE(2) NASCH_NIBBLE_CASE(3)
+        NASCH_NIBBLE_CASE(4) NASCH_NIBBLE_CASE(5) NASCH_NIBBLE_CASE(6) NASCH_NIBBLE_CASE(7)
+        NASCH_NIBBLE_CASE(8) NASCH_NIBBLE_CASE(9) NASCH_NIBBLE_CASE(10) NASCH_NIBBLE_CASE(11)
+        NASCH_NIBBLE_CASE(12) NASCH_NIBBLE_CASE(13) NASCH_NIBBLE_CASE(14)
+        default:
+            for (int q = 0; q < Q; ++q) nibble_cmp<15>(hp[q], lt[q], eq[q]);
+            break;
     }
-    S = moving & lt;
-    U = moving & eq;
+#undef NASCH_NIBBLE_CASE
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        S[q] = moving[q] & lt[q];
+        U[q] = moving[q] & eq[q];
+    }
 }
 
 // Rule 3, second stage, shared by the whole wave.  The tied cars of every lane
@@ -366,6 +372,9 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     // ---- k steps
     uint32_t acc = 0u;
     const bool log = R.flux_log != nullptr;
+    // steps of this launch before the warm-up ends (their flux is not summed)
+    const uint32_t s_warm =
+        R.warmup > (uint64_t)t0 ? (uint32_t)min<uint64_t>(R.warmup - t0, nsteps) : 0u;
     for (uint32_t s = 0; s < nsteps; ++s) {
         const uint32_t t = t0 + s;
         uint32_t fl = 0;
@@ -390,7 +399,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
         if constexpr (VMAX > 0) {
             const uint32_t occ_next = from_next_lane(T[0][0]);
             uint32_t T2[Q][VMAX + 2];
-            uint32_t S[Q], U[Q];
+            uint32_t S[Q], U[Q], moving[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const uint32_t occ = T[q][0];
@@ -402,13 +411,11 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                     T2[q][g] = T[q][g - 1] & ~A;                    // rules 1 and 2
                 }
                 T2[q][VMAX + 1] = 0u;
+                moving[q] = T2[q][1];
                 S[q] = 0u;
                 U[q] = 0u;
-                if (sp.thr != 0u) {
-                    const uint32_t moving = T2[q][1];
-                    if (moving) slow_hi(moving, xw[q], aligned[q], t, L, sp, S[q], U[q]);  // rule 3
-                }
             }
+            if (sp.thr != 0u) slow_hi<Q>(moving, xw, aligned, t, L, sp, S, U);   // rule 3
             if ((sp.thr & 0x0FFFFFFFu) != 0u) slow_lo_wave<Q>(S, U, xw, L, t, sp, rl, lane);
             uint32_t Eq[Q][VMAX + 1];
 #pragma unroll
@@ -455,7 +462,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
             const uint32_t total = wave_total(fl);
             if (lane == 0u) partials[(size_t)s * n_items + item] = total;
         }
-        if ((uint64_t)t >= R.warmup) acc += fl;
+        acc += s >= s_warm ? fl : 0u;
     }
     if (R.flux_acc) {
         const uint32_t total = wave_total(acc);

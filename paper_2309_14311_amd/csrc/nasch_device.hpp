@@ -34,7 +34,10 @@ __device__ __forceinline__ Word4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     for (int r = 0; r < 10; ++r) {
         const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = xor3((uint32_t)(m1 >> 32), c1, k0);
+        // in round 0, n0 depends on counter words 1-2 and the key only, which
+        // are uniform at every call site: plain XORs let it stay scalar
+        const uint32_t n0 = r == 0 ? ((uint32_t)(m1 >> 32) ^ c1) ^ k0
+                                   : xor3((uint32_t)(m1 >> 32), c1, k0);
         const uint32_t n2 = xor3((uint32_t)(m0 >> 32), c3, k1);
         c1 = (uint32_t)m1;
         c3 = (uint32_t)m0;
