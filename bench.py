@@ -56,9 +56,10 @@ def _traffic(k, q, launch_cell_updates):
         return None
     if rec.get("kernel_src_sha256_16") != _src_hash(KSTEP_SRC):
         return None
-    if rec.get("k") != k or rec.get("q") != q:
-        return None
-    return rec["bytes_per_cell_update"] * launch_cell_updates
+    for r in rec.get("records", []):
+        if r.get("k") == k and r.get("q") == q:
+            return r["bytes_per_cell_update"] * launch_cell_updates
+    return None
 
 
 def cpu_baseline_ensemble(reps, budget_s=15.0, steps=100):
