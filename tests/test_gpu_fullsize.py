@@ -88,6 +88,30 @@ def test_open_road_kstep_onestep_and_oracle_windows():
     assert 0 <= extra <= vmax * vmax
 
 
+def test_maximum_length_ring():
+    """L = 2^31 - 1, the largest ring the library accepts: odd, so the word
+    that wraps the ring end is unaligned.  Windows at both ends, across the
+    wrap and inside match the oracle's light cone after two k-step launches;
+    the one-step kernel gives the same road and flux log."""
+    L, vmax, p, seed, T = 2**31 - 1, 5, 0.13, 7, 40
+    N = int(0.2 * L)
+    cfg = dict(L=L, N=N, vmax=vmax, p=p, seed=seed, replica=0, init_v=1)
+    a = Sim(L, N, vmax, p, seed, init_v=1, kernel="kstep", k=32, q=4)
+    a.step(T)
+    _check_windows(a.snapshot_range, cfg, T,
+                   [(0, 256), (L - 256, 256), (L - 100, 200), (L // 3, 160), (1234567891, 96)])
+    ga, _ = a.snapshot()
+    fa = a.flux(0, T)
+    a.close()
+    _flux_properties(fa, ga, N, vmax)
+    b = Sim(L, N, vmax, p, seed, init_v=1, kernel="onestep")
+    b.step(T)
+    gb, _ = b.snapshot()
+    np.testing.assert_array_equal(b.flux(0, T), fa)
+    b.close()
+    assert np.array_equal(ga, gb)
+
+
 def test_agent_ring_equals_grid_and_oracle_windows():
     cfg = workloads.AGENT_RING
     L, N, T = cfg["L"], cfg["N"], cfg["T"]

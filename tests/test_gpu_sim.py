@@ -173,6 +173,32 @@ def test_agent_state_is_cyclically_sorted():
 
 
 # ---------------------------------------------------------------- errors
+@pytest.mark.parametrize("rep,kernel", [("grid", "kstep"), ("grid", "onestep"),
+                                        ("agent", "kstep"), ("agent", "onestep")])
+def test_steps_up_to_the_last_step_number(rep, kernel):
+    """Restore at t = 2^32 - 40 and run to the largest step count, 2^32 - 1:
+    the step numbers in the draws and the device clock do not wrap early, and
+    one more step is refused."""
+    L, N, vmax, p, seed = 5000, 1200, 5, 0.3, 4
+    g0 = oracle.init_grid(L, N, vmax, seed, init_v=1)
+    t0 = 2**32 - 40
+    want, want_flux = oracle.run_grid(g0, vmax, p, seed, 39, t0=t0)
+    s = Sim(L, N, vmax, p, seed, rep=rep, kernel=kernel, init_v=1, k=16)
+    try:
+        s.restore(g0, t0)
+        s.step(20)
+        s.step(19)
+        g, t = s.snapshot()
+        assert t == 2**32 - 1
+        np.testing.assert_array_equal(g, want)
+        np.testing.assert_array_equal(s.flux(t0, 39), want_flux)
+        with pytest.raises(NaschError) as e:
+            s.step(1)
+        assert e.value.code == -4
+    finally:
+        s.close()
+
+
 def test_invalid_arguments_are_rejected():
     for args in [(0, 0, 5, 0.1), (10, 11, 5, 0.1), (10, 5, 9, 0.1), (10, 5, 5, 1.0),
                  (10, 5, 5, -0.1), (10, 5, 5, float("nan")), (2**31, 5, 5, 0.1)]:
