@@ -30,7 +30,7 @@ constexpr uint32_t kTieCap = 256;       // tied cars queued per wave
 
 // LDS scratch of one wave for rule 3.
 struct AgentLds {
-    uint4 blk[kBlockSlots];
+    uint2 blk[kBlockSlots];   // (lt, eq) masks of each tabulated block
     uint32_t tie_x[kTieCap];
     uint8_t tie_r[kTieCap];
 };
@@ -39,9 +39,10 @@ struct AgentLds {
 // The wave's cars are cyclically sorted, so the 32-cell blocks they start in
 // form one run of blocks from the block of lane 0's first car (mod the number
 // of blocks).  The lanes draw the first kBlockSlots blocks of that run
-// together (one Philox call per lane and 64 blocks) into LDS and every car
-// there reads the top nibble of its R from its block's entry; a car further
-// along (a sparse road) draws its own block.  The cars whose nibble ties with
+// together (one Philox call per lane and 64 blocks), compare each block's 32
+// top nibbles with thr's at once, and keep two masks per block in LDS: cars
+// below thr's nibble and cars tying with it.  A car reads its two bits from
+// its block's entry; a car further along (a sparse road) draws its own block.  The cars whose nibble ties with
 // thr's are then numbered across the wave and have their low 28 bits drawn
 // 64 at a time.  `nv` holds each car's velocity after rules 1-2 and receives
 // the result of rule 3.  All 64 lanes must be active; cars with nv == 0 draw
@@ -66,8 +67,9 @@ __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&
     for (uint32_t j = lane; j < n; j += 64u) {
         uint32_t blk = b0 + j;
         if (blk >= nblk) blk -= nblk;
-        const Word4 w = slow_hi_planes(blk, t, sp);
-        lds.blk[j] = make_uint4(w.w0, w.w1, w.w2, w.w3);
+        uint32_t lt, eq;
+        block_lt_eq(slow_hi_planes(blk, t, sp), th, lt, eq);
+        lds.blk[j] = make_uint2(lt, eq);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -76,18 +78,15 @@ __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&
 #pragma unroll
     for (int q = 0; q < C; ++q) {
         if (nv[q] > 0u) {
-            uint4 e;
+            uint2 e;
             if (slot[q] < n) {
                 e = lds.blk[slot[q]];
             } else {
-                const Word4 w = slow_hi_planes(x[q] >> 5, t, sp);
-                e = make_uint4(w.w0, w.w1, w.w2, w.w3);
+                block_lt_eq(slow_hi_planes(x[q] >> 5, t, sp), th, e.x, e.y);
             }
             const uint32_t sh = x[q] & 31u;
-            const uint32_t hi4 = (((e.x >> sh) & 1u) << 3) | (((e.y >> sh) & 1u) << 2) |
-                                 (((e.z >> sh) & 1u) << 1) | ((e.w >> sh) & 1u);
-            if (hi4 < th) --nv[q];
-            else if (hi4 == th) tie |= 1u << q;
+            if ((e.x >> sh) & 1u) --nv[q];
+            else if ((e.y >> sh) & 1u) tie |= 1u << q;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

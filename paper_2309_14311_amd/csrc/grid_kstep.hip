@@ -80,26 +80,6 @@ __device__ __forceinline__ Word4 planes_unaligned(uint32_t x0, uint32_t t, uint3
     return r;
 }
 
-// The bit-sliced nibble (w0 w1 w2 w3), w0 most significant, compared with the
-// constant TH: lt = nibble < TH, eq = nibble == TH.  With TH known the chain
-// folds into a few three-input bitwise operations.
-template <int TH>
-__device__ __forceinline__ void nibble_cmp(const Word4& w, uint32_t& lt, uint32_t& eq) {
-    const uint32_t P[4] = {w.w0, w.w1, w.w2, w.w3};
-    uint32_t l = 0u, e = 0xFFFFFFFFu;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        if ((TH >> (3 - b)) & 1) {
-            l |= e & ~P[b];
-            e &= P[b];
-        } else {
-            e &= ~P[b];
-        }
-    }
-    lt = l;
-    eq = e;
-}
-
 // Rule 3, first stage, for the moving cars of the lane's Q words (word q covers
 // ring cells xw[q] .. xw[q]+31, mod L): S = cars whose top nibble of R is below
 // thr's (slow), U = cars whose top nibble ties with thr's (decided by the low

@@ -76,6 +76,50 @@ __device__ __forceinline__ uint32_t rand32(uint32_t x, uint32_t t, const SlowPar
     return (hi << 28) | slow_lo28(x, t, sp);
 }
 
+// The bit-sliced nibble (w0 w1 w2 w3), w0 most significant, compared with the
+// constant TH: lt = nibble < TH, eq = nibble == TH.  With TH known the chain
+// folds into a few three-input bitwise operations.
+template <int TH>
+__device__ __forceinline__ void nibble_cmp(const Word4& w, uint32_t& lt, uint32_t& eq) {
+    const uint32_t P[4] = {w.w0, w.w1, w.w2, w.w3};
+    uint32_t l = 0u, e = 0xFFFFFFFFu;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        if ((TH >> (3 - b)) & 1) {
+            l |= e & ~P[b];
+            e &= P[b];
+        } else {
+            e &= ~P[b];
+        }
+    }
+    lt = l;
+    eq = e;
+}
+
+// The same comparison of one block with thr's top nibble `th` (uniform over
+// the wave): lt = cars whose nibble is below th, eq = cars whose nibble ties.
+__device__ __forceinline__ void block_lt_eq(const Word4& w, uint32_t th, uint32_t& lt,
+                                            uint32_t& eq) {
+    switch (th) {
+        case 0: nibble_cmp<0>(w, lt, eq); break;
+        case 1: nibble_cmp<1>(w, lt, eq); break;
+        case 2: nibble_cmp<2>(w, lt, eq); break;
+        case 3: nibble_cmp<3>(w, lt, eq); break;
+        case 4: nibble_cmp<4>(w, lt, eq); break;
+        case 5: nibble_cmp<5>(w, lt, eq); break;
+        case 6: nibble_cmp<6>(w, lt, eq); break;
+        case 7: nibble_cmp<7>(w, lt, eq); break;
+        case 8: nibble_cmp<8>(w, lt, eq); break;
+        case 9: nibble_cmp<9>(w, lt, eq); break;
+        case 10: nibble_cmp<10>(w, lt, eq); break;
+        case 11: nibble_cmp<11>(w, lt, eq); break;
+        case 12: nibble_cmp<12>(w, lt, eq); break;
+        case 13: nibble_cmp<13>(w, lt, eq); break;
+        case 14: nibble_cmp<14>(w, lt, eq); break;
+        default: nibble_cmp<15>(w, lt, eq); break;
+    }
+}
+
 // Rule 3 decision for a car whose top nibble of R is already known.
 __device__ __forceinline__ bool slow_from_hi(uint32_t hi4, uint32_t x, uint32_t t,
                                              const SlowParams& sp) {
