@@ -63,7 +63,7 @@ inline SlowParams slow_params(uint64_t seed, uint32_t replica, double p) {
 // rest.  A ring that fits one segment is one tile owning all L cells.
 inline bool kstep_geometry(uint32_t L, uint32_t vmax, uint32_t k, uint32_t q, uint32_t* own,
                            uint32_t* halo, uint32_t* ntiles) {
-    if (k == 0 || (q != 1 && q != 2 && q != 4)) return false;
+    if (k == 0 || q == 0 || q > 4) return false;
     const uint64_t seg = kstep_segment(q);
     const uint64_t H = ((uint64_t)k * vmax + 31u) / 32u * 32u;
     if (seg < 2 * H + 32) return false;
@@ -294,7 +294,7 @@ namespace nasch {
 inline std::vector<std::pair<uint32_t, uint32_t>> kstep_candidates() {
     std::vector<std::pair<uint32_t, uint32_t>> c;
     const uint32_t ks[] = {8, 16, 24, 32, 48, 64};
-    const uint32_t qs[] = {1, 2, 4};
+    const uint32_t qs[] = {1, 2, 3, 4};
     for (uint32_t q : qs)
         for (uint32_t k : ks) c.emplace_back(k, q);
     return c;

@@ -580,6 +580,7 @@ hipError_t launch_grid_kstep(uint32_t vmax, bool open, uint32_t q, const RingDes
     switch (q) {
         case 1: return launch_q<1>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         case 2: return launch_q<2>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
+        case 3: return launch_q<3>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         case 4: return launch_q<4>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         default: return hipErrorInvalidValue;
     }

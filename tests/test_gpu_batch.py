@@ -78,7 +78,7 @@ def test_reset_and_autotune_reproduce():
     b.step(200)
     first = b.flux_sums().copy()
     k, q = b.autotune()
-    assert k > 0 and q in (1, 2, 4)
+    assert k > 0 and q in (1, 2, 3, 4)
     b.reset()
     b.step(200)
     np.testing.assert_array_equal(b.flux_sums(), first)

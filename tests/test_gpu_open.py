@@ -54,7 +54,7 @@ def test_every_vmax(vmax, kernel):
     _run_and_compare(3000, 700, vmax, 0.2, 40 + vmax, 60, 0.6, 0.4, kernel=kernel)
 
 
-@pytest.mark.parametrize("q", [1, 2, 4])
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
 @pytest.mark.parametrize("k", [1, 2, 7, 16, 32, 50])
 def test_kstep_tilings(k, q):
     """Several tiles, so tiles whose segments hold cell 0 or cell L sit beside

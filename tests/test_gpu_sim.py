@@ -83,7 +83,7 @@ def test_probabilities(p):
     _run_and_compare(9001, 3000, 5, p, 3, 20, kernel="onestep", init_v=1)
 
 
-@pytest.mark.parametrize("q", [1, 2, 4])
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
 @pytest.mark.parametrize("k", [1, 2, 3, 7, 16, 32, 50])
 def test_kstep_tilings(k, q):
     """Results do not depend on the temporal block depth or the segment size;
