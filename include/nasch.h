@@ -320,7 +320,8 @@ void nasch_server_default_opts(nasch_server_opts* opts);
 /* Start the server and its scheduling thread. */
 int nasch_server_create(nasch_server** out, const nasch_server_opts* opts);
 /* Queue a request (validated as nasch_init, 1 <= T < 2^32); its footprint,
- * 2 * ceil256(L) + ceil256(8 T) bytes (two grids and the flux log, each
+ * ceil256(L) + 2 * ceil256(4 (vmax + 1) ceil(L / 32)) + ceil256(8 T) bytes
+ * (the byte grid, two bit-plane copies of the road and the flux log, each
  * rounded up to 256 bytes), must fit hbm_budget.  *id receives its id.  Never
  * blocks on the GPU; the request waits in arrival order until it fits. */
 int nasch_server_submit(nasch_server* s, const nasch_request* req, uint64_t* id);

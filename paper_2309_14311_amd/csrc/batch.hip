@@ -1,6 +1,9 @@
 // batch.hip -- the batched ensemble: many independent rings in one device arena,
 // advanced together by the temporal-blocked grid kernel (all rings' tiles in
 // the same launches).  Entry points are documented in include/nasch.h.
+//
+// Each replica holds one byte grid (the initial placement and snapshots) and
+// two bit-plane buffers (the state the kernel steps), 256-byte aligned.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -32,17 +35,23 @@ struct nasch_batch {
     InitRing* d_init_rings = nullptr;     // placement of every replica, one launch
     InitChunk* d_init_chunks = nullptr;
     uint32_t n_init_chunks = 0;
+    ConvJob* d_conv_jobs = nullptr;       // byte grid -> planes pl[0] of every replica
+    ConvChunk* d_conv_chunks = nullptr;
+    uint32_t n_conv_chunks = 0;
 
     bool ok(hipError_t e) { return st.ok(e); }
-    // Every replica at t = 0: the whole arena EMPTY, then all cars scattered.
+    // Every replica at t = 0: the whole arena EMPTY, all cars scattered into
+    // the byte grids, then the grids turned into bit planes.
     bool init_state() {
         return ok(launch_fill_u8(arena, arena_bytes, 0xFFu, stream)) &&
-               ok(launch_init_scatter(d_init_rings, d_init_chunks, n_init_chunks, stream));
+               ok(launch_init_scatter(d_init_rings, d_init_chunks, n_init_chunks, stream)) &&
+               ok(launch_bytes_to_planes(d_conv_jobs, d_conv_chunks, n_conv_chunks, stream));
     }
     ~nasch_batch() {
         graphs.clear();
         eng.release();
-        void* ps[] = {arena, d_acc, d_log, d_clk, d_init_rings, d_init_chunks};
+        void* ps[] = {arena, d_acc, d_log, d_clk, d_init_rings, d_init_chunks, d_conv_jobs,
+                      d_conv_chunks};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -100,9 +109,13 @@ int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
     }
     std::vector<uint64_t> offs(R);
     uint64_t bytes = 0;
+    auto grid_bytes = [](const nasch_replica& p) { return (p.L + 255) / 256 * 256; };
+    auto plane_bytes = [](const nasch_replica& p) {
+        return ((uint64_t)(p.vmax + 1) * plane_words(p.L) * 4u + 255) / 256 * 256;
+    };
     for (uint32_t r = 0; r < R; ++r) {
         offs[r] = bytes;
-        bytes += 2 * ((reps[r].L + 255) / 256 * 256);
+        bytes += grid_bytes(reps[r]) + 2 * plane_bytes(reps[r]);
     }
     b->arena_bytes = bytes;
     if (!b->ok(dev_alloc(&b->arena, bytes)) || !b->ok(dev_alloc(&b->d_acc, R)) ||
@@ -121,12 +134,17 @@ int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
     uint32_t vmax_all = 0;
     std::vector<InitRing> init_rings;
     std::vector<InitChunk> init_chunks;
+    std::vector<ConvJob> conv_jobs;
+    std::vector<ConvChunk> conv_chunks;
     for (uint32_t r = 0; r < R; ++r) {
         const nasch_replica& p = reps[r];
-        const uint64_t sz = (p.L + 255) / 256 * 256;
+        const uint64_t sz = grid_bytes(p), psz = plane_bytes(p);
         RingDesc d{};
         d.buf[0] = b->arena + offs[r];
-        d.buf[1] = b->arena + offs[r] + sz;
+        d.buf[1] = nullptr;
+        d.pl[0] = reinterpret_cast<uint32_t*>(b->arena + offs[r] + sz);
+        d.pl[1] = reinterpret_cast<uint32_t*>(b->arena + offs[r] + sz + psz);
+        d.nw = plane_words(p.L);
         d.flux_log = b->d_log ? b->d_log + (uint64_t)r * b->log_steps : nullptr;
         d.flux_acc = b->d_acc + r;
         d.log_t0 = 0;
@@ -140,11 +158,21 @@ int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
         init_rings.push_back(InitRing{d.buf[0], (uint32_t)p.L, (uint32_t)p.N, p.vmax, p.init_v,
                                       feistel_bits(p.L), 0u, d.sp});
         for (uint64_t c = 0; c < p.N; c += kInitChunk) init_chunks.push_back(InitChunk{r, (uint32_t)c});
+        conv_jobs.push_back(ConvJob{d.buf[0], d.pl[0], d.L, d.nw, d.vmax, 0u});
+        for (uint32_t w = 0; w < d.nw; w += kConvChunk) conv_chunks.push_back(ConvChunk{r, w});
     }
     b->n_init_chunks = (uint32_t)init_chunks.size();
+    b->n_conv_chunks = (uint32_t)conv_chunks.size();
     if (!b->ok(dev_alloc(&b->d_init_rings, R)) ||
-        !b->ok(dev_alloc(&b->d_init_chunks, init_chunks.size())))
+        !b->ok(dev_alloc(&b->d_init_chunks, init_chunks.size())) ||
+        !b->ok(dev_alloc(&b->d_conv_jobs, R)) ||
+        !b->ok(dev_alloc(&b->d_conv_chunks, conv_chunks.size())))
         return NASCH_ENOMEM;
+    if (!b->ok(hipMemcpy(b->d_conv_jobs, conv_jobs.data(), R * sizeof(ConvJob),
+                         hipMemcpyHostToDevice)) ||
+        !b->ok(hipMemcpy(b->d_conv_chunks, conv_chunks.data(),
+                         conv_chunks.size() * sizeof(ConvChunk), hipMemcpyHostToDevice)))
+        return NASCH_EDEVICE;
     if (!b->ok(hipMemcpy(b->d_init_rings, init_rings.data(), R * sizeof(InitRing),
                          hipMemcpyHostToDevice)) ||
         (!init_chunks.empty() &&
@@ -225,8 +253,11 @@ int nasch_batch_snapshot(nasch_batch* b, uint32_t r, uint8_t* out, uint64_t* t_o
     if (!b) return NASCH_EINVAL;
     if (r >= b->reps.size()) return NASCH_ENOTFOUND;
     if (out) {
+        // the replica's planes into its byte grid, then to the host
         const RingDesc& d = b->eng.rings[r];
-        if (!b->ok(hipMemcpyAsync(out, d.buf[b->parity], d.L, hipMemcpyDeviceToHost, b->stream)) ||
+        const ConvJob job{d.buf[0], d.pl[b->parity], d.L, d.nw, d.vmax, 0u};
+        if (!b->ok(launch_planes_to_bytes_one(job, b->stream)) ||
+            !b->ok(hipMemcpyAsync(out, d.buf[0], d.L, hipMemcpyDeviceToHost, b->stream)) ||
             !b->ok(hipStreamSynchronize(b->stream)))
             return NASCH_EDEVICE;
     }

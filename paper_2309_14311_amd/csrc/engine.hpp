@@ -301,7 +301,7 @@ inline std::vector<std::pair<uint32_t, uint32_t>> kstep_candidates() {
 }
 
 // Times every candidate (k, q) admitted by all rings on scratch copies of their
-// current state (buf[cur] of each ring) and returns the fastest.  The rings
+// current state (the bit planes pl[cur] of each ring) and returns the fastest.  The rings
 // themselves are not touched.  `steps` steps are timed per candidate after one
 // untimed launch.
 inline hipError_t autotune_grid(const std::vector<RingDesc>& rings, uint32_t t_now, uint32_t cur,
@@ -312,8 +312,11 @@ inline hipError_t autotune_grid(const std::vector<RingDesc>& rings, uint32_t t_n
     *best_cups = 0.0;
     if (rings.empty()) return hipSuccess;
     uint64_t bytes = 0, cells = 0;
+    auto plane_bytes = [](const RingDesc& r) {
+        return ((uint64_t)(r.vmax + 1) * r.nw * 4u + 255u) / 256u * 256u;
+    };
     for (const RingDesc& r : rings) {
-        bytes += 2 * ((uint64_t)(r.L + 255u) / 256u * 256u);
+        bytes += 2 * plane_bytes(r);
         cells += r.L;
     }
     uint8_t* arena = nullptr;
@@ -328,9 +331,10 @@ inline hipError_t autotune_grid(const std::vector<RingDesc>& rings, uint32_t t_n
         uint64_t off = 0;
         for (const RingDesc& r : rings) {
             RingDesc c = r;
-            const uint64_t sz = (uint64_t)(r.L + 255u) / 256u * 256u;
-            c.buf[0] = arena + off;
-            c.buf[1] = arena + off + sz;
+            const uint64_t sz = plane_bytes(r);
+            c.buf[0] = c.buf[1] = nullptr;
+            c.pl[0] = reinterpret_cast<uint32_t*>(arena + off);
+            c.pl[1] = reinterpret_cast<uint32_t*>(arena + off + sz);
             off += 2 * sz;
             c.flux_log = nullptr;
             c.flux_acc = nullptr;
@@ -338,8 +342,8 @@ inline hipError_t autotune_grid(const std::vector<RingDesc>& rings, uint32_t t_n
             c.parity = 0;
             c.t_end = 0xFFFFFFFFu;
             if (e == hipSuccess)
-                e = hipMemcpyAsync(c.buf[0], r.buf[(cur + r.parity) & 1u], r.L,
-                                   hipMemcpyDeviceToDevice, s);
+                e = hipMemcpyAsync(c.pl[0], r.pl[(cur + r.parity) & 1u],
+                                   (uint64_t)(r.vmax + 1) * r.nw * 4u, hipMemcpyDeviceToDevice, s);
             scratch.rings.push_back(c);
         }
     }

@@ -14,6 +14,8 @@
 //            thermometer down by one: v3 >= m <=> S ? v2 >= m+1 : v2 >= m
 //   rule 4   the cars with v3 == j are shifted j cells to the right, and the
 //            new thermometer is the suffix-OR of the shifted classes.
+// The road is stored in HBM in the same planes (RingDesc), so a launch loads
+// and stores VMAX + 1 words per 32 cells and converts nothing.
 // Neighbouring words come from the same lane or, at lane edges, from lane +-1
 // by cross-lane shuffles.  The segment is the tile's owned cells plus a halo
 // of H >= k*vmax cells on each side (read modulo L, so short rings repeat
@@ -40,15 +42,6 @@
 namespace nasch {
 
 namespace {
-
-// 4 bits at positions 0, 8, 16, 24 of y -> bits 0..3.
-__device__ __forceinline__ uint32_t gather4(uint32_t y) {
-    return (((y & 0x01010101u) * 0x00204081u) >> 21) & 0xFu;
-}
-// bits 0..3 of b -> bits 0, 8, 16, 24.
-__device__ __forceinline__ uint32_t spread4(uint32_t b) {
-    return ((b & 0xFu) * 0x00204081u) & 0x01010101u;
-}
 
 // mask of bits [a, b), 0 <= a <= b <= 32
 __device__ __forceinline__ uint32_t bit_range(uint32_t a, uint32_t b) {
@@ -190,36 +183,28 @@ __device__ __forceinline__ void slow_lo_wave(uint32_t (&S)[Q], const uint32_t (&
     __builtin_amdgcn_wave_barrier();
 }
 
-// (P3 P2 P1 P0) >= M for a constant M, bit-sliced over 32 cells.
-template <int M>
-__device__ __forceinline__ uint32_t ge_const(uint32_t P0, uint32_t P1, uint32_t P2, uint32_t P3) {
-    const uint32_t P[4] = {P0, P1, P2, P3};
-    uint32_t gt = 0u, eq = 0xFFFFFFFFu;
-#pragma unroll
-    for (int b = 3; b >= 0; --b) {
-        if ((M >> b) & 1) {
-            eq &= P[b];
-        } else {
-            gt |= eq & P[b];
-            eq &= ~P[b];
-        }
-    }
-    return gt | eq;
-}
-
-template <int VMAX, int M>
-struct Thermo {
-    __device__ static __forceinline__ void fill(uint32_t* T, uint32_t occ, uint32_t P0,
-                                                uint32_t P1, uint32_t P2, uint32_t P3) {
-        T[M] = occ & ge_const<M>(P0, P1, P2, P3);
-        Thermo<VMAX, M + 1>::fill(T, occ, P0, P1, P2, P3);
-    }
-};
+// The bit planes of the 32 consecutive ring cells x0, x0+1, ... (mod L) when
+// they are not one aligned word of the stored planes (a word across the end
+// of the ring, or a ring shorter than a segment): assembled run by run.
 template <int VMAX>
-struct Thermo<VMAX, VMAX + 1> {
-    __device__ static __forceinline__ void fill(uint32_t*, uint32_t, uint32_t, uint32_t, uint32_t,
-                                                uint32_t) {}
-};
+__device__ __forceinline__ void gather_ring(const uint32_t* __restrict__ src, uint32_t nw, uint32_t L,
+                                         uint32_t x0, uint32_t (&T)[VMAX + 1]) {
+#pragma unroll
+    for (int m = 0; m <= VMAX; ++m) T[m] = 0u;
+    uint32_t pos = x0, i = 0;
+    while (i < 32u) {
+        const uint32_t off = pos & 31u;
+        uint32_t run = min(32u - off, L - pos);
+        run = min(run, 32u - i);
+        const uint32_t mask = run >= 32u ? 0xFFFFFFFFu : ((1u << run) - 1u);
+        const uint32_t w = pos >> 5;
+#pragma unroll
+        for (int m = 0; m <= VMAX; ++m) T[m] |= ((src[(size_t)m * nw + w] >> off) & mask) << i;
+        i += run;
+        pos += run;
+        if (pos >= L) pos = 0;
+    }
+}
 
 }  // namespace
 
@@ -238,8 +223,9 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     uint32_t nsteps = k;
     if (R.t_end != 0xFFFFFFFFu) nsteps = R.t_end > t0 ? min(k, R.t_end - t0) : 0u;
     const uint32_t par = (clk->parity + R.parity + launch_idx) & 1u;
-    const uint8_t* __restrict__ src = R.buf[par];
-    uint8_t* __restrict__ dst = R.buf[par ^ 1u];
+    const uint32_t nw = R.nw;
+    const uint32_t* __restrict__ src = R.pl[par];
+    uint32_t* __restrict__ dst = R.pl[par ^ 1u];
 
     const uint32_t own_start = it.tile * R.own;
     const uint32_t own_len = min(R.own, L - own_start);
@@ -274,7 +260,13 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
             obst[q] = (p0 <= (int64_t)L && (int64_t)L < p0 + 32) ? 1u << (uint32_t)(L - p0) : 0u;
             inj[q] = p0 == 0 ? 1u : 0u;
         } else {
-            x0 = (uint32_t)(((uint64_t)s0 + j0) % L);
+            // s0 < L < 2^31 and j0 < 8192: one subtraction unless the ring is
+            // shorter than the segment
+            x0 = s0 + j0;
+            if (x0 >= L) {
+                x0 -= L;
+                if (x0 >= L) x0 %= L;
+            }
             aligned[q] = ((x0 & 31u) == 0u) && (x0 + 32u <= L);
             keep[q] = obst[q] = inj[q] = 0u;
         }
@@ -282,63 +274,29 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
         const uint32_t lo = max(H, j0), hi = min(H + own_len, j0 + 32u);
         own[q] = lo < hi ? bit_range(lo - j0, hi - j0) : 0u;
 
-        uint32_t by[8];
+        // segment cells past seg_len stay empty; so do road cells outside
+        // [0, L) on an open road
+        const uint32_t valid = j0 + 32u <= seg_len ? 0xFFFFFFFFu
+                               : (j0 < seg_len ? (1u << (seg_len - j0)) - 1u : 0u);
         if constexpr (OPEN) {
-            if (j0 + 32u <= seg_len && p0 >= 0 && p0 + 32 <= (int64_t)L) {
-                const uint4* p = reinterpret_cast<const uint4*>(src + p0);
-                const uint4 a = p[0], b = p[1];
-                by[0] = a.x; by[1] = a.y; by[2] = a.z; by[3] = a.w;
-                by[4] = b.x; by[5] = b.y; by[6] = b.z; by[7] = b.w;
+            if (p0 >= 0 && p0 < (int64_t)L) {
+                const uint32_t v = valid & keep[q];
+                const uint32_t w = (uint32_t)p0 >> 5;
+#pragma unroll
+                for (int m = 0; m <= VMAX; ++m) T[q][m] = src[(size_t)m * nw + w] & v;
             } else {
 #pragma unroll
-                for (int d = 0; d < 8; ++d) {
-                    uint32_t w = 0;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const uint32_t jj = j0 + (uint32_t)(4 * d + e);
-                        const int64_t pos = p0 + (4 * d + e);
-                        uint32_t val = kEmpty;
-                        if (jj < seg_len && pos >= 0 && pos < (int64_t)L) val = src[pos];
-                        w |= val << (8 * e);
-                    }
-                    by[d] = w;
-                }
+                for (int m = 0; m <= VMAX; ++m) T[q][m] = 0u;
             }
-        } else if (j0 + 32u <= seg_len && (x0 & 15u) == 0u && x0 + 32u <= L) {
-            const uint4* p = reinterpret_cast<const uint4*>(src + x0);
-            const uint4 a = p[0], b = p[1];
-            by[0] = a.x; by[1] = a.y; by[2] = a.z; by[3] = a.w;
-            by[4] = b.x; by[5] = b.y; by[6] = b.z; by[7] = b.w;
+        } else if (aligned[q]) {
+            const uint32_t w = x0 >> 5;
+#pragma unroll
+            for (int m = 0; m <= VMAX; ++m) T[q][m] = src[(size_t)m * nw + w] & valid;
         } else {
-            uint32_t pos = x0;
+            gather_ring<VMAX>(src, nw, L, x0, T[q]);
 #pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                uint32_t w = 0;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    uint32_t val = kEmpty;
-                    if (j0 + (uint32_t)(4 * d + e) < seg_len) val = src[pos];
-                    w |= val << (8 * e);
-                    ++pos;
-                    if (pos >= L) pos = 0;
-                }
-                by[d] = w;
-            }
+            for (int m = 0; m <= VMAX; ++m) T[q][m] &= valid;
         }
-        uint32_t P0 = 0, P1 = 0, P2 = 0, P3 = 0, E = 0;
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const uint32_t w = by[d];
-            const uint32_t sh = 4u * d;
-            E |= gather4(w >> 7) << sh;
-            P0 |= gather4(w) << sh;
-            P1 |= gather4(w >> 1) << sh;
-            P2 |= gather4(w >> 2) << sh;
-            P3 |= gather4(w >> 3) << sh;
-        }
-        const uint32_t occ = ~E;
-        T[q][0] = occ;
-        Thermo<VMAX, 1>::fill(T[q], occ, P0, P1, P2, P3);
     }
 
     // rule-3 tables of this wave
@@ -449,40 +407,15 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
         if (lane == 0u && total) atomicAdd(R.flux_acc, (unsigned long long)total);
     }
 
-    // ---- store the owned cells: bit planes -> bytes
+    // ---- store the owned cells (whole words: tiles start on word boundaries;
+    // the road's last word keeps zeros past cell L-1)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         if (own[q] == 0u) continue;
         const uint32_t j0 = 32u * (lane * Q + q);
-        const uint32_t xs = own_start + (j0 - H);
-        uint32_t B0 = 0u, B1 = 0u, B2 = 0u, B3 = 0u;
-        uint32_t Tm[9];
+        const uint32_t w = (own_start + (j0 - H)) >> 5;
 #pragma unroll
-        for (int m = 0; m <= 8; ++m) Tm[m] = 0u;
-#pragma unroll
-        for (int m = 1; m <= VMAX; ++m) Tm[m] = T[q][m];
-#pragma unroll
-        for (int m = 1; m <= VMAX; ++m) B0 ^= T[q][m];
-        B1 = (Tm[2] & ~Tm[4]) | (Tm[6] & ~Tm[8]);
-        B2 = Tm[4] & ~Tm[8];
-        B3 = Tm[8];
-        const uint32_t E = ~T[q][0];
-        uint32_t by[8];
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const uint32_t sh = 4u * d;
-            by[d] = spread4(B0 >> sh) | (spread4(B1 >> sh) << 1) | (spread4(B2 >> sh) << 2) |
-                    (spread4(B3 >> sh) << 3) | (spread4(E >> sh) * 0xFFu);
-        }
-        if (own[q] == 0xFFFFFFFFu && (xs & 15u) == 0u) {
-            uint4* p = reinterpret_cast<uint4*>(dst + xs);
-            p[0] = make_uint4(by[0], by[1], by[2], by[3]);
-            p[1] = make_uint4(by[4], by[5], by[6], by[7]);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 32; ++i)
-                if ((own[q] >> i) & 1u) dst[xs + i] = (uint8_t)(by[i >> 2] >> (8 * (i & 3)));
-        }
+        for (int m = 0; m <= VMAX; ++m) dst[(size_t)m * nw + w] = T[q][m] & own[q];
     }
 }
 

@@ -35,6 +35,140 @@ hipError_t launch_init_grid(uint8_t* g, uint32_t L, uint32_t N, uint32_t vmax, u
     return hipGetLastError();
 }
 
+// ---- bytes <-> bit planes ------------------------------------------------------
+// One thread per 32-cell word, a block per kConvChunk words of one job.
+namespace {
+// bit 0 of each byte of y -> bits 0..3 (byte b -> bit b)
+__device__ __forceinline__ uint32_t gather4(uint32_t y) {
+    return (((y & 0x01010101u) * 0x00204081u) >> 21) & 0xFu;
+}
+// bits 0..3 of b -> bit 0 of bytes 0..3
+__device__ __forceinline__ uint32_t spread4(uint32_t b) {
+    return ((b & 0xFu) * 0x00204081u) & 0x01010101u;
+}
+// (P3 P2 P1 P0) >= m, bit-sliced over 32 cells, for 1 <= m <= 15
+__device__ __forceinline__ uint32_t ge_value(const uint32_t (&P)[4], uint32_t m) {
+    uint32_t gt = 0u, eq = 0xFFFFFFFFu;
+    for (int b = 3; b >= 0; --b) {
+        if ((m >> b) & 1u) {
+            eq &= P[b];
+        } else {
+            gt |= eq & P[b];
+            eq &= ~P[b];
+        }
+    }
+    return gt | eq;
+}
+__device__ __forceinline__ bool conv_job(const ConvJob* jobs, const ConvChunk* chunks,
+                                         const ConvJob& single, ConvJob& J, uint32_t& w) {
+    const ConvChunk c = chunks ? chunks[blockIdx.x] : ConvChunk{0u, blockIdx.x * kConvChunk};
+    J = chunks ? jobs[c.job] : single;
+    w = c.first + threadIdx.x;
+    return w < J.nw;
+}
+}  // namespace
+
+__global__ __launch_bounds__(kConvChunk) void bytes_to_planes_kernel(const ConvJob* jobs,
+                                                                     const ConvChunk* chunks,
+                                                                     ConvJob single) {
+    ConvJob J;
+    uint32_t w;
+    if (!conv_job(jobs, chunks, single, J, w)) return;
+    const uint64_t c0 = (uint64_t)w * 32u;
+    uint32_t by[8];
+    if (c0 + 32u <= J.L) {
+        const uint4* p = reinterpret_cast<const uint4*>(J.bytes + c0);
+        const uint4 a = p[0], b = p[1];
+        by[0] = a.x; by[1] = a.y; by[2] = a.z; by[3] = a.w;
+        by[4] = b.x; by[5] = b.y; by[6] = b.z; by[7] = b.w;
+    } else {
+        for (int d = 0; d < 8; ++d) {
+            uint32_t y = 0;
+            for (int e = 0; e < 4; ++e) {
+                const uint64_t c = c0 + 4u * d + e;
+                const uint32_t val = c < J.L ? J.bytes[c] : kEmpty;   // past the road: empty
+                y |= val << (8 * e);
+            }
+            by[d] = y;
+        }
+    }
+    uint32_t E = 0u, P[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        const uint32_t sh = 4u * d;
+        E |= gather4(by[d] >> 7) << sh;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) P[b] |= gather4(by[d] >> b) << sh;
+    }
+    const uint32_t occ = ~E;
+    J.planes[w] = occ;
+    for (uint32_t m = 1; m <= J.vmax; ++m) J.planes[(uint64_t)m * J.nw + w] = occ & ge_value(P, m);
+}
+
+__global__ __launch_bounds__(kConvChunk) void planes_to_bytes_kernel(const ConvJob* jobs,
+                                                                     const ConvChunk* chunks,
+                                                                     ConvJob single) {
+    ConvJob J;
+    uint32_t w;
+    if (!conv_job(jobs, chunks, single, J, w)) return;
+    uint32_t T[9];
+    for (uint32_t m = 0; m <= 8; ++m) T[m] = m <= J.vmax ? J.planes[(uint64_t)m * J.nw + w] : 0u;
+    // thermometer (T[m]: v >= m) -> binary digits of v
+    uint32_t B0 = 0u;
+    for (uint32_t m = 1; m <= 8; ++m) B0 ^= T[m];
+    const uint32_t B1 = (T[2] & ~T[4]) | (T[6] & ~T[8]);
+    const uint32_t B2 = T[4] & ~T[8];
+    const uint32_t B3 = T[8];
+    const uint32_t E = ~T[0];
+    uint32_t by[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        const uint32_t sh = 4u * d;
+        by[d] = spread4(B0 >> sh) | (spread4(B1 >> sh) << 1) | (spread4(B2 >> sh) << 2) |
+                (spread4(B3 >> sh) << 3) | (spread4(E >> sh) * 0xFFu);
+    }
+    const uint64_t c0 = (uint64_t)w * 32u;
+    if (c0 + 32u <= J.L) {
+        uint4* p = reinterpret_cast<uint4*>(J.bytes + c0);
+        p[0] = make_uint4(by[0], by[1], by[2], by[3]);
+        p[1] = make_uint4(by[4], by[5], by[6], by[7]);
+    } else {
+        for (uint32_t i = 0; c0 + i < J.L; ++i) J.bytes[c0 + i] = (uint8_t)(by[i >> 2] >> (8 * (i & 3)));
+    }
+}
+
+hipError_t launch_bytes_to_planes(const ConvJob* jobs, const ConvChunk* chunks, uint32_t n_chunks,
+                                  hipStream_t s) {
+    if (n_chunks == 0) return hipSuccess;
+    NASCH_LAUNCH(bytes_to_planes_kernel, dim3(n_chunks), dim3(kConvChunk), 0, s, jobs, chunks,
+                 ConvJob{});
+    return hipGetLastError();
+}
+
+hipError_t launch_planes_to_bytes(const ConvJob* jobs, const ConvChunk* chunks, uint32_t n_chunks,
+                                  hipStream_t s) {
+    if (n_chunks == 0) return hipSuccess;
+    NASCH_LAUNCH(planes_to_bytes_kernel, dim3(n_chunks), dim3(kConvChunk), 0, s, jobs, chunks,
+                 ConvJob{});
+    return hipGetLastError();
+}
+
+hipError_t launch_bytes_to_planes_one(const ConvJob& job, hipStream_t s) {
+    const uint32_t blocks = (job.nw + kConvChunk - 1) / kConvChunk;
+    if (blocks == 0) return hipSuccess;
+    NASCH_LAUNCH(bytes_to_planes_kernel, dim3(blocks), dim3(kConvChunk), 0, s, nullptr, nullptr,
+                 job);
+    return hipGetLastError();
+}
+
+hipError_t launch_planes_to_bytes_one(const ConvJob& job, hipStream_t s) {
+    const uint32_t blocks = (job.nw + kConvChunk - 1) / kConvChunk;
+    if (blocks == 0) return hipSuccess;
+    NASCH_LAUNCH(planes_to_bytes_kernel, dim3(blocks), dim3(kConvChunk), 0, s, nullptr, nullptr,
+                 job);
+    return hipGetLastError();
+}
+
 // ---- grid -> agent compaction ---------------------------------------------------
 // One workgroup of 256 threads per chunk; thread i scans a contiguous run of
 // kCompactChunk / 256 cells so that the writes come out in ascending order.

@@ -35,6 +35,14 @@ hipError_t launch_compact_chunks(const uint8_t* g, uint32_t L, const uint32_t* o
 // Grid of an agent state: fill with EMPTY, then g[x[i]] = v[i].
 hipError_t launch_agent_to_grid(const int32_t* x, const uint8_t* v, uint32_t N, uint8_t* g,
                                 uint32_t L, hipStream_t s);
+// Byte form <-> bit-plane form of roads (see RingDesc): a batch of jobs cut into
+// chunks of kConvChunk words, or one job.
+hipError_t launch_bytes_to_planes(const ConvJob* jobs, const ConvChunk* chunks, uint32_t n_chunks,
+                                  hipStream_t s);
+hipError_t launch_planes_to_bytes(const ConvJob* jobs, const ConvChunk* chunks, uint32_t n_chunks,
+                                  hipStream_t s);
+hipError_t launch_bytes_to_planes_one(const ConvJob& job, hipStream_t s);
+hipError_t launch_planes_to_bytes_one(const ConvJob& job, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t value, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, hipStream_t s);
 hipError_t launch_clock_advance(Clock* clk, uint32_t T, uint32_t nlaunch, hipStream_t s);

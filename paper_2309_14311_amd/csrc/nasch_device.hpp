@@ -206,13 +206,21 @@ __device__ __forceinline__ uint32_t initial_velocity(uint32_t x, uint32_t vmax, 
 }
 
 // ---- descriptors --------------------------------------------------------------
-// One ring as the temporal-blocked grid kernel sees it.  Tiles own `own` cells
-// each (the last one the remainder); a tile's segment is its owned cells plus
-// `halo` cells on each side, read modulo L.  With `open` set the road is not a
-// ring: cells outside [0, L) are empty, a car enters cell 0 and the exit at
-// cell L opens by the gate draw of each step (see gate_draw).
+// One ring as the grid kernels see it.  Tiles own `own` cells each (the last
+// one the remainder); a tile's segment is its owned cells plus `halo` cells on
+// each side, read modulo L.  With `open` set the road is not a ring: cells
+// outside [0, L) are empty, a car enters cell 0 and the exit at cell L opens
+// by the gate draw of each step (see gate_draw).
+//
+// The road is kept in one of two forms: bytes (buf, one per cell: 0xFF or v),
+// read by the one-step kernel, the snapshots and the initial placement; or bit
+// planes (pl), read and written by the temporal-blocked kernel.  Plane m
+// (m = 0..vmax) holds nw = ceil(L / 32) words at pl[b] + m * nw: plane 0 is the
+// occupancy (bit i of word w for cell 32 w + i), plane m >= 1 the cars with
+// v >= m.  Bits past cell L-1 are zero.
 struct RingDesc {
     uint8_t* buf[2];         // ping-pong grids, L bytes each
+    uint32_t* pl[2];         // ping-pong bit planes, (vmax + 1) * nw words each
     unsigned long long* flux_log;  // F(t) at flux_log[t - log_t0] (may be null)
     unsigned long long* flux_acc;  // += F(t) for t >= warmup (may be null)
     uint64_t log_t0;
@@ -225,9 +233,27 @@ struct RingDesc {
     uint32_t t_end;          // no step t >= t_end is run (serving); 0xFFFFFFFF = none
     uint32_t first_item;     // index of the ring's first item in the launch
     uint32_t open;           // 1: open road (entry at cell 0, exit after cell L-1)
+    uint32_t nw;             // words per bit plane, ceil(L / 32)
+    uint32_t pad;
     SlowParams sp;
     uint64_t thr_in, thr_out;  // open road: gate thresholds floor(alpha 2^32), floor(beta 2^32)
 };
+
+// One conversion between the byte and bit-plane forms of a road (see
+// RingDesc); ConvChunk names kConvChunk consecutive words of one job.
+struct ConvJob {
+    uint8_t* bytes;
+    uint32_t* planes;
+    uint32_t L, nw, vmax, pad;
+};
+struct ConvChunk {
+    uint32_t job;
+    uint32_t first;
+};
+constexpr uint32_t kConvChunk = 256;
+
+// Words of the bit planes of a road of L cells.
+__host__ __device__ inline uint32_t plane_words(uint64_t L) { return (uint32_t)((L + 31) / 32); }
 
 // Initial placement of one ring: cars [0, N) scattered into g (already EMPTY).
 struct InitRing {

@@ -43,8 +43,12 @@ struct nasch_sim {
     uint64_t t = 0;
     uint32_t parity = 0;
     Clock* d_clk = nullptr;
-    // grid representation
+    // grid representation: bytes (one-step kernel, snapshots) and bit planes
+    // (temporal-blocked kernel); the current state is at index `parity` in the
+    // forms marked valid
     uint8_t* grid[2] = {nullptr, nullptr};
+    uint32_t* planes[2] = {nullptr, nullptr};
+    bool bytes_ok = true, planes_ok = false;
     GridEngine eng;           // one ring, its tiles
     RingDesc* d_onestep = nullptr;  // the same ring for the one-step kernel
     uint32_t* os_partials = nullptr;   // one-step / agent F(t) partials
@@ -72,6 +76,22 @@ struct nasch_sim {
     int enqueue_steps(uint64_t T);
     int set_tuning(uint32_t kern, uint32_t kk, uint32_t qq);
     const uint8_t* current_grid_device();
+    ConvJob conv_job() const {
+        return ConvJob{grid[parity], planes[parity], (uint32_t)L, plane_words(L), vmax, 0u};
+    }
+    // make the bit planes (or the bytes) of the current state valid
+    bool need_planes() {
+        if (planes_ok) return true;
+        if (!ok(launch_bytes_to_planes_one(conv_job(), stream))) return false;
+        planes_ok = true;
+        return true;
+    }
+    bool need_bytes() {
+        if (bytes_ok) return true;
+        if (!ok(launch_planes_to_bytes_one(conv_job(), stream))) return false;
+        bytes_ok = true;
+        return true;
+    }
     // Captured graphs bake the partials pointer in: a new buffer drops them.
     int ensure_os_partials(size_t n) {
         if (n <= os_partials_cap) return NASCH_OK;
@@ -92,8 +112,8 @@ nasch_sim::~nasch_sim() {
     graphs.clear();
     eng.release();
     // agent_grid aliases grid[0]
-    void* ps[] = {d_clk, grid[0], grid[1], d_onestep, ax[0], ax[1], av[0], av[1], d_agent, flux,
-                  os_partials, d_zero, mlcg_pow};
+    void* ps[] = {d_clk, grid[0], grid[1], planes[0], planes[1], d_onestep, ax[0], ax[1], av[0],
+                  av[1], d_agent, flux, os_partials, d_zero, mlcg_pow};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -185,6 +205,8 @@ int nasch_sim::set_tuning(uint32_t kern, uint32_t kk, uint32_t qq) {
 
 // The launches of T steps followed by the clock update (not synchronised).
 int nasch_sim::enqueue_steps(uint64_t T) {
+    const bool grid_kstep = rep == NASCH_REP_GRID && kernel != NASCH_KERNEL_ONESTEP;
+    if (rep == NASCH_REP_GRID && !(grid_kstep ? need_planes() : need_bytes())) return fail();
     auto body = [&]() -> hipError_t {
         uint32_t nl = 0;
         if (rep == NASCH_REP_GRID) {
@@ -244,11 +266,15 @@ int nasch_sim::enqueue_steps(uint64_t T) {
     else nl = (uint32_t)((T + k - 1) / k);
     t += T;
     parity ^= nl & 1u;
+    if (rep == NASCH_REP_GRID) {
+        planes_ok = grid_kstep;
+        bytes_ok = !grid_kstep;
+    }
     return NASCH_OK;
 }
 
 const uint8_t* nasch_sim::current_grid_device() {
-    if (rep == NASCH_REP_GRID) return grid[parity];
+    if (rep == NASCH_REP_GRID) return need_bytes() ? grid[parity] : nullptr;
     if (!ok(launch_agent_to_grid(ax[parity], av[parity], (uint32_t)N, agent_grid, (uint32_t)L,
                                  stream)))
         return nullptr;
@@ -361,11 +387,17 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
     h->dev_bytes += L;
 
     if (o.rep == NASCH_REP_GRID) {
-        if (!h->ok(dev_alloc(&h->grid[1], L))) return NASCH_ENOMEM;
-        h->dev_bytes += L;
+        const uint64_t pw = (uint64_t)(vmax + 1) * plane_words(L);
+        if (!h->ok(dev_alloc(&h->grid[1], L)) || !h->ok(dev_alloc(&h->planes[0], pw)) ||
+            !h->ok(dev_alloc(&h->planes[1], pw)))
+            return NASCH_ENOMEM;
+        h->dev_bytes += L + 8 * pw;
         RingDesc r{};
         r.buf[0] = h->grid[0];
         r.buf[1] = h->grid[1];
+        r.pl[0] = h->planes[0];
+        r.pl[1] = h->planes[1];
+        r.nw = plane_words(L);
         r.L = (uint32_t)L;
         r.vmax = vmax;
         r.sp = sp;
@@ -557,6 +589,8 @@ int nasch_restore(nasch_sim* h, const uint8_t* grid, uint64_t t) {
     if (!h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
     h->parity = 0;
     h->t = t;
+    h->bytes_ok = true;    // the restored bytes go to grid[0]; the planes follow on demand
+    h->planes_ok = false;
     const Clock c{(uint32_t)t, 0u};
     if (!h->ok(hipMemcpyAsync(h->d_clk, &c, sizeof(Clock), hipMemcpyHostToDevice, h->stream)))
         return NASCH_EDEVICE;
@@ -647,7 +681,7 @@ extern "C" int nasch_autotune(nasch_sim* h) {
         double cups = 0;
         RingDesc cur = h->eng.rings[0];
         std::vector<RingDesc> rs{cur};
-        if (!h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
+        if (!h->need_planes() || !h->ok(hipStreamSynchronize(h->stream))) return NASCH_EDEVICE;
         if (!h->ok(autotune_grid(rs, (uint32_t)h->t, h->parity, 256, h->stream, &bk, &bq, &cups)))
             return NASCH_EDEVICE;
         if (!bk) return NASCH_EINVAL;

@@ -93,13 +93,20 @@ struct Job {
     bool cancelled = false;
 };
 
-// Device bytes of one slot: two grids and the flux log, each rounded to 256 bytes.
 // Launches run back to back before the host looks at the slots again.
 constexpr uint32_t kMaxBurst = 8;
 
-uint64_t footprint(const nasch_request& r) {
-    return 2 * ((r.L + 255) / 256 * 256) + (8 * r.T + 255) / 256 * 256;
+// Layout of one slot: the byte grid (initial placement, final snapshot), two
+// bit-plane buffers (the state the kernel steps), the flux log; each rounded
+// up to 256 bytes.
+uint64_t grid_bytes(const nasch_request& r) { return (r.L + 255) / 256 * 256; }
+uint64_t plane_bytes(const nasch_request& r) {
+    return ((uint64_t)(r.vmax + 1) * plane_words(r.L) * 4u + 255) / 256 * 256;
 }
+uint64_t footprint(const nasch_request& r) {
+    return grid_bytes(r) + 2 * plane_bytes(r) + (8 * r.T + 255) / 256 * 256;
+}
+uint64_t log_offset(const nasch_request& r) { return grid_bytes(r) + 2 * plane_bytes(r); }
 
 }  // namespace
 
@@ -139,9 +146,12 @@ bool nasch_server::admit_one(Job& j) {
     if (!arena.alloc(j.bytes, &j.off)) return false;
     uint8_t* base = arena_base + j.off;
     const SlowParams sp = slow_params(r.seed, r.replica, r.p);
+    const ConvJob job{base, reinterpret_cast<uint32_t*>(base + grid_bytes(r)), (uint32_t)r.L,
+                      plane_words(r.L), r.vmax, 0u};
     if (!st.ok(launch_init_grid(base, (uint32_t)r.L, (uint32_t)r.N, r.vmax, r.init_v, sp, stream)) ||
-        !st.ok(launch_fill_u64(reinterpret_cast<unsigned long long*>(base + 2 * ((r.L + 255) / 256 * 256)),
-                               r.T, stream))) {
+        !st.ok(launch_bytes_to_planes_one(job, stream)) ||
+        !st.ok(launch_fill_u64(reinterpret_cast<unsigned long long*>(base + log_offset(r)), r.T,
+                               stream))) {
         arena.release(j.off, j.bytes);
         return false;
     }
@@ -211,13 +221,16 @@ void nasch_server::loop() {
         for (size_t i = 0; i < running.size(); ++i) {
             const Job& j = *running[i];
             const nasch_request& r = j.req;
-            const uint64_t sz = (r.L + 255) / 256 * 256;
+            uint8_t* base = arena_base + j.off;
             RingDesc& d = eng.rings[i];
             if (dirty) {
                 d = RingDesc{};
-                d.buf[0] = arena_base + j.off;
-                d.buf[1] = arena_base + j.off + sz;
-                d.flux_log = reinterpret_cast<unsigned long long*>(arena_base + j.off + 2 * sz);
+                d.buf[0] = base;
+                d.buf[1] = nullptr;
+                d.pl[0] = reinterpret_cast<uint32_t*>(base + grid_bytes(r));
+                d.pl[1] = reinterpret_cast<uint32_t*>(base + grid_bytes(r) + plane_bytes(r));
+                d.nw = plane_words(r.L);
+                d.flux_log = reinterpret_cast<unsigned long long*>(base + log_offset(r));
                 d.flux_acc = nullptr;
                 d.log_t0 = 0;
                 d.warmup = ~0ull;
@@ -264,16 +277,22 @@ void nasch_server::loop() {
             }
             dirty = true;
             const nasch_request& r = j.req;
-            const uint64_t sz = (r.L + 255) / 256 * 256;
+            uint8_t* base = arena_base + j.off;
             flux_host.resize(r.T);
             int status = NASCH_OK;
-            if (!st.ok(hipMemcpyAsync(flux_host.data(), arena_base + j.off + 2 * sz, r.T * 8,
+            if (!st.ok(hipMemcpyAsync(flux_host.data(), base + log_offset(r), r.T * 8,
                                       hipMemcpyDeviceToHost, stream)))
                 status = NASCH_EDEVICE;
-            if (!status && r.grid_out &&
-                !st.ok(hipMemcpyAsync(r.grid_out, arena_base + j.off + (j.parity ? sz : 0), r.L,
-                                      hipMemcpyDeviceToHost, stream)))
-                status = NASCH_EDEVICE;
+            if (!status && r.grid_out) {
+                // the final planes into the slot's byte grid, then to the host
+                const ConvJob job{base,
+                                  reinterpret_cast<uint32_t*>(base + grid_bytes(r) +
+                                                              (j.parity ? plane_bytes(r) : 0)),
+                                  (uint32_t)r.L, plane_words(r.L), r.vmax, 0u};
+                if (!st.ok(launch_planes_to_bytes_one(job, stream)) ||
+                    !st.ok(hipMemcpyAsync(r.grid_out, base, r.L, hipMemcpyDeviceToHost, stream)))
+                    status = NASCH_EDEVICE;
+            }
             if (!status && !st.ok(hipStreamSynchronize(stream))) status = NASCH_EDEVICE;
             uint64_t sum = 0;
             for (uint64_t f : flux_host) sum += f;

@@ -12,6 +12,12 @@ from paper_2309_14311_amd import NaschError, Server, Sim, workloads
 pytestmark = pytest.mark.gpu
 
 
+def _footprint(r):
+    """Device bytes of one request's slot, as nasch_server_submit documents it."""
+    c256 = lambda n: (n + 255) // 256 * 256
+    return c256(r["L"]) + 2 * c256(4 * (r["vmax"] + 1) * ((r["L"] + 31) // 32)) + c256(8 * r["T"])
+
+
 def _oracle(r):
     g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
                           init_v=r["init_v"])
@@ -48,7 +54,7 @@ def test_results_match_oracle():
 def test_alone_equals_in_mix_and_queueing_under_small_budget():
     reqs = workloads.requests(60, seed=4, L_exp=(3.0, 5.0), T_exp=(1.5, 3.0))
     # budget fits a few requests only: the rest must wait, not fail
-    budget = 6 * max(2 * ((r["L"] + 255) // 256 * 256) + 8 * r["T"] + 256 for r in reqs)
+    budget = 6 * max(_footprint(r) for r in reqs)
     srv = Server(k=32, hbm_budget=budget)
     ids = [srv.submit(r["L"], r["N"], r["vmax"], r["p"], r["seed"], r["T"], init_v=r["init_v"],
                       want_grid=True) for r in reqs]

@@ -199,6 +199,41 @@ def test_steps_up_to_the_last_step_number(rep, kernel):
         s.close()
 
 
+@pytest.mark.parametrize("boundary", ["ring", "open"])
+def test_switching_kernels_mid_run(boundary):
+    """The temporal-blocked kernel keeps the road as bit planes, the one-step
+    kernel and the snapshots as bytes: switching kernels and taking snapshots
+    between launches converts between the two without changing the run."""
+    L, N, vmax, p, seed, alpha, beta = 70001, 20000, 5, 0.3, 9, 0.4, 0.7
+    g0 = oracle.init_grid(L, N, vmax, seed, init_v=1)
+    if boundary == "ring":
+        run = lambda g, T, t0: oracle.run_grid(g, vmax, p, seed, T, t0=t0)
+        s = Sim(L, N, vmax, p, seed, init_v=1, kernel="kstep", k=16, use_graph=True)
+    else:
+        run = lambda g, T, t0: oracle.run_open(g, vmax, p, alpha, beta, seed, T, t0=t0)[:2]
+        s = Sim(L, N, vmax, p, seed, init_v=1, kernel="kstep", k=16, use_graph=True,
+                boundary="open", alpha=alpha, beta=beta)
+    try:
+        g, t, fluxes = g0, 0, []
+        for kernel, k, q, T, snap in [("kstep", 16, 0, 50, False), ("onestep", 0, 0, 30, True),
+                                      ("kstep", 0, 0, 100, True), ("kstep", 7, 1, 60, False),
+                                      ("onestep", 0, 0, 25, False), ("kstep", 32, 2, 35, True)]:
+            s.set_tuning(kernel, k=k, q=q)
+            s.step(T)
+            g, f = run(g, T, t)
+            fluxes.append(f)
+            t += T
+            if snap:
+                got, tt = s.snapshot()
+                assert tt == t
+                np.testing.assert_array_equal(got, g)
+        got, _ = s.snapshot()
+        np.testing.assert_array_equal(got, g)
+        np.testing.assert_array_equal(s.flux(0, t), np.concatenate(fluxes))
+    finally:
+        s.close()
+
+
 def test_invalid_arguments_are_rejected():
     for args in [(0, 0, 5, 0.1), (10, 11, 5, 0.1), (10, 5, 9, 0.1), (10, 5, 5, 1.0),
                  (10, 5, 5, -0.1), (10, 5, 5, float("nan")), (2**31, 5, 5, 0.1)]:
