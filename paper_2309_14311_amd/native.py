@@ -142,7 +142,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError(f"libnasch.so not built ({path}); run __graft_entry__.build()")
+        raise RuntimeError(f"libnasch.so not built ({path}); run python -m paper_2309_14311_amd.build")
     import torch  # noqa: F401  (shares its libamdhip64 with the library)
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():

@@ -11,7 +11,7 @@ CLI = os.path.join(os.path.dirname(os.path.abspath(__file__)), "nasch_traffic")
 def main(argv=None) -> int:
     argv = sys.argv[1:] if argv is None else argv
     if not os.path.exists(CLI):
-        print(f"{CLI} is not built; run __graft_entry__.build()", file=sys.stderr)
+        print(f"{CLI} is not built; run python -m paper_2309_14311_amd.build", file=sys.stderr)
         return 2
     return subprocess.run([CLI, *argv]).returncode
 

@@ -10,7 +10,7 @@ import math
 import numpy as np
 
 # The paper's reference test case (Figure 1 caption): 200 cars, L = 1000,
-# p = 0.13, vmax = 5; T and the seed are this build's choice.
+# p = 0.13, vmax = 5; T and the seed are chosen here.
 REFERENCE = dict(L=1000, N=200, vmax=5, p=0.13, seed=1, replica=0, init_v=0, T=2000)
 
 # One large ring (grid form), density 0.2, N = floor(0.2 L).
