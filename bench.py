@@ -73,13 +73,19 @@ def cpu_baseline_ensemble(reps, budget_s=15.0, steps=100):
         g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
                               init_v=r["init_v"])
         t0 = time.perf_counter()
-        oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], steps, replica=r["replica"],
-                        nthreads=nthreads)
+        if r.get("boundary") == "open":   # the serial open-road step (no threaded twin)
+            oracle.run_open(g0, r["vmax"], r["p"], r["alpha"], r["beta"], r["seed"], steps,
+                            replica=r["replica"])
+        else:
+            oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], steps, replica=r["replica"],
+                            nthreads=nthreads)
         spent += time.perf_counter() - t0
         done_cells += r["L"] * steps
         n += 1
         if spent >= budget_s:
             break
+    if any(r.get("boundary") == "open" for r in reps):
+        nthreads = 1
     return {"value": done_cells / spent, "unit": "cell-updates/s", "cores": nthreads,
             "kind": "oracle",
             "sample": f"first {n} of {len(reps)} replicas, {steps} steps each from t=0, "
@@ -90,7 +96,8 @@ def bench_ensemble(args):
     import torch
     from paper_2309_14311_amd import Batch, Sim, workloads
 
-    reps = workloads.ensemble(args.replicas, seed=1, T=args.T, warmup=args.warmup_steps)
+    make = workloads.open_ensemble if args.workload == "open_ensemble" else workloads.ensemble
+    reps = make(args.replicas, seed=1, T=args.T, warmup=args.warmup_steps)
     cells = sum(r["L"] for r in reps)
     _log(f"ensemble: {len(reps)} replicas, sum L = {cells:.4g}, T = {args.T}")
     b = Batch(reps, use_graph=True)
@@ -124,7 +131,8 @@ def bench_ensemble(args):
     value = cell_updates / (ms_per_step * 1e-3)
     kernel_ms = float(np.mean(step_ms)) / launches      # average k-step launch
     achieved = BYTES_PER_CELL_UPDATE * cell_updates / launches / (kernel_ms * 1e-3)
-    traffic = _traffic(k, q, cells * k)
+    is_open = args.workload == "open_ensemble"
+    traffic = None if is_open else _traffic(k, q, cells * k)   # counters cover the ring kernel
 
     extra = {"batched_kernel_cups": cell_updates / (np.mean(step_ms) * 1e-3),
              "k": k, "q": q, "launches_per_pass": launches,
@@ -136,7 +144,9 @@ def bench_ensemble(args):
         sample = reps[::args.plain_stride]
         stream = torch.cuda.Stream()
         sims = [Sim(r["L"], r["N"], r["vmax"], r["p"], r["seed"], replica=r["replica"],
-                    init_v=r["init_v"], stream=stream, use_graph=True) for r in sample]
+                    init_v=r["init_v"], stream=stream, use_graph=True,
+                    boundary=r.get("boundary", "ring"), alpha=r.get("alpha", 0.0),
+                    beta=r.get("beta", 0.0)) for r in sample]
         for s in sims:
             s.reserve_log(2 * args.plain_T)
             s.step(args.plain_T)          # warm-up: captures each sim's launch graph
@@ -161,14 +171,16 @@ def bench_ensemble(args):
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": f"batched ensemble: {len(reps)} rings, L log-uniform "
+        "config": {"workload": ("batched open-road ensemble (alpha, beta U[0,1]): " if is_open
+                                else "batched ensemble: ") + f"{len(reps)} rings, L log-uniform "
                                f"[1e3,1e6], rho U[0.05,0.6], p in {{0,.13,.25,.5}}, vmax U{{1..8}}, "
                                f"T={args.T} ({args.warmup_steps} warm-up)",
                    "cells": cells, "T": args.T},
         "hbm_roofline_frac": value * BYTES_PER_CELL_UPDATE / HBM_PEAK,
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
-                     "kernel": f"grid_kstep_mixed_kernel<{q}>", "kernel_ms": kernel_ms},
+                     "kernel": f"grid_kstep_mixed_kernel<{q}, {'true' if is_open else 'false'}>",
+                     "kernel_ms": kernel_ms},
         "extra": extra,
     }
     if not args.no_cpu:
@@ -302,7 +314,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ensemble",
                     choices=["ensemble", "large_ring", "agent", "reference", "serving",
-                             "open_road"])
+                             "open_road", "open_ensemble"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate-frac", type=float, default=0.5)
     ap.add_argument("--replicas", type=int, default=4096)
@@ -327,7 +339,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     from paper_2309_14311_amd import workloads
-    if args.workload == "ensemble":
+    if args.workload in ("ensemble", "open_ensemble"):
         line = bench_ensemble(args)
     elif args.workload == "serving":
         line = bench_serving(args)

@@ -237,8 +237,12 @@ typedef struct {
     double   p;
     uint64_t seed;
     uint32_t replica;  /* Philox stream id of this replica */
-    uint32_t reserved;
+    uint32_t reserved; /* must be 0 */
     uint64_t warmup;   /* F(t) is summed for t >= warmup */
+    uint32_t boundary; /* NASCH_BOUNDARY_RING or NASCH_BOUNDARY_OPEN (same for every replica) */
+    uint32_t reserved2;/* must be 0 */
+    double   alpha;    /* open road: entry probability per step, 0 <= alpha <= 1 */
+    double   beta;     /* open road: exit probability per step, 0 <= beta <= 1 */
 } nasch_replica;
 
 typedef struct {
@@ -253,7 +257,8 @@ typedef struct {
 void nasch_batch_default_opts(nasch_batch_opts* opts);
 
 /* Create R >= 1 replicas (each validated as in nasch_init) in one device
- * arena, all at t = 0. */
+ * arena, all at t = 0.  The replicas are all rings or all open roads
+ * (NASCH_EINVAL otherwise); vmax, p and the gate probabilities may differ. */
 int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
                      const nasch_batch_opts* opts);
 

@@ -93,9 +93,16 @@ int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
     if (opts) o = *opts;
     if (o.keep_log && o.log_steps == 0) return NASCH_EINVAL;
     for (uint32_t r = 0; r < R; ++r) {
-        int rc = validate_params(reps[r].L, reps[r].N, reps[r].vmax, reps[r].p);
+        const nasch_replica& p = reps[r];
+        int rc = validate_params(p.L, p.N, p.vmax, p.p);
         if (rc) return rc;
-        if (reps[r].init_v > NASCH_INIT_V_UNIFORM) return NASCH_EINVAL;
+        if (p.init_v > NASCH_INIT_V_UNIFORM || p.reserved || p.reserved2 ||
+            p.boundary > NASCH_BOUNDARY_OPEN || p.boundary != reps[0].boundary)
+            return NASCH_EINVAL;
+        // gate probabilities in [0, 1] (NaN fails both comparisons)
+        if (p.boundary == NASCH_BOUNDARY_OPEN &&
+            !(p.alpha >= 0.0 && p.alpha <= 1.0 && p.beta >= 0.0 && p.beta <= 1.0))
+            return NASCH_EINVAL;
     }
     std::unique_ptr<nasch_batch> b(new (std::nothrow) nasch_batch());
     if (!b) return NASCH_ENOMEM;
@@ -153,6 +160,11 @@ int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
         d.vmax = p.vmax;
         d.t_end = 0xFFFFFFFFu;
         d.sp = slow_params(p.seed, p.replica, p.p);
+        if (p.boundary == NASCH_BOUNDARY_OPEN) {
+            d.open = 1u;
+            d.thr_in = (uint64_t)std::floor(std::ldexp(p.alpha, 32));
+            d.thr_out = (uint64_t)std::floor(std::ldexp(p.beta, 32));
+        }
         b->eng.rings.push_back(d);
         vmax_all = std::max(vmax_all, p.vmax);
         init_rings.push_back(InitRing{d.buf[0], (uint32_t)p.L, (uint32_t)p.N, p.vmax, p.init_v,

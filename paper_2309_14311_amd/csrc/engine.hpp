@@ -160,7 +160,7 @@ struct GridEngine {
             vmaxx = std::max(vmaxx, r.vmax);
             n_open += r.open ? 1u : 0u;
         }
-        if (n_open != 0 && (n_open != rings.size() || vmin != vmaxx)) return hipErrorInvalidValue;
+        if (n_open != 0 && n_open != rings.size()) return hipErrorInvalidValue;   // all or none
         launch_open = n_open != 0;
         for (uint32_t ri : order) {
             rings[ri].first_item = (uint32_t)items.size();

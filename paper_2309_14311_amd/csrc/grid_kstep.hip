@@ -436,8 +436,8 @@ __global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restr
 }
 
 // Items of different vmax in one launch: the branch on the ring's vmax is
-// uniform over the wave.
-template <int Q>
+// uniform over the wave.  OPEN: every ring of the launch is an open road.
+template <int Q, bool OPEN>
 __global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* __restrict__ rings,
                                                                const TileItem* __restrict__ items,
                                                                uint32_t n_items, uint32_t* partials,
@@ -454,15 +454,15 @@ __global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* _
     const uint32_t lane = threadIdx.x & 63u;
     RefineLds<Q>& rl = s_ref[wib];
     switch (R.vmax) {
-        case 0: kstep_tile<0, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 1: kstep_tile<1, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 2: kstep_tile<2, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 3: kstep_tile<3, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 4: kstep_tile<4, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 5: kstep_tile<5, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 6: kstep_tile<6, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 7: kstep_tile<7, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 8: kstep_tile<8, Q, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 0: kstep_tile<0, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 1: kstep_tile<1, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 2: kstep_tile<2, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 3: kstep_tile<3, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 4: kstep_tile<4, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 5: kstep_tile<5, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 6: kstep_tile<6, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 7: kstep_tile<7, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 8: kstep_tile<8, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
         default: break;
     }
 }
@@ -492,9 +492,12 @@ hipError_t launch_q(uint32_t vmax, bool open, dim3 grid, hipStream_t s, const Ri
         NASCH_KSTEP_CASE(7)
         NASCH_KSTEP_CASE(8)
         case kMixedVmax:
-            if (open) return hipErrorInvalidValue;   // open roads are single-ring launches
-            NASCH_LAUNCH((grid_kstep_mixed_kernel<Q>), grid, dim3(256), 0, s, rings, items,
-                               n_items, partials, k, clk, s_off, launch_idx);
+            if (open)
+                NASCH_LAUNCH((grid_kstep_mixed_kernel<Q, true>), grid, dim3(256), 0, s, rings,
+                             items, n_items, partials, k, clk, s_off, launch_idx);
+            else
+                NASCH_LAUNCH((grid_kstep_mixed_kernel<Q, false>), grid, dim3(256), 0, s, rings,
+                             items, n_items, partials, k, clk, s_off, launch_idx);
             break;
         default:
             return hipErrorInvalidValue;

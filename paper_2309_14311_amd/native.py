@@ -46,7 +46,8 @@ class Info(ctypes.Structure):
 
 class Replica(ctypes.Structure):
     _fields_ = [("L", U64), ("N", U64), ("vmax", U32), ("init_v", U32), ("p", DBL),
-                ("seed", U64), ("replica", U32), ("reserved", U32), ("warmup", U64)]
+                ("seed", U64), ("replica", U32), ("reserved", U32), ("warmup", U64),
+                ("boundary", U32), ("reserved2", U32), ("alpha", DBL), ("beta", DBL)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -292,6 +293,8 @@ class Batch:
             arr[i].L, arr[i].N, arr[i].vmax = r["L"], r["N"], r["vmax"]
             arr[i].init_v, arr[i].p, arr[i].seed = int(r.get("init_v", 0)), float(r["p"]), r["seed"]
             arr[i].replica, arr[i].warmup = r.get("replica", 0), r.get("warmup", 0)
+            arr[i].boundary = BOUNDARY[r.get("boundary", "ring")]
+            arr[i].alpha, arr[i].beta = float(r.get("alpha", 0.0)), float(r.get("beta", 0.0))
         o = BatchOpts()
         lib.nasch_batch_default_opts(ctypes.byref(o))
         o.stream, o.k, o.q = _stream_ptr(stream), k, q

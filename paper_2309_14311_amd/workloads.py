@@ -62,3 +62,15 @@ def requests(n: int = 2000, seed: int = 7, L_exp=(3.0, 7.0), T_exp=(2.0, 4.0),
         out.append(dict(arrival=t, L=L, N=int(math.floor(rho * L)), vmax=vmax, p=p,
                         seed=1000 + i, replica=0, init_v=1, T=T))
     return out
+
+
+def open_ensemble(n_replicas: int = 4096, seed: int = 1, T: int = 5000, warmup: int = 1000):
+    """The ensemble's roads opened at both ends, for a parameter study over the
+    gates: entry and exit probabilities drawn uniformly from [0, 1]."""
+    reps = ensemble(n_replicas, seed=seed, T=T, warmup=warmup)
+    rng = np.random.default_rng(seed + 7919)
+    for r in reps:
+        r["boundary"] = "open"
+        r["alpha"] = float(rng.random())
+        r["beta"] = float(rng.random())
+    return reps

@@ -90,3 +90,51 @@ def test_batch_rejects_bad_replicas():
         Batch([dict(L=10, N=11, vmax=5, p=0.1, seed=1)])
     with pytest.raises(NaschError):
         Batch([dict(L=10, N=5, vmax=5, p=1.5, seed=1)])
+
+
+def _open_ensemble(n, seed):
+    """Open roads for a parameter study: the small ensemble's roads with entry
+    and exit probabilities drawn over [0, 1], the extremes included."""
+    rng = np.random.default_rng(seed)
+    reps = _small_ensemble(n, seed=seed)
+    for i, r in enumerate(reps):
+        r["boundary"] = "open"
+        r["alpha"] = float(rng.choice([0.0, 1.0, rng.random()]))
+        r["beta"] = float(rng.choice([0.0, 1.0, rng.random()]))
+    return reps
+
+
+@pytest.mark.parametrize("k,q", [(16, 2), (7, 1), (32, 4)])
+def test_open_road_ensemble_matches_oracle(k, q):
+    """A batch of open roads (mixed vmax, p, alpha, beta, ragged and tiny L):
+    every replica's log, flux sum and final road equal the oracle's."""
+    reps = _open_ensemble(40, seed=21)
+    T = 220
+    b = Batch(reps, k=k, q=q, keep_log=True, log_steps=T, use_graph=True)
+    try:
+        b.step(100)
+        b.step(T - 100)
+        sums = b.flux_sums()
+        for i, r in enumerate(reps):
+            g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
+                                  init_v=r["init_v"])
+            g, flux, _, _ = oracle.run_open(g0, r["vmax"], r["p"], r["alpha"], r["beta"],
+                                            r["seed"], T, replica=r["replica"])
+            got, t = b.snapshot(i)
+            assert t == T
+            np.testing.assert_array_equal(got, g, err_msg=f"replica {i} {r}")
+            np.testing.assert_array_equal(b.flux(i, 0, T), flux)
+            assert int(sums[i]) == int(flux[r["warmup"]:].sum())
+    finally:
+        b.close()
+
+
+def test_open_and_ring_replicas_do_not_mix():
+    reps = _small_ensemble(4, seed=2)
+    reps[1].update(boundary="open", alpha=0.5, beta=0.5)
+    with pytest.raises(NaschError):
+        Batch(reps)
+    bad = _open_ensemble(3, seed=4)
+    bad[2]["alpha"] = float("nan")
+    with pytest.raises(NaschError):
+        Batch(bad)
