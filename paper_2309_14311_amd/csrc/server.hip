@@ -128,7 +128,9 @@ struct nasch_server {
     std::deque<nasch_result> done;
     std::vector<uint64_t> cancel_ids;
     uint64_t next_id = 1;
-    uint64_t n_done = 0, launches = 0;
+    uint64_t n_done = 0;
+    // read by nasch_server_stats while the scheduling thread runs
+    std::atomic<uint64_t> n_running{0}, launches{0};
     bool stop = false;
     std::thread worker;
 
@@ -136,14 +138,15 @@ struct nasch_server {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     void loop();
-    bool admit_one(Job& j);
+    enum class Admit { ok, no_room, device_error };
+    Admit admit_one(Job& j);
     void finish(std::unique_ptr<Job> j, int status, uint64_t flux_sum);
 };
 
-bool nasch_server::admit_one(Job& j) {
+nasch_server::Admit nasch_server::admit_one(Job& j) {
     const nasch_request& r = j.req;
     j.bytes = footprint(r);
-    if (!arena.alloc(j.bytes, &j.off)) return false;
+    if (!arena.alloc(j.bytes, &j.off)) return Admit::no_room;
     uint8_t* base = arena_base + j.off;
     const SlowParams sp = slow_params(r.seed, r.replica, r.p);
     const ConvJob job{base, reinterpret_cast<uint32_t*>(base + grid_bytes(r)), (uint32_t)r.L,
@@ -153,12 +156,13 @@ bool nasch_server::admit_one(Job& j) {
         !st.ok(launch_fill_u64(reinterpret_cast<unsigned long long*>(base + log_offset(r)), r.T,
                                stream))) {
         arena.release(j.off, j.bytes);
-        return false;
+        j.bytes = 0;
+        return Admit::device_error;
     }
     j.t = 0;
     j.parity = 0;
     j.t_admit = now();
-    return true;
+    return Admit::ok;
 }
 
 void nasch_server::finish(std::unique_ptr<Job> j, int status, uint64_t flux_sum) {
@@ -183,7 +187,7 @@ void nasch_server::loop() {
     for (;;) {
         // ---- admission and cancellation
         std::vector<std::unique_ptr<Job>> admitted;
-        std::vector<std::unique_ptr<Job>> cancelled_pending;
+        std::vector<std::unique_ptr<Job>> cancelled_pending, failed;
         std::vector<uint64_t> cancels;
         bool waiting;
         {
@@ -202,15 +206,18 @@ void nasch_server::loop() {
             }
             while (!pending.empty() && running.size() + admitted.size() < opts.max_slots) {
                 Job& j = *pending.front();
-                if (!admit_one(j)) break;   // head of line waits for memory
-                admitted.push_back(std::move(pending.front()));
+                const Admit a = admit_one(j);
+                if (a == Admit::no_room) break;   // head of line waits for memory
+                (a == Admit::ok ? admitted : failed).push_back(std::move(pending.front()));
                 pending.pop_front();
             }
             waiting = !pending.empty();
         }
         for (auto& j : cancelled_pending) finish(std::move(j), NASCH_ESTATE, 0);
+        for (auto& j : failed) finish(std::move(j), NASCH_EDEVICE, 0);
         if (!admitted.empty()) dirty = true;
         for (auto& j : admitted) running.push_back(std::move(j));
+        n_running = running.size();
         for (uint64_t id : cancels)
             for (auto& j : running)
                 if (j && j->id == id) j->cancelled = true;
@@ -255,6 +262,7 @@ void nasch_server::loop() {
             // a device failure ends every running request with an error
             for (auto& j : running) finish(std::move(j), NASCH_EDEVICE, 0);
             running.clear();
+            n_running = 0;
             dirty = true;
             continue;
         }
@@ -300,6 +308,7 @@ void nasch_server::loop() {
             finish(std::move(jp), status, sum);
         }
         running.swap(still);
+        n_running = running.size();
     }
 }
 
@@ -321,7 +330,7 @@ int nasch_server_create(nasch_server** out, const nasch_server_opts* opts) {
     if (!o.max_slots) o.max_slots = 4096;
     if (!o.k) o.k = 32;
     if (!o.q) o.q = 4;
-    if (o.q != 1 && o.q != 2 && o.q != 4) return NASCH_EINVAL;
+    if (o.q > 4) return NASCH_EINVAL;
     if (kstep_max_k(NASCH_MAX_VMAX, o.q) < o.k) return NASCH_EINVAL;
     if (!o.hbm_budget) {
         size_t fr = 0, tot = 0;
@@ -402,7 +411,7 @@ int nasch_server_stats(nasch_server* s, uint64_t* pending, uint64_t* running, ui
     if (!s) return NASCH_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
     if (pending) *pending = s->pending.size();
-    if (running) *running = s->running.size();
+    if (running) *running = s->n_running;
     if (done) *done = s->n_done;
     if (bytes_in_use) *bytes_in_use = s->arena.used();
     if (launches) *launches = s->launches;
