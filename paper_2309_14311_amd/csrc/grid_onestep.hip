@@ -4,9 +4,12 @@
 //
 // Each thread owns 32 consecutive cells (one aligned rule-3 block, so one
 // Philox call covers them).  It builds the occupancy mask of its cells and the
-// 8 after them, visits its cars through the mask (the distance to the car in
-// front is a trailing-zero count), and scatters each car into a cleared LDS
-// copy of the tile.  Cars up to vmax cells left of the tile can land inside
+// 8 after them and decides rule 3 for all its cars at once: the block's top
+// nibbles are compared with thr's, and the cars whose nibble ties are numbered
+// across the wave and have their low 28 bits drawn 64 at a time, so no car
+// loop ever runs a Philox call.  It then visits its cars through the mask (the
+// distance to the car in front is a trailing-zero count) and scatters each car
+// into a cleared LDS copy of the tile.  Cars up to vmax cells left of the tile can land inside
 // it; lanes 0..vmax-1 recompute those.  The tile is then written back with
 // 16-byte stores.  F(t) counts owned cars only.
 //
@@ -44,6 +47,53 @@ __device__ __forceinline__ uint32_t nibble(const Word4& w, uint32_t j) {
     return (((w.w0 >> j) & 1u) << 3) | (((w.w1 >> j) & 1u) << 2) | (((w.w2 >> j) & 1u) << 1) |
            ((w.w3 >> j) & 1u);
 }
+
+// LDS of one wave for the tied cars of its 64 words.
+constexpr uint32_t kTieCap = 256;
+struct TieLds {
+    uint32_t code[kTieCap];   // lane << 5 | bit of each queued car
+    uint32_t x0[64];          // first cell of each lane's word
+    uint32_t slow[64];        // slow cars found by the draws, per lane
+};
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The slow cars among `tie` (cars of cells x0 .. x0+31 whose top nibble of R
+// equals thr's): decided by the low 28 bits of R.  Numbered with a wave prefix
+// sum and drawn 64 at a time; cars beyond the queue's capacity are drawn by
+// their own lane.  All 64 lanes of the wave must call it.
+__device__ __forceinline__ uint32_t resolve_ties(uint32_t tie, uint32_t x0, uint32_t t,
+                                                 const SlowParams& sp, TieLds& lds,
+                                                 uint32_t lane) {
+    const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
+    const uint32_t cnt = __popc(tie);
+    const uint32_t incl = wave_scan_incl(cnt);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    if (total == 0u) return 0u;
+    const uint32_t nq = min(total, kTieCap);
+    lds.x0[lane] = x0;
+    lds.slow[lane] = 0u;
+    uint32_t idx = incl - cnt, own = 0u;
+    while (tie) {
+        const uint32_t b = __builtin_ctz(tie);
+        tie &= tie - 1u;
+        if (idx < kTieCap) lds.code[idx] = (lane << 5) | b;
+        else if (slow_lo28(x0 + b, t, sp) < lo_thr) own |= 1u << b;
+        ++idx;
+    }
+    wave_sync_lds();
+    for (uint32_t p = lane; p < nq; p += 64u) {
+        const uint32_t c = lds.code[p];
+        if (slow_lo28(lds.x0[c >> 5] + (c & 31u), t, sp) < lo_thr)
+            atomicOr(&lds.slow[c >> 5], 1u << (c & 31u));
+    }
+    wave_sync_lds();
+    return own | lds.slow[lane];
+}
 }  // namespace
 
 // F(t) of the tile goes to partials[blockIdx.x] (summed by the fold kernel).
@@ -55,6 +105,7 @@ __global__ __launch_bounds__(kThreads) void grid_onestep_kernel(const RingDesc* 
     __shared__ __align__(16) uint8_t s_in[kTile + 2 * kHalo];
     __shared__ __align__(16) uint8_t s_out[kTile];
     __shared__ uint32_t s_flux[kThreads / 64];
+    __shared__ TieLds s_tie[kThreads / 64];
 
     const RingDesc& R = *ring;
     const uint32_t L = R.L, vmax = R.vmax;
@@ -105,31 +156,38 @@ __global__ __launch_bounds__(kThreads) void grid_onestep_kernel(const RingDesc* 
     // ---- owned cars: occupancy of the thread's 32 cells and the 8 after them
     uint32_t flux = 0;
     const uint32_t c0 = tid * 32u;
+    uint64_t occ = 0;
+    uint32_t cars = 0;
     if (c0 < len) {
         const uint4* in4 = reinterpret_cast<const uint4*>(s_in + kHalo + c0);
         const uint4 a = in4[0], b = in4[1];
         const uint2 c = *reinterpret_cast<const uint2*>(s_in + kHalo + c0 + 32);
         const uint32_t w[10] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y};
-        uint64_t occ = 0;
 #pragma unroll
         for (int d = 0; d < 10; ++d) occ |= (uint64_t)byte_msbs(~w[d]) << (4 * d);
         const uint32_t n = min(32u, len - c0);
-        uint32_t cars = (uint32_t)occ & (n >= 32u ? 0xFFFFFFFFu : ((1u << n) - 1u));
-        if (cars) {
-            Word4 hp{0, 0, 0, 0};
-            if (sp.thr != 0) hp = slow_hi_planes((start + c0) >> 5, t, sp);
-            while (cars) {
-                const uint32_t j = __builtin_ctz(cars);
-                cars &= cars - 1u;
-                const uint64_t ahead = occ >> (j + 1);
-                const uint32_t d = ahead ? min((uint32_t)__builtin_ctzll(ahead) + 1u, vmax + 1u)
-                                         : vmax + 1u;
-                const uint32_t v = new_velocity(s_in[kHalo + c0 + j], d, vmax, nibble(hp, j),
-                                                start + c0 + j, t, sp);
-                if (c0 + j + v < len) s_out[c0 + j + v] = (uint8_t)v;
-                flux += v;
-            }
-        }
+        cars = (uint32_t)occ & (n >= 32u ? 0xFFFFFFFFu : ((1u << n) - 1u));
+    }
+    // ---- rule 3 for every car of the block (slow = R < thr); uniform branches
+    uint32_t slow = 0u;
+    if (sp.thr != 0) {
+        uint32_t lt = 0u, eq = 0u;
+        if (cars) block_lt_eq(slow_hi_planes((start + c0) >> 5, t, sp), sp.thr >> 28, lt, eq);
+        slow = lt & cars;
+        if ((sp.thr & 0x0FFFFFFFu) != 0u)
+            slow |= resolve_ties(eq & cars, start + c0, t, sp, s_tie[tid >> 6], tid & 63u);
+    }
+    while (cars) {
+        const uint32_t j = __builtin_ctz(cars);
+        cars &= cars - 1u;
+        const uint64_t ahead = occ >> (j + 1);
+        const uint32_t d = ahead ? min((uint32_t)__builtin_ctzll(ahead) + 1u, vmax + 1u)
+                                 : vmax + 1u;
+        uint32_t v = min(s_in[kHalo + c0 + j] + 1u, vmax);   // rule 1
+        if (v >= d) v = d - 1u;                                // rule 2
+        if (v > 0 && ((slow >> j) & 1u)) --v;                  // rule 3
+        if (c0 + j + v < len) s_out[c0 + j + v] = (uint8_t)v;  // rule 4
+        flux += v;
     }
     // ---- the cars up to vmax cells left of the tile may land inside it: one lane each
     if (tid < vmax) {
