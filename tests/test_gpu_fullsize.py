@@ -135,8 +135,9 @@ def test_agent_ring_equals_grid_and_oracle_windows():
 
 def test_ensemble_in_bench_configuration():
     """The 4096-replica ensemble as the benchmark runs it (graph replay, autotuned
-    (k, q), reset between passes): the smallest replicas against the oracle in
-    full, a sample of the rest against the same replica run alone."""
+    (k, q), reset between passes): the smallest replicas, a median-size one and
+    the largest one against the oracle in full (the largest on the oracle's
+    all-core twin), a sample of the rest against the same replica run alone."""
     reps = workloads.ensemble(4096, seed=1, T=5000, warmup=1000)
     b = Batch(reps, use_graph=True)
     b.autotune()
@@ -144,12 +145,14 @@ def test_ensemble_in_bench_configuration():
     b.step(5000)
     sums = b.flux_sums()
     order = np.argsort([r["L"] for r in reps])
-    for i in order[:12]:
+    nthreads = min(16, oracle.num_threads_available())
+    for i in list(order[:12]) + [order[len(order) // 2], order[-1]]:
         r = reps[i]
         g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
                               init_v=r["init_v"])
-        g, flux = oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], 5000, replica=r["replica"])
-        np.testing.assert_array_equal(b.snapshot(i)[0], g)
+        g, flux = oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], 5000, replica=r["replica"],
+                                  nthreads=nthreads)
+        np.testing.assert_array_equal(b.snapshot(i)[0], g, err_msg=f"replica {i} L={r['L']}")
         assert int(sums[i]) == int(flux[1000:].sum())
     for i in order[::400]:
         r = reps[i]
