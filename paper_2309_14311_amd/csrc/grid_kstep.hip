@@ -73,21 +73,73 @@ __device__ __forceinline__ Word4 planes_unaligned(uint32_t x0, uint32_t t, uint3
     return r;
 }
 
+// Do the 32 ring cells x0, x0+1, ... (mod L) lie in at most two blocks: block
+// x0 >> 5 from bit x0 & 31 up to its end or the ring's end, then the ring's
+// next block from bit 0?  (Always on rings of 64 cells or more, except for a
+// word that covers a short last block whole and runs on into block 0.)
+__device__ __forceinline__ bool two_blocks(uint32_t x0, uint32_t L, uint32_t nw) {
+    const uint32_t run0 = min(32u - (x0 & 31u), L - x0);
+    if (run0 == 32u) return true;
+    const uint32_t b1 = x0 + run0 >= L ? 0u : (x0 >> 5) + 1u;
+    const uint32_t len1 = b1 + 1u == nw ? L - 32u * b1 : 32u;
+    return 32u - run0 <= len1;
+}
+
+// planes_unaligned for cells that satisfy two_blocks, in straight-line code:
+// two block draws joined by shifts.  An aligned word gets its block unchanged
+// (the second draw is then unused).
+__device__ __forceinline__ Word4 planes_two(uint32_t x0, uint32_t t, uint32_t L,
+                                            const SlowParams& sp) {
+    // The shift amounts below depend on x0 only; hoisted out of the step loop
+    // they would hold ten more registers through the whole kernel (and cost
+    // every wave occupancy).  An empty asm makes x0 opaque so they are
+    // recomputed where they are used, in the few waves that take this path.
+    __asm__ volatile("" : "+v"(x0));
+    const uint32_t off = x0 & 31u;
+    const uint32_t run0 = min(32u - off, L - x0);   // 1..32 cells from the first block
+    const uint32_t b0 = x0 >> 5;
+    const uint32_t b1 = x0 + run0 >= L ? 0u : b0 + 1u;
+    const Word4 a = slow_hi_planes(b0, t, sp);
+    const Word4 b = slow_hi_planes(b1, t, sp);
+    const uint32_t m = 0xFFFFFFFFu >> (32u - run0);
+    const uint32_t sh = run0 - 1u;   // b's bit 0 goes to bit run0 (nowhere when run0 = 32)
+    Word4 r;
+    r.w0 = ((a.w0 >> off) & m) | ((b.w0 << sh) << 1);
+    r.w1 = ((a.w1 >> off) & m) | ((b.w1 << sh) << 1);
+    r.w2 = ((a.w2 >> off) & m) | ((b.w2 << sh) << 1);
+    r.w3 = ((a.w3 >> off) & m) | ((b.w3 << sh) << 1);
+    return r;
+}
+
+// How a wave draws the top-nibble planes (uniform over the wave, fixed for a
+// launch): every word one aligned block (the interior of a ring); some words
+// across two blocks (the tiles at the end of a ring whose length is not a
+// multiple of 32); anything else (rings shorter than a segment).
+enum : uint32_t { kDrawAligned = 0, kDrawTwo = 1, kDrawGeneric = 2 };
+
 // Rule 3, first stage, for the moving cars of the lane's Q words (word q covers
 // ring cells xw[q] .. xw[q]+31, mod L): S = cars whose top nibble of R is below
 // thr's (slow), U = cars whose top nibble ties with thr's (decided by the low
-// 28 bits).  The Q block draws are independent, so their Philox chains
-// interleave; the comparison is specialised on thr's top nibble, which is
+// 28 bits).  The comparison is specialised on thr's top nibble, which is
 // uniform over the wave.
 template <int Q>
 __device__ __forceinline__ void slow_hi(const uint32_t (&moving)[Q], const uint32_t (&xw)[Q],
-                                        const bool (&aligned)[Q], uint32_t t, uint32_t L,
-                                        const SlowParams& sp, uint32_t (&S)[Q],
-                                        uint32_t (&U)[Q]) {
+                                        const bool (&aligned)[Q], uint32_t draw_mode,
+                                        uint32_t t, uint32_t L, const SlowParams& sp,
+                                        uint32_t (&S)[Q], uint32_t (&U)[Q]) {
     Word4 hp[Q];
+    if (draw_mode == kDrawAligned) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-        hp[q] = aligned[q] ? slow_hi_planes(xw[q] >> 5, t, sp) : planes_unaligned(xw[q], t, L, sp);
+        for (int q = 0; q < Q; ++q) hp[q] = slow_hi_planes(xw[q] >> 5, t, sp);
+    } else if (draw_mode == kDrawTwo) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) hp[q] = planes_two(xw[q], t, L, sp);
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            hp[q] = aligned[q] ? slow_hi_planes(xw[q] >> 5, t, sp)
+                               : planes_unaligned(xw[q], t, L, sp);
+    }
     uint32_t lt[Q], eq[Q];
 #define NASCH_NIBBLE_CASE(TH)                                             \
     case TH:                                                              \
@@ -116,8 +168,10 @@ __device__ __forceinline__ void slow_hi(const uint32_t (&moving)[Q], const uint3
 // at a time, reading the word's first ring cell from a table written once per
 // launch, and ORs each slow car into an LDS mask of its word.  Every lane then
 // takes its words' masks (and clears them for the next step): one LDS read per
-// word instead of a loop over the lane's tied cars.  Cars numbered beyond the
-// queue's capacity are drawn by their own lane.
+// word instead of a loop over the lane's tied cars.  A word rarely holds more
+// than two tied cars, so those two are queued without a loop.  When the wave
+// has more tied cars than the queue holds (possible, never seen), cars
+// numbered beyond its capacity are drawn by their own lane.
 constexpr uint32_t kRefineCap = 256;
 
 template <int Q>
@@ -147,29 +201,53 @@ __device__ __forceinline__ void slow_lo_wave(uint32_t (&S)[Q], const uint32_t (&
     if (total == 0u) return;
     const uint32_t nq = min(total, kRefineCap);
     uint32_t idx = incl - cnt;
+    if (total <= kRefineCap) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        uint32_t u = U[q];
-        const uint32_t wcode = (lane * Q + q) << 5;
-        while (u) {
-            const uint32_t b = __builtin_ctz(u);
-            u &= u - 1u;
-            if (idx < kRefineCap) {
-                lds.code[idx] = wcode | b;
-            } else {
-                uint32_t x = xw[q] + b;
-                if (x >= L) x %= L;
-                if (slow_lo28(x, t, sp) < lo_thr) S[q] |= 1u << b;
+        for (int q = 0; q < Q; ++q) {
+            const uint32_t u = U[q];
+            const uint32_t wcode = (lane * Q + q) << 5;
+            const uint32_t u1 = u & (u - 1u);
+            if (u) lds.code[idx] = wcode | __builtin_ctz(u);
+            if (u1) lds.code[idx + 1u] = wcode | __builtin_ctz(u1);
+            uint32_t r = u1 & (u1 - 1u);
+            for (uint32_t j = idx + 2u; r; ++j) {
+                lds.code[j] = wcode | __builtin_ctz(r);
+                r &= r - 1u;
             }
-            ++idx;
+            idx += __popc(u);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            uint32_t u = U[q];
+            const uint32_t wcode = (lane * Q + q) << 5;
+            while (u) {
+                const uint32_t b = __builtin_ctz(u);
+                u &= u - 1u;
+                if (idx < kRefineCap) {
+                    lds.code[idx] = wcode | b;
+                } else {
+                    uint32_t x = xw[q] + b;
+                    if (x >= L) x %= L;
+                    if (slow_lo28(x, t, sp) < lo_thr) S[q] |= 1u << b;
+                }
+                ++idx;
+            }
         }
     }
     wave_sync_lds();
+    // a word's first cell is below L, so x < L + 31: one conditional
+    // subtraction brings it into the ring unless the ring is shorter than 32
+    const bool tiny = L < 32u;
     for (uint32_t p = lane; p < nq; p += 64u) {
         const uint32_t c = lds.code[p];
         const uint32_t w = c >> 5, b = c & 31u;
         uint32_t x = lds.xw[w] + b;
-        if (x >= L) x %= L;   // a word across the end of a short ring
+        if (tiny) {
+            if (x >= L) x %= L;
+        } else {
+            x = min(x, x - L);   // x - L wraps above x unless x >= L
+        }
         if (slow_lo28(x, t, sp) < lo_thr) atomicOr(&lds.slow[w], 1u << b);
     }
     wave_sync_lds();
@@ -306,6 +384,18 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
         rl.slow[lane * Q + q] = 0u;
     }
     wave_sync_lds();
+    uint32_t draw_mode = kDrawAligned;   // open roads: every word is aligned
+    if constexpr (!OPEN) {
+        bool all_aligned = true, all_two = true;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            all_aligned = all_aligned && aligned[q];
+            all_two = all_two && two_blocks(xw[q], L, nw);
+        }
+        if (__builtin_amdgcn_ballot_w64(!all_aligned) != 0u)
+            draw_mode = (L >= 64u && __builtin_amdgcn_ballot_w64(!all_two) == 0u) ? kDrawTwo
+                                                                                 : kDrawGeneric;
+    }
 
     // ---- k steps
     uint32_t acc = 0u;
@@ -353,7 +443,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                 S[q] = 0u;
                 U[q] = 0u;
             }
-            if (sp.thr != 0u) slow_hi<Q>(moving, xw, aligned, t, L, sp, S, U);   // rule 3
+            if (sp.thr != 0u) slow_hi<Q>(moving, xw, aligned, draw_mode, t, L, sp, S, U);  // rule 3
             if ((sp.thr & 0x0FFFFFFFu) != 0u) slow_lo_wave<Q>(S, U, xw, L, t, sp, rl, lane);
             uint32_t Eq[Q][VMAX + 1];
 #pragma unroll
