@@ -4,17 +4,40 @@
 namespace nasch {
 
 // Initial grid of one ring: EMPTY everywhere, then car i < N at its placement.
-// Scatter form: one Feistel evaluation (with cycle-walking) per car.
+// Scatter form: each car's Feistel value is cycle-walked until it lands in
+// [0, L).  A car needs two walks on average but up to about seven in a wave of
+// 64, so a lane whose car has landed takes the next car of the wave's range
+// instead of idling: the wave's work is the sum of the walks, not 64 times
+// their maximum.
 __global__ __launch_bounds__(256) void init_scatter_kernel(const InitRing* __restrict__ rings,
                                                            const InitChunk* __restrict__ chunks,
                                                            InitRing single) {
     const InitChunk c = chunks ? chunks[blockIdx.x] : InitChunk{0u, blockIdx.x * kInitChunk};
     const InitRing R = chunks ? rings[c.ring] : single;
-    for (uint32_t j = threadIdx.x; j < kInitChunk; j += blockDim.x) {
-        const uint32_t i = c.first + j;
-        if (i >= R.N) break;
-        const uint32_t x = placement(i, R.L, R.b, R.sp);
-        R.g[x] = (uint8_t)(R.init_v ? initial_velocity(x, R.vmax, R.sp) : 0u);
+    constexpr uint32_t kPerWave = kInitChunk / 4;   // 256 threads: four waves
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t begin =
+        c.first + kPerWave * (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t end = min(begin + kPerWave, R.N);
+    if (begin >= end) return;   // uniform over the wave
+    const uint32_t half = R.b >> 1;
+    const uint32_t mask = (half >= 32) ? 0xFFFFFFFFu : ((1u << half) - 1u);
+    uint32_t y = begin + lane;      // the lane's car, then its walk
+    bool active = y < end;
+    uint32_t next = begin + 64u;    // first car not yet taken (uniform)
+    while (__builtin_amdgcn_ballot_w64(active) != 0u) {
+        y = feistel_fwd(y, half, mask, R.sp);
+        const bool done = active && y < R.L;
+        if (done) R.g[y] = (uint8_t)(R.init_v ? initial_velocity(y, R.vmax, R.sp) : 0u);
+        const bool take = done || !active;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(take);
+        const uint32_t rank =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (take) {
+            y = next + rank;
+            active = y < end;
+        }
+        next += (uint32_t)__popcll(m);
     }
 }
 
