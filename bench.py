@@ -32,12 +32,27 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 BYTES_PER_CELL_UPDATE = 2.0  # read 1 B + write 1 B of uint8 state per cell per step
+# 32-bit vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-operations/s)
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
 KSTEP_SRC = os.path.join(ROOT, "paper_2309_14311_amd", "csrc", "grid_kstep.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grid_kstep_ensemble.json")
 
 
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kstep_ops_per_cell_update(vmax, p):
+    """Algorithmic operations of the bit-sliced update, per cell-update: per 32-cell
+    word and step, rules 1-2 take vmax funnel shifts, vmax - 1 ORs and vmax AND-NOTs
+    (3 vmax - 1), rule 3 vmax selects, rule 4 vmax class masks, vmax shifts and
+    vmax ORs, and F(t) vmax popcounts: 8 vmax in all (with the slow-mask AND).  When
+    p > 0 the word's rule-3 block draw adds one Philox4x32-10 call (10 rounds of two
+    32x32->64 multiplies and two three-input XORs: 40) and the 4-bit comparison (4).
+    Tied cars (1 in 16 moving cars when p has bits below 2^-4) draw once more each;
+    their number depends on the state, so they are not counted."""
+    thr = int(p * 2.0 ** 32)
+    return (8 * vmax + (44 if thr > 0 else 0)) / 32.0
 
 
 def _src_hash(path):
@@ -131,6 +146,11 @@ def bench_ensemble(args):
     value = cell_updates / (ms_per_step * 1e-3)
     kernel_ms = float(np.mean(step_ms)) / launches      # average k-step launch
     achieved = BYTES_PER_CELL_UPDATE * cell_updates / launches / (kernel_ms * 1e-3)
+    # the kernel is bound by VALU issue: its roofline counts the algorithmic
+    # operations per launch (averaged like the bytes above) against the
+    # vector-ALU peak
+    ops_per_cu = sum(r["L"] * kstep_ops_per_cell_update(r["vmax"], r["p"]) for r in reps) / cells
+    ops_achieved = ops_per_cu * cell_updates / launches / (kernel_ms * 1e-3)
     is_open = args.workload == "open_ensemble"
     traffic = None if is_open else _traffic(k, q, cells * k)   # counters cover the ring kernel
 
@@ -177,10 +197,12 @@ def bench_ensemble(args):
                                f"T={args.T} ({args.warmup_steps} warm-up)",
                    "cells": cells, "T": args.T},
         "hbm_roofline_frac": value * BYTES_PER_CELL_UPDATE / HBM_PEAK,
-        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
+        "roofline": {"bound": "alu", "achieved": ops_achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "TOP/s", "frac": ops_achieved / VALU_PEAK, "traffic": traffic,
                      "kernel": f"grid_kstep_mixed_kernel<{q}, {'true' if is_open else 'false'}>",
-                     "kernel_ms": kernel_ms},
+                     "kernel_ms": kernel_ms, "ops_per_cell_update": ops_per_cu,
+                     "hbm_algorithmic_GBps": achieved / 1e9,
+                     "hbm_algorithmic_frac": achieved / HBM_PEAK},
         "extra": extra,
     }
     if not args.no_cpu:

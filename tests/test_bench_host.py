@@ -1,0 +1,35 @@
+"""Host-side logic of the benchmark (no GPU): the algorithmic operation count
+behind the k-step kernel's roofline, and the one-GPU guard."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_op_count_per_cell_update():
+    # 8 vmax per 32-cell word for rules 1-4 and F(t); 44 more when p draws
+    assert bench.kstep_ops_per_cell_update(0, 0.0) == 0.0
+    assert bench.kstep_ops_per_cell_update(5, 0.0) == 40 / 32
+    assert bench.kstep_ops_per_cell_update(5, 0.13) == (40 + 44) / 32
+    assert bench.kstep_ops_per_cell_update(8, 0.5) == (64 + 44) / 32
+    # thr = floor(p 2^32) = 0: rule 3 never fires and nothing is drawn
+    assert bench.kstep_ops_per_cell_update(3, 2.0 ** -33) == 24 / 32
+    assert bench.kstep_ops_per_cell_update(3, 2.0 ** -32) == (24 + 44) / 32
+
+
+def test_alu_peak_from_unit_counts():
+    assert bench.VALU_PEAK == pytest.approx(39.3216e12)
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_more_than_one_gpu_is_refused(n):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr or "1 GPU" in r.stderr or "--gpus 1" in r.stderr
+    assert r.stdout == ""

@@ -95,6 +95,24 @@ def test_kstep_tilings(k, q):
         assert k * 6 > (2048 * q - 32) // 2, e   # only geometries that cannot fit may fail
 
 
+@pytest.mark.parametrize("vmax", [1, 5, 8])
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+def test_rule3_draws_at_the_ring_end(q, vmax):
+    """Words that are not aligned to the 32-cell draw blocks: the first tile's
+    left halo and the last tile's wrap-around when L is not a multiple of 32
+    (two blocks per word), and rings shorter than a segment, where a word may
+    touch three blocks or wrap more than once.  p = 0.13 also exercises the
+    tied cars of those words."""
+    k = 16
+    H = -(-k * vmax // 32) * 32
+    seg = 2048 * q
+    own = seg - 2 * H
+    lengths = [64, 65, 95, 97, 129, 1000, seg - 33, seg - 1, seg + 1, own + 1, own + 17,
+               2 * own - 5, 2 * own + 31, 3 * own + 16, 3 * own + 32]
+    for i, L in enumerate(lengths):
+        _run_and_compare(L, max(1, L // 4), vmax, 0.13, 900 + i, 40, k=k, q=q, init_v=1)
+
+
 @pytest.mark.parametrize("L", [1, 2, 3, 5, 8, 31, 32, 33, 63, 64, 100, 1023, 2047, 2048, 2049])
 def test_tiny_and_ragged_rings(L):
     for N in sorted({0, 1, L // 3, L - 1, L}):
