@@ -301,6 +301,9 @@ def bench_single(args, cfg, rep, kernels):
     torch.cuda.synchronize()
     s.close()
     value = res["kstep"]
+    if "onestep" in res and rep == "grid":
+        # the one-step kernel reads and writes every cell's byte: HBM-bound
+        res["onestep_hbm_frac"] = res["onestep"] * BYTES_PER_CELL_UPDATE / HBM_PEAK
     if rep == "grid" and cfg["L"] >= 1 << 24:
         # the bit-sliced kernel without temporal blocking (k = 1): the one-step
         # path whose bound is HBM at 2 B per cell-update

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnasch.so")
 
-SOURCES = ["init.hip", "grid_onestep.hip", "grid_kstep.hip", "agent.hip", "runtime.hip",
+SOURCES = ["init.hip", "grid_kstep.hip", "agent.hip", "runtime.hip",
            "batch.hip", "server.hip", "output.hip"]
 CLI_SRC = "traffic_main.cpp"
 CLI = os.path.join(PKG, "nasch_traffic")

@@ -115,6 +115,7 @@ struct GridEngine {
     uint32_t k = 0, q = 0;
     uint32_t launch_vmax = kMixedVmax;  // single specialisation when all rings agree
     bool launch_open = false;           // the rings are open roads (all or none)
+    bool io_bytes = false;              // kernels read and write the byte form (one vmax)
     uint32_t version = 0;               // bumped whenever d_items / geometry change
     // per-launch F(t) partials of every item and step, and the rings that keep a log
     uint32_t* d_partials = nullptr;
@@ -241,7 +242,11 @@ struct GridEngine {
         const uint32_t n = launches_for(T);
         for (uint32_t i = 0; i < n; ++i) {
             const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
-            hipError_t e = launch_grid_kstep(launch_vmax, launch_open, q, d_rings, d_items,
+            hipError_t e =
+                io_bytes ? launch_grid_kstep_bytes(launch_vmax, launch_open, q, d_rings, d_items,
+                                                   (uint32_t)items.size(), d_partials, ki, d_clk,
+                                                   i * k, i, s)
+                         : launch_grid_kstep(launch_vmax, launch_open, q, d_rings, d_items,
                                              (uint32_t)items.size(), d_partials, ki, d_clk, i * k,
                                              i, s);
             if (e == hipSuccess && n_log_rings)

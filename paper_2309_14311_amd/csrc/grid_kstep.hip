@@ -37,6 +37,7 @@
 // the entering car (v = 0) after rule 4 if the gate lets one in and the cell
 // was empty at the start of the step.  Both branches are uniform over the wave
 // and cost nothing in the other segments.
+#include "bitplanes.hpp"
 #include "launchers.hpp"
 
 namespace nasch {
@@ -284,12 +285,74 @@ __device__ __forceinline__ void gather_ring(const uint32_t* __restrict__ src, ui
     }
 }
 
+// ---- the byte form (BYTES = true): the road is read and written as one byte
+// per cell and converted to and from bit planes in registers.
+
+// The 32 bytes of an aligned 32-cell word (16-byte loads).
+__device__ __forceinline__ void load_bytes32(const uint8_t* __restrict__ p, uint32_t (&d)[8]) {
+    const uint4 a = *reinterpret_cast<const uint4*>(p);
+    const uint4 b = *reinterpret_cast<const uint4*>(p + 16);
+    d[0] = a.x; d[1] = a.y; d[2] = a.z; d[3] = a.w;
+    d[4] = b.x; d[5] = b.y; d[6] = b.z; d[7] = b.w;
+}
+
+// The bytes of the 32 consecutive ring cells x0, x0+1, ... (mod L), x0 < L,
+// one at a time (a word across the end of the ring, or a short ring).
+__device__ __forceinline__ void gather_bytes_ring(const uint8_t* __restrict__ src, uint32_t L,
+                                                  uint32_t x0, uint32_t (&d)[8]) {
+    uint32_t pos = x0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        uint32_t w = 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            w |= (uint32_t)src[pos] << (8 * b);
+            pos = pos + 1u == L ? 0u : pos + 1u;
+        }
+        d[i] = w;
+    }
+}
+
+// Open road: the bytes of cells p0 .. p0+31 (p0 < L, a multiple of 32); cells
+// at or past L read as empty.
+__device__ __forceinline__ void load_bytes_open(const uint8_t* __restrict__ src, uint32_t L,
+                                                uint32_t p0, uint32_t (&d)[8]) {
+    if (p0 + 32u <= L) {
+        load_bytes32(src + p0, d);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        uint32_t w = 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t c = p0 + 4u * i + b;
+            w |= (uint32_t)(c < L ? src[c] : (uint8_t)kEmpty) << (8 * b);
+        }
+        d[i] = w;
+    }
+}
+
+// Write the owned cells (bits of own) of the word of road cells c0 .. c0+31;
+// a wholly owned word lies inside the road and is written with 16-byte stores.
+__device__ __forceinline__ void store_bytes(uint8_t* __restrict__ dst, uint32_t c0, uint32_t own,
+                                            const uint32_t (&d)[8]) {
+    if (own == 0xFFFFFFFFu) {
+        *reinterpret_cast<uint4*>(dst + c0) = make_uint4(d[0], d[1], d[2], d[3]);
+        *reinterpret_cast<uint4*>(dst + c0 + 16) = make_uint4(d[4], d[5], d[6], d[7]);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+        if ((own >> i) & 1u) dst[c0 + i] = (uint8_t)(d[i >> 2] >> (8 * (i & 3)));
+}
+
 }  // namespace
 
 // One wave advances one tile item by up to k steps.  F(t) of a ring with a
 // flux log goes to partials[s * n_items + item] (summed per ring and step by
 // the fold kernel); flux_acc gets one atomic per wave.
-template <int VMAX, int Q, bool OPEN>
+template <int VMAX, int Q, bool OPEN, bool BYTES>
 __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it, uint32_t item,
                                            uint32_t n_items, uint32_t* __restrict__ partials,
                                            uint32_t lane, uint32_t k,
@@ -356,7 +419,28 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
         // [0, L) on an open road
         const uint32_t valid = j0 + 32u <= seg_len ? 0xFFFFFFFFu
                                : (j0 < seg_len ? (1u << (seg_len - j0)) - 1u : 0u);
-        if constexpr (OPEN) {
+        if constexpr (BYTES) {
+            const uint8_t* __restrict__ bsrc = R.buf[par];
+            uint32_t d[8];
+            bool inside = true;
+            if constexpr (OPEN) {
+                if (p0 >= 0 && p0 < (int64_t)L) load_bytes_open(bsrc, L, (uint32_t)p0, d);
+                else inside = false;
+            } else if (aligned[q]) {
+                load_bytes32(bsrc + x0, d);
+            } else {
+                gather_bytes_ring(bsrc, L, x0, d);
+            }
+            if (inside) {
+                bytes_to_thermo<VMAX>(d, T[q]);
+                const uint32_t v = OPEN ? valid & keep[q] : valid;
+#pragma unroll
+                for (int m = 0; m <= VMAX; ++m) T[q][m] &= v;
+            } else {
+#pragma unroll
+                for (int m = 0; m <= VMAX; ++m) T[q][m] = 0u;
+            }
+        } else if constexpr (OPEN) {
             if (p0 >= 0 && p0 < (int64_t)L) {
                 const uint32_t v = valid & keep[q];
                 const uint32_t w = (uint32_t)p0 >> 5;
@@ -504,13 +588,20 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
         if (own[q] == 0u) continue;
         const uint32_t j0 = 32u * (lane * Q + q);
         const uint32_t w = (own_start + (j0 - H)) >> 5;
+        if constexpr (BYTES) {
+            uint32_t d[8];
+            thermo_to_bytes<VMAX>(T[q], d);
+            store_bytes(R.buf[par ^ 1u], 32u * w, own[q], d);
+        } else {
 #pragma unroll
-        for (int m = 0; m <= VMAX; ++m) dst[(size_t)m * nw + w] = T[q][m] & own[q];
+            for (int m = 0; m <= VMAX; ++m) dst[(size_t)m * nw + w] = T[q][m] & own[q];
+        }
     }
 }
 
 // All items of a launch share vmax (and the boundary): one specialisation.
-template <int VMAX, int Q, bool OPEN>
+// BYTES: the road is read and written in its byte form (the one-step kernel).
+template <int VMAX, int Q, bool OPEN, bool BYTES>
 __global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restrict__ rings,
                                                          const TileItem* __restrict__ items,
                                                          uint32_t n_items, uint32_t* partials,
@@ -521,8 +612,8 @@ __global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restr
     const uint32_t wave = blockIdx.x * 4u + wib;
     if (wave >= n_items) return;
     const TileItem it = items[wave];
-    kstep_tile<VMAX, Q, OPEN>(rings[it.ring], it, wave, n_items, partials, threadIdx.x & 63u, k,
-                              clk, s_off, launch_idx, s_ref[wib]);
+    kstep_tile<VMAX, Q, OPEN, BYTES>(rings[it.ring], it, wave, n_items, partials,
+                                     threadIdx.x & 63u, k, clk, s_off, launch_idx, s_ref[wib]);
 }
 
 // Items of different vmax in one launch: the branch on the ring's vmax is
@@ -544,15 +635,15 @@ __global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* _
     const uint32_t lane = threadIdx.x & 63u;
     RefineLds<Q>& rl = s_ref[wib];
     switch (R.vmax) {
-        case 0: kstep_tile<0, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 1: kstep_tile<1, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 2: kstep_tile<2, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 3: kstep_tile<3, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 4: kstep_tile<4, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 5: kstep_tile<5, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 6: kstep_tile<6, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 7: kstep_tile<7, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 8: kstep_tile<8, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 0: kstep_tile<0, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 1: kstep_tile<1, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 2: kstep_tile<2, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 3: kstep_tile<3, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 4: kstep_tile<4, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 5: kstep_tile<5, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 6: kstep_tile<6, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 7: kstep_tile<7, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 8: kstep_tile<8, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
         default: break;
     }
 }
@@ -565,11 +656,11 @@ hipError_t launch_q(uint32_t vmax, bool open, dim3 grid, hipStream_t s, const Ri
 #define NASCH_KSTEP_CASE(V)                                                                      \
     case V:                                                                                      \
         if (open)                                                                                \
-            NASCH_LAUNCH((grid_kstep_kernel<V, Q, true>), grid, dim3(256), 0, s, rings, items,   \
-                         n_items, partials, k, clk, s_off, launch_idx);                          \
+            NASCH_LAUNCH((grid_kstep_kernel<V, Q, true, false>), grid, dim3(256), 0, s, rings,   \
+                         items, n_items, partials, k, clk, s_off, launch_idx);                   \
         else                                                                                     \
-            NASCH_LAUNCH((grid_kstep_kernel<V, Q, false>), grid, dim3(256), 0, s, rings, items,  \
-                         n_items, partials, k, clk, s_off, launch_idx);                          \
+            NASCH_LAUNCH((grid_kstep_kernel<V, Q, false, false>), grid, dim3(256), 0, s, rings,  \
+                         items, n_items, partials, k, clk, s_off, launch_idx);                   \
         break;
     switch (vmax) {
         NASCH_KSTEP_CASE(0)
@@ -608,6 +699,51 @@ hipError_t launch_grid_kstep(uint32_t vmax, bool open, uint32_t q, const RingDes
         case 2: return launch_q<2>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         case 3: return launch_q<3>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         case 4: return launch_q<4>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+template <int Q>
+hipError_t launch_bytes_q(uint32_t vmax, bool open, dim3 grid, hipStream_t s,
+                          const RingDesc* rings, const TileItem* items, uint32_t n_items,
+                          uint32_t* partials, uint32_t k, const Clock* clk, uint32_t s_off,
+                          uint32_t launch_idx) {
+#define NASCH_KSTEP_BYTES_CASE(V)                                                                \
+    case V:                                                                                      \
+        if (open)                                                                                \
+            NASCH_LAUNCH((grid_kstep_kernel<V, Q, true, true>), grid, dim3(256), 0, s, rings,    \
+                         items, n_items, partials, k, clk, s_off, launch_idx);                   \
+        else                                                                                     \
+            NASCH_LAUNCH((grid_kstep_kernel<V, Q, false, true>), grid, dim3(256), 0, s, rings,   \
+                         items, n_items, partials, k, clk, s_off, launch_idx);                   \
+        break;
+    switch (vmax) {
+        NASCH_KSTEP_BYTES_CASE(0)
+        NASCH_KSTEP_BYTES_CASE(1)
+        NASCH_KSTEP_BYTES_CASE(2)
+        NASCH_KSTEP_BYTES_CASE(3)
+        NASCH_KSTEP_BYTES_CASE(4)
+        NASCH_KSTEP_BYTES_CASE(5)
+        NASCH_KSTEP_BYTES_CASE(6)
+        NASCH_KSTEP_BYTES_CASE(7)
+        NASCH_KSTEP_BYTES_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef NASCH_KSTEP_BYTES_CASE
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_grid_kstep_bytes(uint32_t vmax, bool open, uint32_t q, const RingDesc* rings,
+                                   const TileItem* items, uint32_t n_items, uint32_t* partials,
+                                   uint32_t k, const Clock* clk, uint32_t s_off,
+                                   uint32_t launch_idx, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const dim3 grid((n_items + 3u) / 4u);
+    switch (q) {
+        case 1: return launch_bytes_q<1>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         default: return hipErrorInvalidValue;
     }
 }

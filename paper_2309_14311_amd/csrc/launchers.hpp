@@ -55,17 +55,6 @@ hipError_t launch_fold_ring_flux(const RingDesc* rings, const uint32_t* log_ring
 hipError_t launch_fold_agent_flux(const AgentDesc* a, const uint32_t* partials, uint32_t n_items,
                                   uint32_t k, const Clock* clk, uint32_t s_off, hipStream_t s);
 
-// ---- grid, byte-wise one step per launch (grid_onestep.hip) --------------------
-constexpr uint32_t kOneStepTile = 8192;
-constexpr uint32_t onestep_blocks(uint32_t L) {
-    return (uint32_t)(((uint64_t)L + kOneStepTile - 1) / kOneStepTile);
-}
-// F(t) of block b goes to partials[b]; the ring desc for the fold has
-// first_item 0 and ntiles = onestep_blocks(L).
-hipError_t launch_grid_onestep(const RingDesc* ring, uint32_t L, uint32_t* partials,
-                               const Clock* clk, uint32_t s_off, uint32_t launch_idx,
-                               hipStream_t s);
-
 // ---- grid, bit-sliced, k steps per launch (grid_kstep.hip) --------------------
 // Cells per wave segment for q words of 32 cells per lane.
 constexpr uint32_t kstep_segment(uint32_t q) { return 64u * 32u * q; }
@@ -77,6 +66,16 @@ hipError_t launch_grid_kstep(uint32_t vmax, bool open, uint32_t q, const RingDes
                              const TileItem* items, uint32_t n_items, uint32_t* partials,
                              uint32_t k, const Clock* clk, uint32_t s_off, uint32_t launch_idx,
                              hipStream_t s);
+// The same kernel reading and writing the road's byte form (ring.buf) instead
+// of its bit planes; one vmax per launch (no kMixedVmax), q = 1 only.  With
+// k = 1 it is the one-step kernel.
+hipError_t launch_grid_kstep_bytes(uint32_t vmax, bool open, uint32_t q, const RingDesc* rings,
+                                   const TileItem* items, uint32_t n_items, uint32_t* partials,
+                                   uint32_t k, const Clock* clk, uint32_t s_off,
+                                   uint32_t launch_idx, hipStream_t s);
+// Words per lane of the one-step kernel: one step per wave leaves the load
+// latency exposed, and q = 1 (more, smaller waves) hides it better than q = 2.
+constexpr uint32_t kOneStepQ = 1;
 
 // ---- agent (agent.hip) --------------------------------------------------------
 // F(t) of wave w goes to partials[w], w < ceil(N / 64).

@@ -49,11 +49,10 @@ struct nasch_sim {
     uint8_t* grid[2] = {nullptr, nullptr};
     uint32_t* planes[2] = {nullptr, nullptr};
     bool bytes_ok = true, planes_ok = false;
-    GridEngine eng;           // one ring, its tiles
-    RingDesc* d_onestep = nullptr;  // the same ring for the one-step kernel
-    uint32_t* os_partials = nullptr;   // one-step / agent F(t) partials
+    GridEngine eng;           // one ring, its tiles (bit planes, k steps per launch)
+    GridEngine eng1;          // the same ring for the one-step kernel (bytes, k = 1)
+    uint32_t* os_partials = nullptr;   // agent F(t) partials
     size_t os_partials_cap = 0;
-    uint32_t* d_zero = nullptr;        // device index list {0}
     // agent representation
     int32_t* ax[2] = {nullptr, nullptr};
     uint8_t* av[2] = {nullptr, nullptr};
@@ -111,9 +110,10 @@ struct nasch_sim {
 nasch_sim::~nasch_sim() {
     graphs.clear();
     eng.release();
+    eng1.release();
     // agent_grid aliases grid[0]
-    void* ps[] = {d_clk, grid[0], grid[1], planes[0], planes[1], d_onestep, ax[0], ax[1], av[0],
-                  av[1], d_agent, flux, os_partials, d_zero, mlcg_pow};
+    void* ps[] = {d_clk, grid[0], grid[1], planes[0], planes[1], ax[0], ax[1], av[0],
+                  av[1], d_agent, flux, os_partials, mlcg_pow};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -146,15 +146,12 @@ int nasch_sim::ensure_log(uint64_t steps) {
 // Push the descriptors (pointers, geometry) to the device.
 int nasch_sim::refresh_descs() {
     if (rep == NASCH_REP_GRID) {
-        RingDesc& r = eng.rings[0];
-        r.flux_log = flux;
-        r.log_t0 = log_t0;
-        if (!ok(eng.upload_rings(stream))) return fail();
-        RingDesc os = r;
-        os.first_item = 0;
-        os.ntiles = onestep_blocks((uint32_t)L);
-        if (!ok(hipMemcpyAsync(d_onestep, &os, sizeof(RingDesc), hipMemcpyHostToDevice, stream)))
-            return fail();
+        for (GridEngine* g : {&eng, &eng1}) {
+            RingDesc& r = g->rings[0];
+            r.flux_log = flux;
+            r.log_t0 = log_t0;
+            if (!ok(g->upload_rings(stream))) return fail();
+        }
     } else {
         h_agent.flux_log = flux;
         h_agent.log_t0 = log_t0;
@@ -211,16 +208,9 @@ int nasch_sim::enqueue_steps(uint64_t T) {
         uint32_t nl = 0;
         if (rep == NASCH_REP_GRID) {
             if (kernel == NASCH_KERNEL_ONESTEP) {
-                const uint32_t nb = onestep_blocks((uint32_t)L);
-                for (uint64_t i = 0; i < T; ++i) {
-                    hipError_t e = launch_grid_onestep(d_onestep, (uint32_t)L, os_partials, d_clk,
-                                                       (uint32_t)i, (uint32_t)i, stream);
-                    if (e == hipSuccess)
-                        e = launch_fold_ring_flux(d_onestep, d_zero, 1, nb, os_partials, nb, 1,
-                                                  d_clk, (uint32_t)i, stream);
-                    if (e != hipSuccess) return e;
-                }
-                nl = (uint32_t)T;
+                hipError_t e = eng1.enqueue(T, d_clk, stream);
+                if (e != hipSuccess) return e;
+                nl = eng1.launches_for(T);
             } else {
                 hipError_t e = eng.enqueue(T, d_clk, stream);
                 if (e != hipSuccess) return e;
@@ -372,8 +362,7 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
         h->own_stream = true;
     }
     const SlowParams sp = slow_params(seed, o.replica, p);
-    if (!h->ok(dev_alloc(&h->d_clk, 1)) || !h->ok(dev_alloc(&h->d_zero, 1))) return NASCH_ENOMEM;
-    if (!h->ok(hipMemsetAsync(h->d_zero, 0, sizeof(uint32_t), h->stream))) return NASCH_EDEVICE;
+    if (!h->ok(dev_alloc(&h->d_clk, 1))) return NASCH_ENOMEM;
     const Clock c0{0u, 0u};
     if (!h->ok(hipMemcpyAsync(h->d_clk, &c0, sizeof(Clock), hipMemcpyHostToDevice, h->stream)))
         return NASCH_EDEVICE;
@@ -410,9 +399,9 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
             r.thr_out = (uint64_t)std::floor(std::ldexp(o.beta, 32));
         }
         h->eng.rings.push_back(r);
-        if (!h->ok(dev_alloc(&h->d_onestep, 1))) return NASCH_ENOMEM;
-        rc = h->ensure_os_partials(onestep_blocks((uint32_t)L));
-        if (rc) return rc;
+        h->eng1.rings.push_back(r);
+        h->eng1.io_bytes = true;
+        if (!h->ok(h->eng1.set_geometry(1, kOneStepQ, h->stream))) return NASCH_EDEVICE;
         uint32_t kk = o.k, qq = o.q;
         uint32_t dk, dq;
         default_tuning((uint32_t)L, vmax, &dk, &dq);
