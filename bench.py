@@ -301,9 +301,12 @@ def bench_single(args, cfg, rep, kernels):
     torch.cuda.synchronize()
     s.close()
     value = res["kstep"]
-    if "onestep" in res and rep == "grid":
-        # the one-step kernel reads and writes every cell's byte: HBM-bound
-        res["onestep_hbm_frac"] = res["onestep"] * BYTES_PER_CELL_UPDATE / HBM_PEAK
+    # algorithmic bytes per cell-update: the grid reads and writes each cell's
+    # byte; the agent form reads and writes x (4 B) and v (1 B) of each car
+    bpcu = BYTES_PER_CELL_UPDATE if rep == "grid" else 10.0 * cfg["N"] / cfg["L"]
+    if "onestep" in res:
+        # one step per launch moves all of them every step: HBM-bound
+        res["onestep_hbm_frac"] = res["onestep"] * bpcu / HBM_PEAK
     if rep == "grid" and cfg["L"] >= 1 << 24:
         # the bit-sliced kernel without temporal blocking (k = 1): the one-step
         # path whose bound is HBM at 2 B per cell-update
@@ -327,7 +330,8 @@ def bench_single(args, cfg, rep, kernels):
                                f"p={cfg['p']} T={T}" + (" shared-stream rng" if rng == "stream"
                                                         else ""),
                    "k": info["k"], "q": info["q"]},
-        "hbm_roofline_frac": value * BYTES_PER_CELL_UPDATE / HBM_PEAK,
+        "hbm_roofline_frac": value * bpcu / HBM_PEAK,
+        "bytes_per_cell_update": bpcu,
         "extra": {(k if k.endswith("frac") else f"{k}_cups"): v for k, v in res.items()},
     }
 

@@ -3,13 +3,11 @@
 // uint8 velocities v[N].  Car i's distance to the car in front is
 // d = (x[i+1] - x[i]) mod L (d = L for a car alone); rules 1-4 follow.
 //
-// Two kernels:
-//   agent_onestep_kernel  one thread per car, one step per launch;
-//   agent_kstep_kernel    one wave per 64 x kAgentCarsPerLane consecutive cars
-//                         kept in registers for k steps.  Car i after s steps
-//                         depends only on cars i .. i+s, so the last k cars of
-//                         a wave are a halo: each wave writes back the first
-//                         `own` cars and the waves overlap by the halo.
+// agent_kstep_kernel: one wave per 64 x kAgentCarsPerLane consecutive cars,
+// kept in registers for k steps.  Car i after s steps depends only on cars
+// i .. i+s, so the last k cars of a wave are a halo: each wave writes back the
+// first `own` cars and the waves overlap by the halo.  Launched with one step
+// it is the one-step kernel.
 // Rule 3 uses the same keyed draw as the grid kernels (R depends on the cell a
 // car starts the step in), so both representations give identical results.
 #include "launchers.hpp"
@@ -127,63 +125,6 @@ __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&
     __builtin_amdgcn_wave_barrier();
 }
 }  // namespace
-
-// F(t) of each wave goes to partials[wave] (summed by the fold kernel).
-__global__ __launch_bounds__(256) void agent_onestep_kernel(const AgentDesc* __restrict__ A,
-                                                            uint32_t* __restrict__ partials,
-                                                            const Clock* __restrict__ clk,
-                                                            uint32_t s_off, uint32_t launch_idx) {
-    const uint32_t N = A->N, L = A->L, vmax = A->vmax;
-    const SlowParams sp = A->sp;
-    const uint32_t t = clk->t + A->t + s_off;
-    const uint32_t par = (clk->parity + A->parity + launch_idx) & 1u;
-    const int32_t* __restrict__ x = A->x[par];
-    const uint8_t* __restrict__ v = A->v[par];
-    int32_t* __restrict__ xo = A->x[par ^ 1u];
-    uint8_t* __restrict__ vo = A->v[par ^ 1u];
-
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t nv = 0;
-    if (i < N) {
-        const uint32_t xi = (uint32_t)x[i];
-        uint32_t d = L;
-        if (N > 1) {
-            const uint32_t xn = (uint32_t)x[i + 1 == N ? 0 : i + 1];
-            d = xn >= xi ? xn - xi : xn + L - xi;
-        }
-        nv = accel_brake(v[i], d, vmax);
-        if (A->rng) {                                                        // rule 3
-            const uint64_t n = (uint64_t)t * N + i + 1u;
-            const uint32_t r = mlcg_mul(mlcg_pow(A->mlcg_pow, n), A->mlcg_x0);
-            if (nv > 0 && r < A->mlcg_thr) --nv;
-        } else if (nv > 0 && sp.thr != 0) {
-            const Word4 w = slow_hi_planes(xi >> 5, t, sp);
-            const uint32_t sh = xi & 31u;
-            const uint32_t hi4 = (((w.w0 >> sh) & 1u) << 3) | (((w.w1 >> sh) & 1u) << 2) |
-                                 (((w.w2 >> sh) & 1u) << 1) | ((w.w3 >> sh) & 1u);
-            if (slow_from_hi(hi4, xi, t, sp)) --nv;
-        }
-        uint32_t xn = xi + nv;                                               // rule 4
-        if (xn >= L) xn -= L;
-        xo[i] = (int32_t)xn;
-        vo[i] = (uint8_t)nv;
-    }
-    const uint32_t total = wave_total(nv);
-    if ((threadIdx.x & 63u) == 0) {
-        if (A->flux_log) partials[i >> 6] = total;
-        if (A->flux_acc && (uint64_t)t >= A->warmup && total)
-            atomicAdd(A->flux_acc, (unsigned long long)total);
-    }
-}
-
-hipError_t launch_agent_onestep(const AgentDesc* a, uint32_t N, uint32_t* partials,
-                                const Clock* clk, uint32_t s_off, uint32_t launch_idx,
-                                hipStream_t s) {
-    if (N == 0) return hipSuccess;
-    NASCH_LAUNCH(agent_onestep_kernel, dim3((N + 255) / 256), dim3(256), 0, s, a, partials, clk,
-                 s_off, launch_idx);
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------------
 constexpr uint32_t CPL = kAgentCarsPerLane;

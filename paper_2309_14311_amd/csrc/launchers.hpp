@@ -78,12 +78,9 @@ hipError_t launch_grid_kstep_bytes(uint32_t vmax, bool open, uint32_t q, const R
 constexpr uint32_t kOneStepQ = 1;
 
 // ---- agent (agent.hip) --------------------------------------------------------
-// F(t) of wave w goes to partials[w], w < ceil(N / 64).
-hipError_t launch_agent_onestep(const AgentDesc* a, uint32_t N, uint32_t* partials,
-                                const Clock* clk, uint32_t s_off, uint32_t launch_idx,
-                                hipStream_t s);
 // k steps per launch: each wave holds 64 * kAgentCarsPerLane consecutive cars and
-// writes back all but the last k of them.
+// writes back all but the last k of them (fewer steps than the tiling's k are
+// correct too; one step per launch is the one-step kernel).
 constexpr uint32_t kAgentCarsPerLane = 8;
 hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t ntiles, uint32_t* partials, uint32_t k,
                               const Clock* clk, uint32_t s_off, uint32_t launch_idx,

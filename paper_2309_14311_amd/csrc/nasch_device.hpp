@@ -67,15 +67,6 @@ __device__ __forceinline__ uint32_t slow_lo28(uint32_t x, uint32_t t, const Slow
     return philox(x, t, sp.replica, kTagSlowLo, sp.k0, sp.k1).w0 >> 4;
 }
 
-// Full R for one cell (used where cells are handled one at a time).
-__device__ __forceinline__ uint32_t rand32(uint32_t x, uint32_t t, const SlowParams& sp) {
-    const Word4 b = slow_hi_planes(x >> 5, t, sp);
-    const uint32_t s = x & 31u;
-    const uint32_t hi = (((b.w0 >> s) & 1u) << 3) | (((b.w1 >> s) & 1u) << 2) |
-                        (((b.w2 >> s) & 1u) << 1) | ((b.w3 >> s) & 1u);
-    return (hi << 28) | slow_lo28(x, t, sp);
-}
-
 // The bit-sliced nibble (w0 w1 w2 w3), w0 most significant, compared with the
 // constant TH: lt = nibble < TH, eq = nibble == TH.  With TH known the chain
 // folds into a few three-input bitwise operations.
@@ -120,15 +111,6 @@ __device__ __forceinline__ void block_lt_eq(const Word4& w, uint32_t th, uint32_
     }
 }
 
-// Rule 3 decision for a car whose top nibble of R is already known.
-__device__ __forceinline__ bool slow_from_hi(uint32_t hi4, uint32_t x, uint32_t t,
-                                             const SlowParams& sp) {
-    const uint32_t th = sp.thr >> 28;
-    if (hi4 != th) return hi4 < th;
-    const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
-    if (lo_thr == 0) return false;
-    return slow_lo28(x, t, sp) < lo_thr;
-}
 
 // Open road: the gate draw of step t.  A car enters empty cell 0 iff word 0 is
 // below thr_in = floor(alpha 2^32); the exit is open iff word 1 is below

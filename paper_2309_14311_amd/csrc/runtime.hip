@@ -103,8 +103,6 @@ struct nasch_sim {
         os_partials_cap = n;
         return NASCH_OK;
     }
-    // agent one-step waves = all waves of its grid
-    uint32_t agent_onestep_waves() const { return 4u * (uint32_t)((N + 255) / 256); }
 };
 
 nasch_sim::~nasch_sim() {
@@ -218,13 +216,15 @@ int nasch_sim::enqueue_steps(uint64_t T) {
             }
         } else {
             if (kernel == NASCH_KERNEL_ONESTEP) {
-                const uint32_t nw = agent_onestep_waves();
+                // one step per launch: the k-step kernel with one step, on the
+                // current tiling (its halo is sized for k, which one step leaves
+                // correct)
                 for (uint64_t i = 0; i < T; ++i) {
-                    hipError_t e = launch_agent_onestep(d_agent, (uint32_t)N, os_partials, d_clk,
-                                                        (uint32_t)i, (uint32_t)i, stream);
+                    hipError_t e = launch_agent_kstep(d_agent, h_agent.ntiles, os_partials, 1u,
+                                                      d_clk, (uint32_t)i, (uint32_t)i, stream);
                     if (e == hipSuccess)
-                        e = launch_fold_agent_flux(d_agent, os_partials, nw, 1, d_clk, (uint32_t)i,
-                                                   stream);
+                        e = launch_fold_agent_flux(d_agent, os_partials, h_agent.ntiles, 1u, d_clk,
+                                                   (uint32_t)i, stream);
                     if (e != hipSuccess) return e;
                 }
                 nl = (uint32_t)T;
@@ -460,7 +460,7 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
         }
         uint32_t kk = o.k ? o.k : kDefaultAgentK;
         if (!agent_geometry((uint32_t)N, kk, &a.own, &a.ntiles)) return NASCH_EINVAL;
-        rc = h->ensure_os_partials(std::max<size_t>((size_t)a.ntiles * kk, h->agent_onestep_waves()));
+        rc = h->ensure_os_partials((size_t)a.ntiles * kk);
         if (rc) return rc;
         h->k = kk;
         h->q = o.q ? o.q : 1;
