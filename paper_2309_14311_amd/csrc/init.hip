@@ -1,4 +1,5 @@
 // init.hip -- initial state, representation changes and small utility kernels.
+#include "bitplanes.hpp"
 #include "launchers.hpp"
 
 namespace nasch {
@@ -60,15 +61,9 @@ hipError_t launch_init_grid(uint8_t* g, uint32_t L, uint32_t N, uint32_t vmax, u
 
 // ---- bytes <-> bit planes ------------------------------------------------------
 // One thread per 32-cell word, a block per kConvChunk words of one job.
+// The bytes of a word and their bit planes are exchanged with the 8x8 bit
+// transposes of bitplanes.hpp; vmax is a run-time value here.
 namespace {
-// bit 0 of each byte of y -> bits 0..3 (byte b -> bit b)
-__device__ __forceinline__ uint32_t gather4(uint32_t y) {
-    return (((y & 0x01010101u) * 0x00204081u) >> 21) & 0xFu;
-}
-// bits 0..3 of b -> bit 0 of bytes 0..3
-__device__ __forceinline__ uint32_t spread4(uint32_t b) {
-    return ((b & 0xFu) * 0x00204081u) & 0x01010101u;
-}
 // (P3 P2 P1 P0) >= m, bit-sliced over 32 cells, for 1 <= m <= 15
 __device__ __forceinline__ uint32_t ge_value(const uint32_t (&P)[4], uint32_t m) {
     uint32_t gt = 0u, eq = 0xFFFFFFFFu;
@@ -115,15 +110,10 @@ __global__ __launch_bounds__(kConvChunk) void bytes_to_planes_kernel(const ConvJ
             by[d] = y;
         }
     }
-    uint32_t E = 0u, P[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        const uint32_t sh = 4u * d;
-        E |= gather4(by[d] >> 7) << sh;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) P[b] |= gather4(by[d] >> b) << sh;
-    }
-    const uint32_t occ = ~E;
+    uint32_t bits[8];
+    bytes_to_bitplanes(by, bits);
+    const uint32_t P[4] = {bits[0], bits[1], bits[2], bits[3]};   // v, bit by bit
+    const uint32_t occ = ~bits[7];                                 // 0xFF has bit 7
     J.planes[w] = occ;
     for (uint32_t m = 1; m <= J.vmax; ++m) J.planes[(uint64_t)m * J.nw + w] = occ & ge_value(P, m);
 }
@@ -143,13 +133,10 @@ __global__ __launch_bounds__(kConvChunk) void planes_to_bytes_kernel(const ConvJ
     const uint32_t B2 = T[4] & ~T[8];
     const uint32_t B3 = T[8];
     const uint32_t E = ~T[0];
+    // an empty cell gets every bit set: 0xFF
+    const uint32_t bits[8] = {B0 | E, B1 | E, B2 | E, B3 | E, E, E, E, E};
     uint32_t by[8];
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        const uint32_t sh = 4u * d;
-        by[d] = spread4(B0 >> sh) | (spread4(B1 >> sh) << 1) | (spread4(B2 >> sh) << 2) |
-                (spread4(B3 >> sh) << 3) | (spread4(E >> sh) * 0xFFu);
-    }
+    bitplanes_to_bytes(bits, by);
     const uint64_t c0 = (uint64_t)w * 32u;
     if (c0 + 32u <= J.L) {
         uint4* p = reinterpret_cast<uint4*>(J.bytes + c0);
