@@ -1,6 +1,6 @@
 """GPU parity of single simulations against the CPU oracle, element by element:
-initial state, every kernel (byte-wise one-step, bit-sliced k-step for every
-(k, q), agent one-step and k-step), flux logs and snapshots, tiny and ragged
+initial state, every kernel (one-step on the byte form, k-step on bit planes
+for every (k, q), agent one-step and k-step), flux logs and snapshots, tiny and ragged
 rings, every vmax, the degenerate p and densities, checkpoint/restore and
 launch-sequence replay.  Integer work: the bar is bit-exact equality."""
 import numpy as np
@@ -248,6 +248,38 @@ def test_switching_kernels_mid_run(boundary):
         got, _ = s.snapshot()
         np.testing.assert_array_equal(got, g)
         np.testing.assert_array_equal(s.flux(0, t), np.concatenate(fluxes))
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("rng", ["keyed", "stream"])
+def test_agent_onestep_on_every_tiling(rng):
+    """The agent form's one-step launches run on the tiling its k-step setting
+    left (halo sized for that k).  Switched in turn after tilings for k = 1 to
+    100, and back to the k-step kernel, every phase continues the oracle's
+    trajectory exactly."""
+    L, N, vmax, p, seed = 20011, 5003, 5, 0.13, 12
+    g0 = oracle.init_grid(L, N, vmax, seed, init_v=1)
+    x0, v0 = oracle.grid_to_agent(g0)
+    phases = [("onestep", 0, 13), ("kstep", 1, 9), ("onestep", 0, 11), ("kstep", 100, 120),
+              ("onestep", 0, 7), ("kstep", 7, 30), ("onestep", 0, 17), ("kstep", 32, 40),
+              ("onestep", 0, 5)]
+    T = sum(n for _, _, n in phases)
+    s = Sim(L, N, vmax, p, seed, rep="agent", rng=rng, init_v=1, use_graph=True)
+    try:
+        for kernel, k, n in phases:
+            s.set_tuning(kernel, k=k)
+            s.step(n)
+        if rng == "stream":
+            # the serial stream oracle keeps the cars in index order, as the kernels do
+            xo, vo, fo = oracle.run_agent_mlcg(L, x0, v0, vmax, p, seed, T)
+            x, v = s.agent_state()
+            np.testing.assert_array_equal(x, xo)
+            np.testing.assert_array_equal(v, vo)
+        else:
+            g, fo = oracle.run_grid(g0, vmax, p, seed, T)
+            np.testing.assert_array_equal(s.snapshot()[0], g)
+        np.testing.assert_array_equal(s.flux(0, T), fo)
     finally:
         s.close()
 
