@@ -78,7 +78,7 @@ extern "C" {
 #define NASCH_INIT_V_ZERO    0u
 #define NASCH_INIT_V_UNIFORM 1u
 #define NASCH_KERNEL_AUTO    0u /* autotuned: the temporal-blocked kernel, (k, q) chosen by timing */
-#define NASCH_KERNEL_ONESTEP 1u /* grid: one byte-wise step per launch (k = 1, no blocking) */
+#define NASCH_KERNEL_ONESTEP 1u /* one step per launch (no blocking); grid: on the byte form; agent: one-step launches of the k-step kernel */
 #define NASCH_KERNEL_KSTEP   2u /* grid: k steps per launch, bit-sliced, k*vmax halo; agent: k steps per launch */
 #define NASCH_RNG_KEYED      0u /* rule 3 draws R(seed, replica, t, x), see above */
 #define NASCH_RNG_STREAM     1u /* agent form only: the paper's one shared stream, see below */
