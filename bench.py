@@ -308,6 +308,21 @@ def bench_single(args, cfg, rep, kernels):
         # one step per launch moves all of them every step: HBM-bound
         res["onestep_hbm_frac"] = res["onestep"] * bpcu / HBM_PEAK
     if rep == "grid" and cfg["L"] >= 1 << 24:
+        # achievable HBM bandwidth: a device-to-device copy of 1 GiB (torch's
+        # copy kernel), timed with events on its stream; bytes read + written
+        n = 1 << 30
+        a = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+        c = torch.empty_like(a)
+        c.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            c.copy_(a)
+        e1.record()
+        e1.synchronize()
+        res["copy_GBps"] = 2.0 * n * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del a, c
+        torch.cuda.empty_cache()
         # the bit-sliced kernel without temporal blocking (k = 1): the one-step
         # path whose bound is HBM at 2 B per cell-update
         s = Sim(cfg["L"], cfg["N"], cfg["vmax"], cfg["p"], cfg["seed"], rep=rep,
@@ -332,7 +347,7 @@ def bench_single(args, cfg, rep, kernels):
                    "k": info["k"], "q": info["q"]},
         "hbm_roofline_frac": value * bpcu / HBM_PEAK,
         "bytes_per_cell_update": bpcu,
-        "extra": {(k if k.endswith("frac") else f"{k}_cups"): v for k, v in res.items()},
+        "extra": {(k if k.endswith(("frac", "GBps")) else f"{k}_cups"): v for k, v in res.items()},
     }
 
 
