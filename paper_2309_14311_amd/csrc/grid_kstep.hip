@@ -15,7 +15,10 @@
 //   rule 4   the cars with v3 == j are shifted j cells to the right, and the
 //            new thermometer is the suffix-OR of the shifted classes.
 // The road is stored in HBM in the same planes (RingDesc), so a launch loads
-// and stores VMAX + 1 words per 32 cells and converts nothing.
+// and stores VMAX + 1 words per 32 cells and converts nothing.  The BYTES
+// instantiations read and write the road's byte form instead and convert each
+// word in registers (bitplanes.hpp); launched with k = 1 they are the one-step
+// kernel.
 // Neighbouring words come from the same lane or, at lane edges, from lane +-1
 // by cross-lane shuffles.  The segment is the tile's owned cells plus a halo
 // of H >= k*vmax cells on each side (read modulo L, so short rings repeat
@@ -386,7 +389,8 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     uint32_t obst[Q];     // open road: cell L
     uint32_t inj[Q];      // open road: cell 0
 
-    // ---- load: bytes -> bit planes
+    // ---- load the segment's words as bit planes (from the planes in HBM, or
+    // from the byte form converted in registers)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const uint32_t j0 = 32u * (lane * Q + q);
@@ -582,7 +586,8 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     }
 
     // ---- store the owned cells (whole words: tiles start on word boundaries;
-    // the road's last word keeps zeros past cell L-1)
+    // the road's last plane word keeps zeros past cell L-1, and its last byte
+    // word is written cell by cell up to L-1)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         if (own[q] == 0u) continue;
