@@ -308,19 +308,26 @@ def bench_single(args, cfg, rep, kernels):
         # one step per launch moves all of them every step: HBM-bound
         res["onestep_hbm_frac"] = res["onestep"] * bpcu / HBM_PEAK
     if rep == "grid" and cfg["L"] >= 1 << 24:
-        # achievable HBM bandwidth: a device-to-device copy of 1 GiB (torch's
-        # copy kernel), timed with events on its stream; bytes read + written
+        # achievable HBM bandwidth, bytes read + written over 1 GiB, timed with
+        # events: the runtime's device-to-device copy, and an elementwise
+        # read-modify-write kernel (the faster of the two here)
         n = 1 << 30
         a = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
         c = torch.empty_like(a)
-        c.copy_(a)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            c.copy_(a)
-        e1.record()
-        e1.synchronize()
-        res["copy_GBps"] = 2.0 * n * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+        def rate(fn):
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                fn()
+            e1.record()
+            e1.synchronize()
+            return 2.0 * n * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+        res["copy_GBps"] = rate(lambda: c.copy_(a))
+        res["stream_rw_GBps"] = rate(lambda: torch.add(a.view(torch.float32), 1.0,
+                                                        out=c.view(torch.float32)))
         del a, c
         torch.cuda.empty_cache()
         # the bit-sliced kernel without temporal blocking (k = 1): the one-step
