@@ -280,6 +280,23 @@ int nasch_batch_flux(nasch_batch* b, uint32_t r, uint64_t t0, uint64_t count, ui
 /* Grid of replica r (L_r bytes) and the step count.  Synchronises. */
 int nasch_batch_snapshot(nasch_batch* b, uint32_t r, uint8_t* out, uint64_t* t_out);
 
+/* Checkpoint of the whole batch: every replica's grid, back to back in replica
+ * order (replica r's L_r bytes start at L_0 + ... + L_{r-1}; out holds the sum
+ * of the L_r), and the step count.  out is caller-owned host memory; one
+ * conversion launch and one copy.  Synchronises.  NASCH_EINVAL for a NULL out. */
+int nasch_batch_snapshot_all(nasch_batch* b, uint8_t* out, uint64_t* t_out);
+
+/* Resume from a checkpoint (the model state is the grid, so this is what
+ * checkpoint and resume of an ensemble need; see nasch_restore for one ring):
+ * every replica's grid from `grids`, laid out as nasch_batch_snapshot_all writes
+ * it (host memory, caller-owned, read before the call returns), and the step
+ * counter set to t for all replicas.  Each cell must be 0xFF or at most the
+ * replica's vmax, and a ring's car count must equal its N (an open road's may
+ * differ).  The flux sums and the flux log are cleared.  Synchronises.
+ * NASCH_EINVAL for a bad grid (the batch is then unchanged), NASCH_ERANGE for
+ * t >= 2^32, NASCH_ENOMEM if the staging copy cannot be allocated. */
+int nasch_batch_restore(nasch_batch* b, const uint8_t* grids, uint64_t t);
+
 /* Choose (k, q) for this batch by timing candidates on a scratch copy of the
  * arena (the replicas do not advance); *k_out / *q_out may be NULL. */
 int nasch_batch_autotune(nasch_batch* b, uint32_t* k_out, uint32_t* q_out);

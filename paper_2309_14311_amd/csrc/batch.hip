@@ -277,6 +277,120 @@ int nasch_batch_snapshot(nasch_batch* b, uint32_t r, uint8_t* out, uint64_t* t_o
     return NASCH_OK;
 }
 
+// The checkpoint of a batch as the caller sees it is every replica's grid back
+// to back.  On the device each replica gets a 256-byte aligned slice of a
+// staging buffer instead (the conversion kernels move whole words with 16-byte
+// accesses), and the host packs or unpacks the two layouts.
+static uint64_t staged_bytes(const nasch_batch* b, std::vector<uint64_t>& offs) {
+    uint64_t off = 0;
+    offs.clear();
+    for (const RingDesc& d : b->eng.rings) {
+        offs.push_back(off);
+        off += ((uint64_t)d.L + 255u) / 256u * 256u;
+    }
+    return off;
+}
+
+// Convert every replica between its planes pl[parity] and its staging slice,
+// with a temporary device copy of the job table.
+static int convert_staged(nasch_batch* b, uint8_t* d_stage, const std::vector<uint64_t>& offs,
+                          uint32_t parity, bool to_planes) {
+    std::vector<ConvJob> jobs;
+    for (size_t r = 0; r < b->eng.rings.size(); ++r) {
+        const RingDesc& d = b->eng.rings[r];
+        jobs.push_back(ConvJob{d_stage + offs[r], d.pl[parity], d.L, d.nw, d.vmax, 0u});
+    }
+    ConvJob* d_jobs = nullptr;
+    if (!b->ok(dev_alloc(&d_jobs, jobs.size()))) return NASCH_ENOMEM;
+    int rc = NASCH_OK;
+    if (!b->ok(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(ConvJob),
+                              hipMemcpyHostToDevice, b->stream)) ||
+        !b->ok(to_planes ? launch_bytes_to_planes(d_jobs, b->d_conv_chunks, b->n_conv_chunks,
+                                                  b->stream)
+                         : launch_planes_to_bytes(d_jobs, b->d_conv_chunks, b->n_conv_chunks,
+                                                  b->stream)) ||
+        !b->ok(hipStreamSynchronize(b->stream)))
+        rc = NASCH_EDEVICE;
+    (void)hipFree(d_jobs);
+    return rc;
+}
+
+int nasch_batch_snapshot_all(nasch_batch* b, uint8_t* out, uint64_t* t_out) {
+    if (!b || !out) return NASCH_EINVAL;
+    std::vector<uint64_t> offs;
+    const uint64_t staged = staged_bytes(b, offs);
+    std::vector<uint8_t> host;
+    uint8_t* d_stage = nullptr;
+    if (!b->ok(hipStreamSynchronize(b->stream))) return NASCH_EDEVICE;
+    try {
+        host.resize(staged);
+    } catch (const std::bad_alloc&) {
+        return NASCH_ENOMEM;
+    }
+    if (!b->ok(dev_alloc(&d_stage, staged))) return NASCH_ENOMEM;
+    int rc = convert_staged(b, d_stage, offs, b->parity, false);
+    if (!rc && !b->ok(hipMemcpy(host.data(), d_stage, staged, hipMemcpyDeviceToHost)))
+        rc = NASCH_EDEVICE;
+    (void)hipFree(d_stage);
+    if (rc) return rc;
+    uint64_t pos = 0;
+    for (size_t r = 0; r < b->eng.rings.size(); ++r) {
+        std::memcpy(out + pos, host.data() + offs[r], b->eng.rings[r].L);
+        pos += b->eng.rings[r].L;
+    }
+    if (t_out) *t_out = b->t;
+    return NASCH_OK;
+}
+
+int nasch_batch_restore(nasch_batch* b, const uint8_t* grids, uint64_t t) {
+    if (!b || !grids) return NASCH_EINVAL;
+    if (t > 0xFFFFFFFFull) return NASCH_ERANGE;
+    // validate everything before touching the device state
+    uint64_t pos = 0;
+    for (const nasch_replica& p : b->reps) {
+        uint64_t cars = 0;
+        for (uint64_t i = 0; i < p.L; ++i) {
+            const uint8_t c = grids[pos + i];
+            if (c == 0xFFu) continue;
+            if (c > p.vmax) return NASCH_EINVAL;
+            ++cars;
+        }
+        if (p.boundary != NASCH_BOUNDARY_OPEN && cars != p.N) return NASCH_EINVAL;
+        pos += p.L;
+    }
+    std::vector<uint64_t> offs;
+    const uint64_t staged = staged_bytes(b, offs);
+    std::vector<uint8_t> host;
+    try {
+        host.assign(staged, 0xFFu);
+    } catch (const std::bad_alloc&) {
+        return NASCH_ENOMEM;
+    }
+    pos = 0;
+    for (size_t r = 0; r < b->eng.rings.size(); ++r) {
+        std::memcpy(host.data() + offs[r], grids + pos, b->eng.rings[r].L);
+        pos += b->eng.rings[r].L;
+    }
+    const uint32_t R = (uint32_t)b->reps.size();
+    uint8_t* d_stage = nullptr;
+    if (!b->ok(hipStreamSynchronize(b->stream))) return NASCH_EDEVICE;
+    if (!b->ok(dev_alloc(&d_stage, staged))) return NASCH_ENOMEM;
+    int rc = NASCH_OK;
+    if (!b->ok(hipMemcpy(d_stage, host.data(), staged, hipMemcpyHostToDevice))) rc = NASCH_EDEVICE;
+    if (!rc) rc = convert_staged(b, d_stage, offs, 0u, true);
+    (void)hipFree(d_stage);
+    if (rc) return rc;
+    const Clock c{(uint32_t)t, 0u};
+    if (!b->ok(launch_fill_u64(b->d_acc, R, b->stream)) ||
+        (b->d_log && !b->ok(launch_fill_u64(b->d_log, (uint64_t)R * b->log_steps, b->stream))) ||
+        !b->ok(hipMemcpyAsync(b->d_clk, &c, sizeof(Clock), hipMemcpyHostToDevice, b->stream)) ||
+        !b->ok(hipStreamSynchronize(b->stream)))
+        return NASCH_EDEVICE;
+    b->t = t;
+    b->parity = 0;
+    return NASCH_OK;
+}
+
 int nasch_batch_set_tuning(nasch_batch* b, uint32_t k, uint32_t q) {
     if (!b) return NASCH_EINVAL;
     if (k == 0) k = b->eng.k;

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kConvChunk) void bytes_to_planes_kernel(const ConvJ
     if (!conv_job(jobs, chunks, single, J, w)) return;
     const uint64_t c0 = (uint64_t)w * 32u;
     uint32_t by[8];
-    if (c0 + 32u <= J.L) {
+    if (c0 + 32u <= J.L) {   // J.bytes is 16-byte aligned (every caller's buffers are)
         const uint4* p = reinterpret_cast<const uint4*>(J.bytes + c0);
         const uint4 a = p[0], b = p[1];
         by[0] = a.x; by[1] = a.y; by[2] = a.z; by[3] = a.w;
@@ -143,7 +143,8 @@ __global__ __launch_bounds__(kConvChunk) void planes_to_bytes_kernel(const ConvJ
         p[0] = make_uint4(by[0], by[1], by[2], by[3]);
         p[1] = make_uint4(by[4], by[5], by[6], by[7]);
     } else {
-        for (uint32_t i = 0; c0 + i < J.L; ++i) J.bytes[c0 + i] = (uint8_t)(by[i >> 2] >> (8 * (i & 3)));
+        for (uint32_t i = 0; i < 32u && c0 + i < J.L; ++i)
+            J.bytes[c0 + i] = (uint8_t)(by[i >> 2] >> (8 * (i & 3)));
     }
 }
 

@@ -104,6 +104,8 @@ _SIGS = {
     "nasch_batch_flux_sums": (I32, [VP, u64p]),
     "nasch_batch_flux": (I32, [VP, U32, U64, U64, u64p]),
     "nasch_batch_snapshot": (I32, [VP, U32, u8p, u64p]),
+    "nasch_batch_snapshot_all": (I32, [VP, u8p, u64p]),
+    "nasch_batch_restore": (I32, [VP, u8p, U64]),
     "nasch_batch_autotune": (I32, [VP, u32p, u32p]),
     "nasch_batch_set_tuning": (I32, [VP, U32, U32]),
     "nasch_batch_last_device_error": (I32, [VP]),
@@ -339,6 +341,22 @@ class Batch:
         self._check(_lib.nasch_batch_snapshot(self._h, r, _u8(out), ctypes.byref(t)),
                     "nasch_batch_snapshot")
         return out, t.value
+
+    def snapshot_all(self):
+        """Every replica's grid back to back (replica order) and the step count."""
+        out = np.empty(sum(r["L"] for r in self.replicas), np.uint8)
+        t = ctypes.c_uint64()
+        self._check(_lib.nasch_batch_snapshot_all(self._h, _u8(out), ctypes.byref(t)),
+                    "nasch_batch_snapshot_all")
+        return out, t.value
+
+    def restore(self, grids, t):
+        """Set every replica's grid (back to back, as snapshot_all returns them) and
+        the step count."""
+        g = np.ascontiguousarray(grids, dtype=np.uint8)
+        if g.size != sum(r["L"] for r in self.replicas):
+            raise ValueError("grids must hold every replica's L cells back to back")
+        self._check(_lib.nasch_batch_restore(self._h, _u8(g), t), "nasch_batch_restore")
 
     def autotune(self):
         k, q = ctypes.c_uint32(), ctypes.c_uint32()

@@ -138,3 +138,90 @@ def test_open_and_ring_replicas_do_not_mix():
     bad[2]["alpha"] = float("nan")
     with pytest.raises(NaschError):
         Batch(bad)
+
+
+def test_every_state_of_a_tiny_ring_in_one_batch():
+    """Every grid state of a ring of L = 8 cells with vmax = 3 (5^8 = 390625
+    states, each cell empty or a car with v = 0..3) as the replicas of one
+    batch, restored in one call: after 40 steps (launches of 16, 16 and 8) every
+    replica's grid and flux sum equal the oracle's.  The ring is far shorter
+    than the k vmax halo, so every segment holds many periodic images; p = 0.3
+    has bits below its top nibble, so tied draws are refined too."""
+    import itertools
+    L, vmax, p, seed, T = 8, 3, 0.3, 77, 40
+    states = np.array(list(itertools.product(range(vmax + 2), repeat=L)), np.uint8)
+    states[states == vmax + 1] = 0xFF
+    cars = (states != 0xFF).sum(axis=1)
+    reps = [dict(L=L, N=int(n), vmax=vmax, p=p, seed=seed, replica=i) for i, n in enumerate(cars)]
+    b = Batch(reps, k=16, q=2, use_graph=True)
+    try:
+        b.restore(states.reshape(-1), 0)
+        b.step(T)
+        got, t = b.snapshot_all()
+        assert t == T
+        got = got.reshape(-1, L)
+        sums = b.flux_sums()
+    finally:
+        b.close()
+    bad = []
+    for i in range(len(reps)):
+        g, flux = oracle.run_grid(states[i], vmax, p, seed, T, replica=i)
+        if not np.array_equal(got[i], g) or int(sums[i]) != int(flux.sum()):
+            bad.append(i)
+            if len(bad) >= 5:
+                break
+    assert not bad, f"replicas {bad}: first state {states[bad[0]]}"
+
+
+def test_batch_checkpoint_and_resume():
+    """snapshot_all at t = 150, restore into a fresh batch, 100 more steps:
+    grids and the flux of those steps equal the uninterrupted run's."""
+    reps = _small_ensemble(24, seed=13)
+    for r in reps:
+        r["warmup"] = 0
+    a = Batch(reps, keep_log=True, log_steps=250)
+    try:
+        a.step(150)
+        snap, t = a.snapshot_all()
+        assert t == 150
+        mid_sums = a.flux_sums().copy()
+        a.step(100)
+        want, _ = a.snapshot_all()
+        want_sums = a.flux_sums() - mid_sums
+        want_log = [a.flux(i, 150, 100) for i in range(len(reps))]
+    finally:
+        a.close()
+    b = Batch(reps, keep_log=True, log_steps=250, use_graph=True)
+    try:
+        b.restore(snap, 150)
+        b.step(100)
+        got, t = b.snapshot_all()
+        assert t == 250
+        np.testing.assert_array_equal(got, want)
+        np.testing.assert_array_equal(b.flux_sums(), want_sums)
+        for i in range(len(reps)):
+            np.testing.assert_array_equal(b.flux(i, 150, 100), want_log[i])
+        # the per-replica snapshot agrees with the whole-batch one
+        off = 0
+        for i, r in enumerate(reps):
+            np.testing.assert_array_equal(b.snapshot(i)[0], got[off:off + r["L"]])
+            off += r["L"]
+    finally:
+        b.close()
+
+
+def test_batch_restore_rejects_bad_grids():
+    reps = [dict(L=40, N=10, vmax=3, p=0.2, seed=1, replica=i) for i in range(3)]
+    b = Batch(reps)
+    try:
+        good, _ = b.snapshot_all()
+        for bad in (np.where(good == 0xFF, 0xFF, 4).astype(np.uint8),    # v > vmax
+                    np.full_like(good, 0xFF)):                            # car count != N
+            with pytest.raises(NaschError):
+                b.restore(bad, 5)
+        with pytest.raises(NaschError):
+            b.restore(good, 2**32)
+        b.restore(good, 7)    # a good checkpoint still restores
+        assert b.snapshot_all()[1] == 7
+    finally:
+        b.close()
