@@ -77,12 +77,11 @@ def _traffic(k, q, launch_cell_updates):
     return None
 
 
-def cpu_baseline_ensemble(reps, budget_s=15.0, steps=100):
-    """The oracle (all-core OpenMP twin) on a bounded sample of the ensemble:
-    replicas taken in order, each run `steps` steps from its initial state,
-    until `budget_s` seconds of CPU work have been spent."""
+def _time_oracle(reps, nthreads, budget_s, steps):
+    """Run the oracle on replicas taken in order, each `steps` steps from its
+    initial state, until `budget_s` seconds of CPU work have been spent; returns
+    (cell-updates done, seconds spent, replicas run, threads used)."""
     import oracle
-    nthreads = min(16, os.cpu_count() or 1)
     done_cells, spent, n = 0, 0.0, 0
     for r in reps:
         g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
@@ -91,6 +90,7 @@ def cpu_baseline_ensemble(reps, budget_s=15.0, steps=100):
         if r.get("boundary") == "open":   # the serial open-road step (no threaded twin)
             oracle.run_open(g0, r["vmax"], r["p"], r["alpha"], r["beta"], r["seed"], steps,
                             replica=r["replica"])
+            nthreads = 1
         else:
             oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], steps, replica=r["replica"],
                             nthreads=nthreads)
@@ -99,12 +99,23 @@ def cpu_baseline_ensemble(reps, budget_s=15.0, steps=100):
         n += 1
         if spent >= budget_s:
             break
-    if any(r.get("boundary") == "open" for r in reps):
-        nthreads = 1
-    return {"value": done_cells / spent, "unit": "cell-updates/s", "cores": nthreads,
-            "kind": "oracle",
-            "sample": f"first {n} of {len(reps)} replicas, {steps} steps each from t=0, "
-                      f"{done_cells:.3g} cell-updates in {spent:.1f} s"}
+    return done_cells, spent, n, nthreads
+
+
+def cpu_baseline_ensemble(reps, budget_s=15.0, steps=100):
+    """The oracle on a bounded sample of the ensemble: the all-core OpenMP twin
+    for `budget_s` seconds (the reported value), then the serial oracle for
+    half as long on the same replicas."""
+    def sample(cells, spent, n):
+        return (f"first {n} of {len(reps)} replicas, {steps} steps each from t=0, "
+                f"{cells:.3g} cell-updates in {spent:.1f} s")
+
+    cells, spent, n, threads = _time_oracle(reps, min(16, os.cpu_count() or 1), budget_s, steps)
+    s_cells, s_spent, s_n, _ = _time_oracle(reps, 1, budget_s / 2, steps)
+    return {"value": cells / spent, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle", "sample": sample(cells, spent, n),
+            "serial": {"value": s_cells / s_spent, "unit": "cell-updates/s", "cores": 1,
+                       "sample": sample(s_cells, s_spent, s_n)}}
 
 
 def bench_ensemble(args):

@@ -1,5 +1,5 @@
 """Host-side logic of the benchmark (no GPU): the algorithmic operation count
-behind the k-step kernel's roofline, and the one-GPU guard."""
+behind the k-step kernel's roofline, the one-GPU guard and the CPU baseline."""
 import os
 import subprocess
 import sys
@@ -33,3 +33,13 @@ def test_more_than_one_gpu_is_refused(n):
     assert r.returncode == 2
     assert "one GPU" in r.stderr or "1 GPU" in r.stderr or "--gpus 1" in r.stderr
     assert r.stdout == ""
+
+
+def test_cpu_baseline_reports_all_core_and_serial_oracle():
+    from paper_2309_14311_amd import workloads
+    reps = workloads.ensemble(8, seed=1, T=5000, warmup=1000)
+    cb = bench.cpu_baseline_ensemble(reps, budget_s=0.2, steps=10)
+    assert cb["kind"] == "oracle" and cb["unit"] == "cell-updates/s"
+    assert cb["value"] > 0 and 1 <= cb["cores"] <= 16
+    assert cb["serial"]["cores"] == 1 and cb["serial"]["value"] > 0
+    assert "replicas" in cb["sample"] and "replicas" in cb["serial"]["sample"]
