@@ -1,36 +1,34 @@
 // bitplanes.hpp -- conversion between the byte form of the road (one byte per
 // cell: 0xFF empty, else the car's v <= 8) and the bit planes of the bit-sliced
-// kernels, 32 cells at a time, by 8x8 bit-matrix transposes.
+// kernels, 32 cells at a time, by bit-matrix transposes in registers.
 //
 // A 32-cell word is eight 32-bit values d[0..7]: cell 4i + b is byte b of d[i].
-// Its eight bit planes P[0..7] hold, in bit c, bit k of cell c's byte.  Each
-// 8-cell block (two of the d) is an 8x8 bit matrix whose transpose puts the
-// cells' bit k in its byte k; the planes are then the blocks' bytes side by
-// side.  The thermometer planes the kernels use (T[0] occupancy, T[m] v >= m)
-// follow from the planes of bits 0..3 (v) and bit 7 (empty).
+// Such a byte is 0xFF or at most 8, so its low four bits (its code) identify it:
+// code 15 only for an empty cell.  The four code planes N[0..3] hold, in bit c,
+// bit k of cell c's code.  Packed two cells to a byte, the codes of eight cells
+// fill one 32-bit value: in nibble word i (cells 8i .. 8i+7), byte j holds cell
+// 8i + j in its low and cell 8i + 4 + j in its high nibble, so bit 8j + 4h + k
+// is bit k of cell 8i + 4h + j.  Exchanging the index bits j and k (two delta
+// swaps) puts bit k of the eight cells in byte k, and the code planes are
+// those bytes side by side.  The thermometer planes the kernels use (T[0]
+// occupancy, T[m] v >= m) follow from the code planes.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace nasch {
 
-// 8x8 bit-matrix transpose of the 64-bit block (hi:lo): bit 8r + c and bit
-// 8c + r trade places.  Three delta swaps exchange the bits one, two and four
-// places off the diagonal (2x2, then 4x4 sub-blocks).
-__host__ __device__ inline void transpose8x8(uint32_t& lo, uint32_t& hi) {
-    uint32_t t;
-    t = (lo ^ (lo >> 7)) & 0x00AA00AAu;
-    lo ^= t ^ (t << 7);
-    t = (hi ^ (hi >> 7)) & 0x00AA00AAu;
-    hi ^= t ^ (t << 7);
-    t = (lo ^ (lo >> 14)) & 0x0000CCCCu;
-    lo ^= t ^ (t << 14);
-    t = (hi ^ (hi >> 14)) & 0x0000CCCCu;
-    hi ^= t ^ (t << 14);
-    // the last swap crosses the halves: (hi:lo) >> 28 against (hi:lo)
-    t = (lo ^ ((lo >> 28) | (hi << 4))) & 0xF0F0F0F0u;
-    lo ^= t;
-    hi ^= t >> 4;
+// Exchange the bits of x selected by m with the bits d places above them.
+__host__ __device__ inline uint32_t delta_swap(uint32_t x, uint32_t m, int d) {
+    const uint32_t t = (x ^ (x >> d)) & m;
+    return x ^ t ^ (t << d);
+}
+
+// Bit 8j + 4h + k and bit 8k + 4h + j trade places (j, k in 0..3, h in 0..1):
+// index bits 0 and 3 are exchanged 7 places apart, index bits 1 and 4 14
+// places apart.  The map is its own inverse.
+__host__ __device__ inline uint32_t nibble_transpose(uint32_t x) {
+    return delta_swap(delta_swap(x, 0x00AA00AAu, 7), 0x0000CCCCu, 14);
 }
 
 // byte j of x, moved to byte position `to`
@@ -38,36 +36,38 @@ __host__ __device__ inline uint32_t byte_at(uint32_t x, int j, int to) {
     return ((x >> (8 * j)) & 0xFFu) << (8 * to);
 }
 
-// The eight bit planes of a 32-cell word of bytes.
-__host__ __device__ inline void bytes_to_bitplanes(const uint32_t (&d)[8], uint32_t (&P)[8]) {
-    uint32_t lo[4], hi[4];
+// The four code planes of a 32-cell word of bytes.
+__host__ __device__ inline void bytes_to_code_planes(const uint32_t (&d)[8], uint32_t (&N)[4]) {
+    uint32_t n[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        lo[j] = d[2 * j];
-        hi[j] = d[2 * j + 1];
-        transpose8x8(lo[j], hi[j]);   // byte k: bit k of cells 8j .. 8j+7
-    }
+    for (int i = 0; i < 4; ++i)
+        n[i] = nibble_transpose((d[2 * i] & 0x0F0F0F0Fu) | ((d[2 * i + 1] << 4) & 0xF0F0F0F0u));
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        P[k] = byte_at(lo[0], k, 0) | byte_at(lo[1], k, 1) | byte_at(lo[2], k, 2) |
-               byte_at(lo[3], k, 3);
-        P[k + 4] = byte_at(hi[0], k, 0) | byte_at(hi[1], k, 1) | byte_at(hi[2], k, 2) |
-                   byte_at(hi[3], k, 3);
+    for (int k = 0; k < 4; ++k)
+        N[k] = byte_at(n[0], k, 0) | byte_at(n[1], k, 1) | byte_at(n[2], k, 2) | byte_at(n[3], k, 3);
+}
+
+// Each byte of x holds a code (0..8, or 15 for an empty cell); 15 becomes 0xFF.
+// Only code 15 has both bit 3 and bit 0 set, so x & (x << 3) leaves 8 in those
+// bytes and nothing elsewhere, and 8 * 30 = 0xF0 fills their high nibble.
+__host__ __device__ inline uint32_t code_bytes(uint32_t x) {
+    return x | ((x & (x << 3)) * 30u);
+}
+
+// The 32 bytes of a word from its code planes (the inverse).
+__host__ __device__ inline void code_planes_to_bytes(const uint32_t (&N)[4], uint32_t (&d)[8]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t n = nibble_transpose(byte_at(N[0], i, 0) | byte_at(N[1], i, 1) |
+                                            byte_at(N[2], i, 2) | byte_at(N[3], i, 3));
+        d[2 * i] = code_bytes(n & 0x0F0F0F0Fu);
+        d[2 * i + 1] = code_bytes((n >> 4) & 0x0F0F0F0Fu);
     }
 }
 
-// The 32 bytes of a word from its eight bit planes (the inverse).
-__host__ __device__ inline void bitplanes_to_bytes(const uint32_t (&P)[8], uint32_t (&d)[8]) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        uint32_t lo = byte_at(P[0], j, 0) | byte_at(P[1], j, 1) | byte_at(P[2], j, 2) |
-                      byte_at(P[3], j, 3);
-        uint32_t hi = byte_at(P[4], j, 0) | byte_at(P[5], j, 1) | byte_at(P[6], j, 2) |
-                      byte_at(P[7], j, 3);
-        transpose8x8(lo, hi);
-        d[2 * j] = lo;
-        d[2 * j + 1] = hi;
-    }
+// Occupancy from the code planes: only an empty cell has code bits 3 and 0 both set.
+__host__ __device__ inline uint32_t code_occupied(const uint32_t (&N)[4]) {
+    return ~(N[0] & N[3]);
 }
 
 // (b3 b2 b1 b0) >= M, bit-sliced over 32 cells, for a constant 1 <= M <= 15.
@@ -102,11 +102,11 @@ struct ThermoFill {
 // T[m] the cells whose car has v >= m.
 template <int VMAX>
 __host__ __device__ inline void bytes_to_thermo(const uint32_t (&d)[8], uint32_t (&T)[VMAX + 1]) {
-    uint32_t P[8];
-    bytes_to_bitplanes(d, P);
-    const uint32_t occ = ~P[7];   // v <= 8 leaves bit 7 clear; 0xFF sets it
+    uint32_t N[4];
+    bytes_to_code_planes(d, N);
+    const uint32_t occ = code_occupied(N);
     T[0] = occ;
-    ThermoFill<VMAX, 1>::run(occ, P[0], P[1], P[2], P[3], T);
+    ThermoFill<VMAX, 1>::run(occ, N[0], N[1], N[2], N[3], T);
 }
 
 // T[M] of a thermometer code, zero above VMAX.
@@ -131,8 +131,8 @@ __host__ __device__ inline void thermo_to_bytes(const uint32_t (&T)[VMAX + 1], u
     const uint32_t b1 = (t2 & ~t4) | (t6 & ~t8);
     const uint32_t b2 = t4 & ~t8;
     const uint32_t b3 = t8;
-    const uint32_t P[8] = {b0 | e, b1 | e, b2 | e, b3 | e, e, e, e, e};
-    bitplanes_to_bytes(P, d);
+    const uint32_t N[4] = {b0 | e, b1 | e, b2 | e, b3 | e};   // code 15 where empty
+    code_planes_to_bytes(N, d);
 }
 
 }  // namespace nasch

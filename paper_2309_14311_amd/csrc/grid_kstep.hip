@@ -489,8 +489,9 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     uint32_t acc = 0u;
     const bool log = R.flux_log != nullptr;
     // steps of this launch before the warm-up ends (their flux is not summed)
-    const uint32_t s_warm =
-        R.warmup > (uint64_t)t0 ? (uint32_t)min<uint64_t>(R.warmup - t0, nsteps) : 0u;
+    // (compared as integers: min<uint64_t> here compiled to double-precision instructions)
+    const uint64_t to_warm = R.warmup > (uint64_t)t0 ? R.warmup - t0 : 0u;
+    const uint32_t s_warm = to_warm < nsteps ? (uint32_t)to_warm : nsteps;
     for (uint32_t s = 0; s < nsteps; ++s) {
         const uint32_t t = t0 + s;
         uint32_t fl = 0;

@@ -61,8 +61,8 @@ hipError_t launch_init_grid(uint8_t* g, uint32_t L, uint32_t N, uint32_t vmax, u
 
 // ---- bytes <-> bit planes ------------------------------------------------------
 // One thread per 32-cell word, a block per kConvChunk words of one job.
-// The bytes of a word and their bit planes are exchanged with the 8x8 bit
-// transposes of bitplanes.hpp; vmax is a run-time value here.
+// The bytes of a word and their code planes are exchanged with the transposes
+// of bitplanes.hpp; vmax is a run-time value here.
 namespace {
 // (P3 P2 P1 P0) >= m, bit-sliced over 32 cells, for 1 <= m <= 15
 __device__ __forceinline__ uint32_t ge_value(const uint32_t (&P)[4], uint32_t m) {
@@ -110,10 +110,9 @@ __global__ __launch_bounds__(kConvChunk) void bytes_to_planes_kernel(const ConvJ
             by[d] = y;
         }
     }
-    uint32_t bits[8];
-    bytes_to_bitplanes(by, bits);
-    const uint32_t P[4] = {bits[0], bits[1], bits[2], bits[3]};   // v, bit by bit
-    const uint32_t occ = ~bits[7];                                 // 0xFF has bit 7
+    uint32_t P[4];   // v, bit by bit (code 15 where empty)
+    bytes_to_code_planes(by, P);
+    const uint32_t occ = code_occupied(P);
     J.planes[w] = occ;
     for (uint32_t m = 1; m <= J.vmax; ++m) J.planes[(uint64_t)m * J.nw + w] = occ & ge_value(P, m);
 }
@@ -133,10 +132,10 @@ __global__ __launch_bounds__(kConvChunk) void planes_to_bytes_kernel(const ConvJ
     const uint32_t B2 = T[4] & ~T[8];
     const uint32_t B3 = T[8];
     const uint32_t E = ~T[0];
-    // an empty cell gets every bit set: 0xFF
-    const uint32_t bits[8] = {B0 | E, B1 | E, B2 | E, B3 | E, E, E, E, E};
+    // an empty cell gets code 15, which becomes 0xFF
+    const uint32_t N[4] = {B0 | E, B1 | E, B2 | E, B3 | E};
     uint32_t by[8];
-    bitplanes_to_bytes(bits, by);
+    code_planes_to_bytes(N, by);
     const uint64_t c0 = (uint64_t)w * 32u;
     if (c0 + 32u <= J.L) {
         uint4* p = reinterpret_cast<uint4*>(J.bytes + c0);
