@@ -168,9 +168,9 @@ __device__ __forceinline__ void slow_hi(const uint32_t (&moving)[Q], const uint3
 
 // Rule 3, second stage, shared by the whole wave.  The tied cars of every lane
 // (bits of U, word by word, in order) are numbered with a wave prefix sum and
-// queued in LDS as (word, bit) codes; the wave then draws their low 28 bits 64
-// at a time, reading the word's first ring cell from a table written once per
-// launch, and ORs each slow car into an LDS mask of its word.  Every lane then
+// queued in LDS as (word, bit) codes, which are their segment cells; the wave
+// then draws their low 28 bits 64 at a time, taking a car's ring cell from its
+// segment cell (see XMode), and ORs each slow car into an LDS mask of its word.  Every lane then
 // takes its words' masks (and clears them for the next step): one LDS read per
 // word instead of a loop over the lane's tied cars.  A word rarely holds more
 // than two tied cars, so those two are queued without a loop.  When the wave
@@ -181,9 +181,14 @@ constexpr uint32_t kRefineCap = 256;
 template <int Q>
 struct RefineLds {
     uint32_t code[kRefineCap];   // (lane Q + q) << 5 | bit of each queued car
-    uint32_t xw[64 * Q];         // ring cell of the first cell of every word
     uint32_t slow[64 * Q];       // slow cars found by the draws, per word
 };
+
+// The ring cell of segment cell j is seg0 + j reduced by XMode (uniform over the
+// wave): kXNone on an open road (seg0 is the road cell of segment cell 0, taken
+// modulo 2^32, and queued cars lie on the road), kXSub on a ring at least as
+// long as the segment (seg0 < L, so one subtraction), kXMod on a shorter ring.
+enum : uint32_t { kXNone = 0, kXSub = 1, kXMod = 2 };
 
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -193,9 +198,9 @@ __device__ __forceinline__ void wave_sync_lds() {
 
 template <int Q>
 __device__ __forceinline__ void slow_lo_wave(uint32_t (&S)[Q], const uint32_t (&U)[Q],
-                                             const uint32_t (&xw)[Q], uint32_t L, uint32_t t,
-                                             const SlowParams& sp, RefineLds<Q>& lds,
-                                             uint32_t lane) {
+                                             const uint32_t (&xw)[Q], uint32_t L, uint32_t seg0,
+                                             uint32_t x_mode, uint32_t t, const SlowParams& sp,
+                                             RefineLds<Q>& lds, uint32_t lane) {
     const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
     uint32_t cnt = 0;
 #pragma unroll
@@ -240,19 +245,15 @@ __device__ __forceinline__ void slow_lo_wave(uint32_t (&S)[Q], const uint32_t (&
         }
     }
     wave_sync_lds();
-    // a word's first cell is below L, so x < L + 31: one conditional
-    // subtraction brings it into the ring unless the ring is shorter than 32
-    const bool tiny = L < 32u;
     for (uint32_t p = lane; p < nq; p += 64u) {
-        const uint32_t c = lds.code[p];
-        const uint32_t w = c >> 5, b = c & 31u;
-        uint32_t x = lds.xw[w] + b;
-        if (tiny) {
-            if (x >= L) x %= L;
-        } else {
+        const uint32_t c = lds.code[p];   // the car's segment cell
+        uint32_t x = seg0 + c;
+        if (x_mode == kXSub) {
             x = min(x, x - L);   // x - L wraps above x unless x >= L
+        } else if (x_mode == kXMod) {
+            x %= L;
         }
-        if (slow_lo28(x, t, sp) < lo_thr) atomicOr(&lds.slow[w], 1u << b);
+        if (slow_lo28(x, t, sp) < lo_thr) atomicOr(&lds.slow[c >> 5], 1u << (c & 31u));
     }
     wave_sync_lds();
 #pragma unroll
@@ -468,7 +469,6 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     // rule-3 tables of this wave
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        rl.xw[lane * Q + q] = xw[q];
         rl.slow[lane * Q + q] = 0u;
     }
     wave_sync_lds();
@@ -484,6 +484,10 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
             draw_mode = (L >= 64u && __builtin_amdgcn_ballot_w64(!all_two) == 0u) ? kDrawTwo
                                                                                  : kDrawGeneric;
     }
+
+    // segment cell -> ring cell for the tied cars' draws
+    const uint32_t seg0 = OPEN ? (uint32_t)base : s0;
+    const uint32_t x_mode = OPEN ? kXNone : (L >= kstep_segment(Q) ? kXSub : kXMod);
 
     // ---- k steps
     uint32_t acc = 0u;
@@ -533,7 +537,8 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                 U[q] = 0u;
             }
             if (sp.thr != 0u) slow_hi<Q>(moving, xw, aligned, draw_mode, t, L, sp, S, U);  // rule 3
-            if ((sp.thr & 0x0FFFFFFFu) != 0u) slow_lo_wave<Q>(S, U, xw, L, t, sp, rl, lane);
+            if ((sp.thr & 0x0FFFFFFFu) != 0u)
+                slow_lo_wave<Q>(S, U, xw, L, seg0, x_mode, t, sp, rl, lane);
             uint32_t Eq[Q][VMAX + 1];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
