@@ -93,7 +93,10 @@ typedef struct {
     uint32_t init_v;   /* NASCH_INIT_V_ZERO or NASCH_INIT_V_UNIFORM                         */
     uint32_t kernel;   /* NASCH_KERNEL_*                                                    */
     uint32_t k;        /* steps per launch for NASCH_KERNEL_KSTEP; 0 = default             */
-    uint32_t q;        /* 32-cell words per lane for the bit-sliced kernel (1 to 4); 0 = default   */
+    uint32_t q;        /* grid form: 32-cell words per lane of the bit-sliced kernel (1 to 4);
+                          agent form: cars per lane of its k-step tiling (4 to 8), by default
+                          chosen from the density so that the rule-3 blocks a wave's cars
+                          start in take as few passes per car as possible; 0 = default       */
     uint32_t use_graph;/* 1: replay nasch_step_n launch sequences from a captured hipGraph */
     uint32_t rng;      /* NASCH_RNG_KEYED (default) or NASCH_RNG_STREAM (agent form only)   */
     void*    stream;   /* hipStream_t to run on; NULL = a stream owned by the handle        */

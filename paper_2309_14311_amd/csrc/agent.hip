@@ -3,8 +3,8 @@
 // uint8 velocities v[N].  Car i's distance to the car in front is
 // d = (x[i+1] - x[i]) mod L (d = L for a car alone); rules 1-4 follow.
 //
-// agent_kstep_kernel: one wave per 64 x kAgentCarsPerLane consecutive cars,
-// kept in registers for k steps.  Car i after s steps depends only on cars
+// agent_kstep_kernel<C>: one wave per 64 C consecutive cars (C per lane, chosen
+// on the host from the density), kept in registers for k steps.  Car i after s steps depends only on cars
 // i .. i+s, so the last k cars of a wave are a halo: each wave writes back the
 // first `own` cars and the waves overlap by the halo.  Launched with one step
 // it is the one-step kernel.
@@ -127,10 +127,13 @@ __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&
 }  // namespace
 
 // ---------------------------------------------------------------------------------
-constexpr uint32_t CPL = kAgentCarsPerLane;
-
-// F(t) of each wave and step goes to partials[s * ntiles + wave].
+// Wave w holds cars [w own, w own + 64 CPL) and writes back the first own of
+// them; F(t) of each wave and step goes to partials[s * ntiles + wave].  own is
+// a multiple of 8 (agent_geometry), so for CPL = 4 and 8 a lane's x and v are
+// aligned for vector loads and stores.
+template <int CPL>
 __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __restrict__ A,
+                                                          uint32_t own, uint32_t ntiles,
                                                           uint32_t* __restrict__ partials,
                                                           uint32_t k,
                                                           const Clock* __restrict__ clk,
@@ -139,9 +142,9 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t wave = blockIdx.x * 4u + wib;
-    if (wave >= A->ntiles) return;
+    if (wave >= ntiles) return;
     AgentLds& lds = s_lds[wib];
-    const uint32_t N = A->N, L = A->L, vmax = A->vmax, own = A->own;
+    const uint32_t N = A->N, L = A->L, vmax = A->vmax;
     const SlowParams sp = A->sp;
     const uint32_t t0 = clk->t + A->t + s_off;
     const uint32_t par = (clk->parity + A->parity + launch_idx) & 1u;
@@ -156,15 +159,29 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
 
     uint32_t x[CPL], v[CPL];
     if ((uint64_t)first + CPL <= N) {
-        const uint4* p = reinterpret_cast<const uint4*>(xs + first);
-        const uint4 a = p[0], b = p[1];
-        x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
-        const uint2 vv = *reinterpret_cast<const uint2*>(vs + first);
+        if constexpr (CPL == 8) {
+            const uint4* p = reinterpret_cast<const uint4*>(xs + first);
+            const uint4 a = p[0], b = p[1];
+            x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+            x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+            const uint2 vv = *reinterpret_cast<const uint2*>(vs + first);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            v[q] = (vv.x >> (8 * q)) & 0xFFu;
-            v[q + 4] = (vv.y >> (8 * q)) & 0xFFu;
+            for (int q = 0; q < 4; ++q) {
+                v[q] = (vv.x >> (8 * q)) & 0xFFu;
+                v[q + 4] = (vv.y >> (8 * q)) & 0xFFu;
+            }
+        } else if constexpr (CPL == 4) {
+            const uint4 a = *reinterpret_cast<const uint4*>(xs + first);
+            x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+            const uint32_t vv = *reinterpret_cast<const uint32_t*>(vs + first);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = (vv >> (8 * q)) & 0xFFu;
+        } else {
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                x[q] = (uint32_t)xs[first + q];
+                v[q] = vs[first + q];
+            }
         }
     } else {
 #pragma unroll
@@ -177,7 +194,6 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
 
     uint32_t acc = 0u;
     const bool log = A->flux_log != nullptr;
-    const uint32_t ntiles = A->ntiles;
     // shared stream: the number of the lane's first car at step t0, advanced
     // by a^N per step; car q adds a factor a, and a^-N when its index wraps.
     const uint32_t idx0 = (uint32_t)((uint64_t)first % N);
@@ -238,16 +254,28 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
 
     // write back the owned cars
     if (lane * CPL + CPL <= own_len) {
-        uint4* p = reinterpret_cast<uint4*>(xd + first);
-        p[0] = make_uint4(x[0], x[1], x[2], x[3]);
-        p[1] = make_uint4(x[4], x[5], x[6], x[7]);
-        uint32_t lo = 0, hi = 0;
+        if constexpr (CPL == 8) {
+            uint4* p = reinterpret_cast<uint4*>(xd + first);
+            p[0] = make_uint4(x[0], x[1], x[2], x[3]);
+            p[1] = make_uint4(x[4], x[5], x[6], x[7]);
+            uint32_t lo = 0, hi = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            lo |= v[q] << (8 * q);
-            hi |= v[q + 4] << (8 * q);
+            for (int q = 0; q < 4; ++q) {
+                lo |= v[q] << (8 * q);
+                hi |= v[q + 4] << (8 * q);
+            }
+            *reinterpret_cast<uint2*>(vd + first) = make_uint2(lo, hi);
+        } else if constexpr (CPL == 4) {
+            *reinterpret_cast<uint4*>(xd + first) = make_uint4(x[0], x[1], x[2], x[3]);
+            *reinterpret_cast<uint32_t*>(vd + first) =
+                v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+        } else {
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                xd[first + q] = (int32_t)x[q];
+                vd[first + q] = (uint8_t)v[q];
+            }
         }
-        *reinterpret_cast<uint2*>(vd + first) = make_uint2(lo, hi);
     } else {
 #pragma unroll
         for (int q = 0; q < (int)CPL; ++q) {
@@ -259,12 +287,26 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
     }
 }
 
-hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t ntiles, uint32_t* partials, uint32_t k,
-                              const Clock* clk, uint32_t s_off, uint32_t launch_idx,
-                              hipStream_t s) {
+hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t cpl, uint32_t own, uint32_t ntiles,
+                              uint32_t* partials, uint32_t k, const Clock* clk, uint32_t s_off,
+                              uint32_t launch_idx, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
-    NASCH_LAUNCH(agent_kstep_kernel, dim3((ntiles + 3) / 4), dim3(256), 0, s, a, partials, k, clk,
-                 s_off, launch_idx);
+    const dim3 grid((ntiles + 3) / 4);
+#define NASCH_AGENT_CASE(C)                                                                   \
+    case C:                                                                                   \
+        NASCH_LAUNCH(agent_kstep_kernel<C>, grid, dim3(256), 0, s, a, own, ntiles, partials, k, \
+                     clk, s_off, launch_idx);                                                 \
+        break;
+    switch (cpl) {
+        NASCH_AGENT_CASE(4)
+        NASCH_AGENT_CASE(5)
+        NASCH_AGENT_CASE(6)
+        NASCH_AGENT_CASE(7)
+        NASCH_AGENT_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef NASCH_AGENT_CASE
     return hipGetLastError();
 }
 

@@ -86,14 +86,38 @@ inline uint32_t kstep_max_k(uint32_t vmax, uint32_t q) {
     return (seg - 32u) / 2u / 32u * 32u / vmax;
 }
 
-// Agent k-step geometry: 512 cars per wave, the last round_up(k, 8) are halo.
-inline bool agent_geometry(uint32_t N, uint32_t k, uint32_t* own, uint32_t* ntiles) {
-    const uint32_t per_wave = 64u * kAgentCarsPerLane;
+// Agent k-step geometry: 64 cpl cars per wave, the last round_up(k, 8) are halo
+// (so the cars a wave owns start on a multiple of 8).
+inline bool agent_geometry(uint32_t N, uint32_t k, uint32_t cpl, uint32_t* own,
+                           uint32_t* ntiles) {
+    if (cpl < kAgentMinCarsPerLane || cpl > kAgentMaxCarsPerLane) return false;
+    const uint32_t per_wave = 64u * cpl;
     const uint32_t halo = (k + 7u) / 8u * 8u;
     if (k == 0 || halo + 8u > per_wave) return false;
     *own = per_wave - halo;
     *ntiles = N == 0 ? 0u : (N + *own - 1u) / *own;
     return true;
+}
+
+// Cars per lane of the agent k-step kernel for keyed draws.  Each step the wave
+// tabulates the rule-3 blocks (32 cells) its 64 cpl cars start in, 64 blocks per
+// pass of one Philox call per lane; at density rho the cars span about
+// 2 cpl / rho blocks (with a margin for uneven gaps and the first block's
+// offset).  The choice minimises passes per car; ties keep more cars per lane.
+inline uint32_t agent_cars_per_lane(uint64_t N, uint64_t L) {
+    if (N == 0 || L == 0) return kAgentMaxCarsPerLane;
+    const double rho = (double)N / (double)L;
+    uint32_t best = kAgentMaxCarsPerLane;
+    double best_cost = 0.0;
+    for (uint32_t c = kAgentMaxCarsPerLane; c >= kAgentMinCarsPerLane; --c) {
+        const double passes = std::ceil((2.1 * c / rho + 2.0) / 64.0);
+        const double cost = passes / c;
+        if (c == kAgentMaxCarsPerLane || cost < best_cost * (1.0 - 1e-9)) {
+            best = c;
+            best_cost = cost;
+        }
+    }
+    return best;
 }
 
 template <typename T>

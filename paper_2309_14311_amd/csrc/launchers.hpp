@@ -77,12 +77,14 @@ hipError_t launch_grid_kstep_bytes(uint32_t vmax, bool open, uint32_t q, const R
 constexpr uint32_t kOneStepQ = 1;
 
 // ---- agent (agent.hip) --------------------------------------------------------
-// k steps per launch: each wave holds 64 * kAgentCarsPerLane consecutive cars and
-// writes back all but the last k of them (fewer steps than the tiling's k are
-// correct too; one step per launch is the one-step kernel).
-constexpr uint32_t kAgentCarsPerLane = 8;
-hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t ntiles, uint32_t* partials, uint32_t k,
-                              const Clock* clk, uint32_t s_off, uint32_t launch_idx,
-                              hipStream_t s);
+// k steps per launch: each wave holds 64 * cpl consecutive cars (cpl cars per
+// lane, kAgentMinCarsPerLane to kAgentMaxCarsPerLane) and writes back the first
+// own of them, own <= 64 cpl - k (fewer steps than the tiling's k are correct
+// too; one step per launch is the one-step kernel).
+constexpr uint32_t kAgentMinCarsPerLane = 4;
+constexpr uint32_t kAgentMaxCarsPerLane = 8;
+hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t cpl, uint32_t own, uint32_t ntiles,
+                              uint32_t* partials, uint32_t k, const Clock* clk, uint32_t s_off,
+                              uint32_t launch_idx, hipStream_t s);
 
 }  // namespace nasch

@@ -302,8 +302,6 @@ struct AgentDesc {
     uint64_t warmup;
     uint32_t t, parity;
     uint32_t N, L, vmax;
-    uint32_t own;            // cars written back per tile by the k-step kernel
-    uint32_t ntiles;
     uint32_t rng;            // 0: keyed Philox draw; 1: shared minstd stream
     SlowParams sp;
     // shared stream (rng == 1)

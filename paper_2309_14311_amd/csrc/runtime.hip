@@ -58,6 +58,11 @@ struct nasch_sim {
     uint8_t* av[2] = {nullptr, nullptr};
     AgentDesc h_agent{};
     AgentDesc* d_agent = nullptr;
+    // tiling of the agent k-step kernel: cars per lane, cars written back per
+    // wave, waves.  The one-step launches keep a tiling of their own, eight cars
+    // per lane, whose vector loads and stores keep that HBM-bound kernel at speed.
+    uint32_t agent_cpl = kAgentMaxCarsPerLane, agent_own = 0, agent_ntiles = 0;
+    uint32_t agent_own1 = 0, agent_ntiles1 = 0;
     uint8_t* agent_grid = nullptr;  // scratch grid for snapshots
     uint32_t* mlcg_pow = nullptr;   // jump table of the shared stream
     uint32_t rng = NASCH_RNG_KEYED;
@@ -175,20 +180,18 @@ int nasch_sim::set_tuning(uint32_t kern, uint32_t kk, uint32_t qq) {
             }
         }
     } else {
-        if (qq != 1 && qq != 2 && qq != 4) return NASCH_EINVAL;
-        if (kern == NASCH_KERNEL_KSTEP) {
+        // the agent form's q is the number of cars per lane of the k-step tiling
+        if (qq < kAgentMinCarsPerLane || qq > kAgentMaxCarsPerLane) return NASCH_EINVAL;
+        if (kern == NASCH_KERNEL_KSTEP || qq != agent_cpl) {
             uint32_t own, ntiles;
-            if (!agent_geometry((uint32_t)N, kk, &own, &ntiles)) return NASCH_EINVAL;
+            if (!agent_geometry((uint32_t)N, kk, qq, &own, &ntiles)) return NASCH_EINVAL;
             int rc = ensure_os_partials((size_t)ntiles * kk);
             if (rc) return rc;
-            if (h_agent.own != own || h_agent.ntiles != ntiles) {
-                h_agent.own = own;
-                h_agent.ntiles = ntiles;
+            if (agent_own != own || agent_ntiles != ntiles || agent_cpl != qq) {
+                agent_own = own;
+                agent_ntiles = ntiles;
+                agent_cpl = qq;
                 graphs.clear();
-                if (!ok(hipMemcpyAsync(d_agent, &h_agent, sizeof(AgentDesc), hipMemcpyHostToDevice,
-                                       stream)) ||
-                    !ok(hipStreamSynchronize(stream)))
-                    return fail();
             }
         }
     }
@@ -217,13 +220,13 @@ int nasch_sim::enqueue_steps(uint64_t T) {
         } else {
             if (kernel == NASCH_KERNEL_ONESTEP) {
                 // one step per launch: the k-step kernel with one step, on the
-                // current tiling (its halo is sized for k, which one step leaves
-                // correct)
+                // one-step tiling
                 for (uint64_t i = 0; i < T; ++i) {
-                    hipError_t e = launch_agent_kstep(d_agent, h_agent.ntiles, os_partials, 1u,
-                                                      d_clk, (uint32_t)i, (uint32_t)i, stream);
+                    hipError_t e = launch_agent_kstep(d_agent, kAgentMaxCarsPerLane, agent_own1,
+                                                      agent_ntiles1, os_partials, 1u, d_clk,
+                                                      (uint32_t)i, (uint32_t)i, stream);
                     if (e == hipSuccess)
-                        e = launch_fold_agent_flux(d_agent, os_partials, h_agent.ntiles, 1u, d_clk,
+                        e = launch_fold_agent_flux(d_agent, os_partials, agent_ntiles1, 1u, d_clk,
                                                    (uint32_t)i, stream);
                     if (e != hipSuccess) return e;
                 }
@@ -232,10 +235,11 @@ int nasch_sim::enqueue_steps(uint64_t T) {
                 nl = (uint32_t)((T + k - 1) / k);
                 for (uint32_t i = 0; i < nl; ++i) {
                     const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
-                    hipError_t e = launch_agent_kstep(d_agent, h_agent.ntiles, os_partials, ki,
-                                                      d_clk, i * k, i, stream);
+                    hipError_t e = launch_agent_kstep(d_agent, agent_cpl, agent_own,
+                                                      agent_ntiles, os_partials, ki, d_clk,
+                                                      i * k, i, stream);
                     if (e == hipSuccess)
-                        e = launch_fold_agent_flux(d_agent, os_partials, h_agent.ntiles, ki, d_clk,
+                        e = launch_fold_agent_flux(d_agent, os_partials, agent_ntiles, ki, d_clk,
                                                    i * k, stream);
                     if (e != hipSuccess) return e;
                 }
@@ -459,11 +463,20 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
             a.mlcg_pow = h->mlcg_pow;
         }
         uint32_t kk = o.k ? o.k : kDefaultAgentK;
-        if (!agent_geometry((uint32_t)N, kk, &a.own, &a.ntiles)) return NASCH_EINVAL;
-        rc = h->ensure_os_partials((size_t)a.ntiles * kk);
+        // cars per lane: the shared stream draws no blocks, so it takes the most
+        const uint32_t cpl =
+            o.q ? o.q
+                : (o.rng == NASCH_RNG_STREAM ? kAgentMaxCarsPerLane : agent_cars_per_lane(N, L));
+        if (!agent_geometry((uint32_t)N, kk, cpl, &h->agent_own, &h->agent_ntiles) ||
+            !agent_geometry((uint32_t)N, 1u, kAgentMaxCarsPerLane, &h->agent_own1,
+                            &h->agent_ntiles1))
+            return NASCH_EINVAL;
+        h->agent_cpl = cpl;
+        rc = h->ensure_os_partials(
+            std::max((size_t)h->agent_ntiles * kk, (size_t)h->agent_ntiles1));
         if (rc) return rc;
         h->k = kk;
-        h->q = o.q ? o.q : 1;
+        h->q = cpl;
         h->kernel = o.kernel == NASCH_KERNEL_AUTO ? NASCH_KERNEL_KSTEP : o.kernel;
         rc = agent_from_grid(h.get(), g0);
         if (rc) return rc;

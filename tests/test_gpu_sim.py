@@ -133,6 +133,33 @@ def test_densities_grid_and_agent(rho):
         _run_and_compare(L, N, 5, 0.13, 9, 60, rep=rep, kernel=kernel, init_v=1, replica=2)
 
 
+@pytest.mark.parametrize("cpl", [4, 5, 6, 7, 8])
+def test_agent_cars_per_lane(cpl):
+    """Every width of the agent form's k-step tiling (cars per lane, its q), on
+    a ring whose last tile is ragged, with ties in the draws; the one-step
+    kernel with that setting; and a switch of width mid-run."""
+    L, N, vmax, p, seed = 40009, 10007, 5, 0.13, 31
+    _run_and_compare(L, N, vmax, p, seed, 70, rep="agent", kernel="kstep", k=16, q=cpl, init_v=1)
+    _run_and_compare(L, N, vmax, p, seed, 9, rep="agent", kernel="onestep", k=16, q=cpl,
+                     init_v=1)
+    g0 = oracle.init_grid(L, N, vmax, seed, init_v=1)
+    want, want_flux = oracle.run_grid(g0, vmax, p, seed, 50)
+    s = Sim(L, N, vmax, p, seed, rep="agent", init_v=1, k=8, q=cpl)
+    try:
+        assert s.info()["q"] == cpl
+        s.step(20)
+        s.set_tuning("kstep", k=24, q=12 - cpl)
+        assert s.info()["q"] == 12 - cpl
+        s.step(30)
+        np.testing.assert_array_equal(s.snapshot()[0], want)
+        np.testing.assert_array_equal(s.flux(0, 50), want_flux)
+        for bad in (3, 9):
+            with pytest.raises(NaschError):
+                s.set_tuning("kstep", q=bad)
+    finally:
+        s.close()
+
+
 @pytest.mark.parametrize("k", [1, 5, 8, 31, 64, 100])
 def test_agent_kstep_depths(k):
     _run_and_compare(100003, 25000, 5, 0.25, 1, 203, rep="agent", kernel="kstep", k=k, init_v=1)
@@ -254,9 +281,9 @@ def test_switching_kernels_mid_run(boundary):
 
 @pytest.mark.parametrize("rng", ["keyed", "stream"])
 def test_agent_onestep_on_every_tiling(rng):
-    """The agent form's one-step launches run on the tiling its k-step setting
-    left (halo sized for that k).  Switched in turn after tilings for k = 1 to
-    100, and back to the k-step kernel, every phase continues the oracle's
+    """The agent form's one-step launches run on a tiling of their own (eight
+    cars per lane), the k-step launches on one sized for their k.  Switched in
+    turn with k-step phases at k = 1 to 100, every phase continues the oracle's
     trajectory exactly."""
     L, N, vmax, p, seed = 20011, 5003, 5, 0.13, 12
     g0 = oracle.init_grid(L, N, vmax, seed, init_v=1)
