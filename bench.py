@@ -102,6 +102,27 @@ def _time_oracle(reps, nthreads, budget_s, steps):
     return done_cells, spent, n, nthreads
 
 
+def _host_info():
+    """CPU model, sockets, physical cores and logical CPUs of the host."""
+    model, cores = None, set()
+    try:
+        with open("/proc/cpuinfo") as f:
+            pid = None
+            for line in f:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "model name" and model is None:
+                    model = val
+                elif key == "physical id":
+                    pid = val
+                elif key == "core id":
+                    cores.add((pid, val))
+    except OSError:
+        pass
+    return {"cpu": model, "sockets": len({p for p, _ in cores}) or None,
+            "physical_cores": len(cores) or None, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline_ensemble(reps, budget_s=15.0, steps=100):
     """The oracle on a bounded sample of the ensemble: the all-core OpenMP twin
     for `budget_s` seconds (the reported value), then the serial oracle for
@@ -115,7 +136,52 @@ def cpu_baseline_ensemble(reps, budget_s=15.0, steps=100):
     return {"value": cells / spent, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle", "sample": sample(cells, spent, n),
             "serial": {"value": s_cells / s_spent, "unit": "cell-updates/s", "cores": 1,
-                       "sample": sample(s_cells, s_spent, s_n)}}
+                       "sample": sample(s_cells, s_spent, s_n)},
+            "host": _host_info()}
+
+
+def cpu_baseline_single(cfg, budget_s=15.0, rng="keyed", max_cells=1 << 22):
+    """The oracle on a bounded sample of a one-road workload: a road of at most
+    max_cells cells with the workload's density, vmax, p and seed, stepped a
+    chunk of steps at a time for `budget_s` seconds on all cores (the reported
+    value), then for half as long serially.  The keyed grid oracle stands for
+    both representations (they give identical results); an open road and the
+    shared stream have only serial oracles."""
+    import oracle
+    L = min(cfg["L"], max_cells)
+    N = int(round(cfg["N"] * L / cfg["L"]))
+    g0 = oracle.init_grid(L, N, cfg["vmax"], cfg["seed"], init_v=cfg["init_v"])
+    chunk = max(10, (1 << 20) // L)
+    is_open = "alpha" in cfg
+    stream = rng == "stream"
+
+    def timed(nthreads, budget):
+        g, t, spent = g0, 0, 0.0
+        x, v = oracle.grid_to_agent(g0) if stream else (None, None)
+        while spent < budget:
+            t0 = time.perf_counter()
+            if is_open:
+                g = oracle.run_open(g, cfg["vmax"], cfg["p"], cfg["alpha"], cfg["beta"],
+                                    cfg["seed"], chunk, t0=t)[0]
+            elif stream:
+                # each chunk starts a stream of its own (seed + t): fast-forwarding
+                # one past t N draws is serial work that would dwarf the chunk
+                x, v, _ = oracle.run_agent_mlcg(L, x, v, cfg["vmax"], cfg["p"],
+                                                cfg["seed"] + t, chunk)
+            else:
+                g = oracle.run_grid(g, cfg["vmax"], cfg["p"], cfg["seed"], chunk, t0=t,
+                                    nthreads=nthreads)[0]
+            spent += time.perf_counter() - t0
+            t += chunk
+        return L * t / spent, f"L = {L}, N = {N}, {t} steps from t = 0 in {spent:.1f} s"
+
+    threads = 1 if (is_open or stream) else min(16, os.cpu_count() or 1)
+    value, smp = timed(threads, budget_s)
+    s_value, s_smp = timed(1, budget_s / 2)
+    return {"value": value, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": smp, "serial": {"value": s_value, "unit": "cell-updates/s", "cores": 1,
+                                      "sample": s_smp},
+            "host": _host_info()}
 
 
 def bench_ensemble(args):
@@ -351,7 +417,7 @@ def bench_single(args, cfg, rep, kernels):
         res["kstep_k1_hbm_frac"] = res["kstep_k1"] * BYTES_PER_CELL_UPDATE / HBM_PEAK
         torch.cuda.synchronize()
         s.close()
-    return {
+    line = {
         "metric": "cell-updates/s and % HBM roofline, batched vs plain on 1 GPU, bit-exact",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": cfg["L"] * T / value * 1e3,
@@ -367,6 +433,9 @@ def bench_single(args, cfg, rep, kernels):
         "bytes_per_cell_update": bpcu,
         "extra": {(k if k.endswith(("frac", "GBps")) else f"{k}_cups"): v for k, v in res.items()},
     }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_single(cfg, budget_s=args.cpu_budget, rng=rng)
+    return line
 
 
 def main():

@@ -43,3 +43,14 @@ def test_cpu_baseline_reports_all_core_and_serial_oracle():
     assert cb["value"] > 0 and 1 <= cb["cores"] <= 16
     assert cb["serial"]["cores"] == 1 and cb["serial"]["value"] > 0
     assert "replicas" in cb["sample"] and "replicas" in cb["serial"]["sample"]
+
+
+@pytest.mark.parametrize("name,rng", [("LARGE_RING", "keyed"), ("OPEN_ROAD", "keyed"),
+                                      ("AGENT_RING", "stream"), ("REFERENCE", "keyed")])
+def test_cpu_baseline_of_one_road_workloads(name, rng):
+    from paper_2309_14311_amd import workloads
+    cb = bench.cpu_baseline_single(getattr(workloads, name), budget_s=0.05, rng=rng,
+                                   max_cells=1 << 14)
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["serial"]["value"] > 0
+    assert cb["cores"] >= 1 and cb["serial"]["cores"] == 1
+    assert cb["host"]["logical_cpus"] >= 1
