@@ -4,10 +4,10 @@
 // d = (x[i+1] - x[i]) mod L (d = L for a car alone); rules 1-4 follow.
 //
 // agent_kstep_kernel<C>: one wave per 64 C consecutive cars (C per lane, chosen
-// on the host from the density), kept in registers for k steps.  Car i after s steps depends only on cars
-// i .. i+s, so the last k cars of a wave are a halo: each wave writes back the
-// first `own` cars and the waves overlap by the halo.  Launched with one step
-// it is the one-step kernel.
+// on the host from the density), kept in registers for k steps.  Car i after
+// s steps depends only on cars i .. i+s, so the last k cars of a wave are a
+// halo: each wave writes back the first `own` cars and the waves overlap by
+// the halo.  Launched with one step it is the one-step kernel.
 // Rule 3 uses the same keyed draw as the grid kernels (R depends on the cell a
 // car starts the step in), so both representations give identical results.
 #include "launchers.hpp"
@@ -40,9 +40,9 @@ struct AgentLds {
 // together (one Philox call per lane and 64 blocks), compare each block's 32
 // top nibbles with thr's at once, and keep two masks per block in LDS: cars
 // below thr's nibble and cars tying with it.  A car reads its two bits from
-// its block's entry; a car further along (a sparse road) draws its own block.  The cars whose nibble ties with
-// thr's are then numbered across the wave and have their low 28 bits drawn
-// 64 at a time.  `nv` holds each car's velocity after rules 1-2 and receives
+// its block's entry; a car further along (a sparse road) draws its own block.
+// The cars whose nibble ties with thr's are then numbered across the wave and
+// have their low 28 bits drawn 64 at a time.  `nv` holds each car's velocity after rules 1-2 and receives
 // the result of rule 3.  All 64 lanes must be active; cars with nv == 0 draw
 // nothing.
 template <int C>
