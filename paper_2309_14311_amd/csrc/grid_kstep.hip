@@ -377,6 +377,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     const uint32_t H = R.halo;
     const uint32_t seg_len = own_len + 2u * H;
     const uint32_t s0 = (own_start + L - (H % L)) % L;  // ring cell of segment cell 0
+    const bool short_ring = L < kstep_segment(Q);        // the segment wraps the ring
     const int64_t base = (int64_t)own_start - (int64_t)H;  // open road: cell of segment cell 0
     // open road: does the segment hold cell 0 / cells at or past L (wave-uniform)
     const bool edge_l = OPEN && base <= 0;
@@ -406,12 +407,14 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
             obst[q] = (p0 <= (int64_t)L && (int64_t)L < p0 + 32) ? 1u << (uint32_t)(L - p0) : 0u;
             inj[q] = p0 == 0 ? 1u : 0u;
         } else {
-            // s0 < L < 2^31 and j0 < 8192: one subtraction unless the ring is
-            // shorter than the segment
+            // s0 < L < 2^31 and j0 < the segment length: at most one
+            // subtraction unless the ring is shorter than the segment (a
+            // wave-uniform branch)
             x0 = s0 + j0;
-            if (x0 >= L) {
-                x0 -= L;
-                if (x0 >= L) x0 %= L;
+            if (short_ring) {
+                x0 %= L;
+            } else {
+                x0 = min(x0, x0 - L);   // x0 - L wraps above x0 unless x0 >= L
             }
             aligned[q] = ((x0 & 31u) == 0u) && (x0 + 32u <= L);
             keep[q] = obst[q] = inj[q] = 0u;
@@ -474,20 +477,22 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     wave_sync_lds();
     uint32_t draw_mode = kDrawAligned;   // open roads: every word is aligned
     if constexpr (!OPEN) {
-        bool all_aligned = true, all_two = true;
+        bool all_aligned = true;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            all_aligned = all_aligned && aligned[q];
-            all_two = all_two && two_blocks(xw[q], L, nw);
-        }
-        if (__builtin_amdgcn_ballot_w64(!all_aligned) != 0u)
+        for (int q = 0; q < Q; ++q) all_aligned = all_aligned && aligned[q];
+        if (__builtin_amdgcn_ballot_w64(!all_aligned) != 0u) {
+            // only waves at the end of a ring (or on a short one) get here
+            bool all_two = true;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) all_two = all_two && two_blocks(xw[q], L, nw);
             draw_mode = (L >= 64u && __builtin_amdgcn_ballot_w64(!all_two) == 0u) ? kDrawTwo
                                                                                  : kDrawGeneric;
+        }
     }
 
     // segment cell -> ring cell for the tied cars' draws
     const uint32_t seg0 = OPEN ? (uint32_t)base : s0;
-    const uint32_t x_mode = OPEN ? kXNone : (L >= kstep_segment(Q) ? kXSub : kXMod);
+    const uint32_t x_mode = OPEN ? kXNone : (short_ring ? kXMod : kXSub);
 
     // ---- k steps
     uint32_t acc = 0u;
