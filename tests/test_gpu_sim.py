@@ -160,6 +160,21 @@ def test_agent_cars_per_lane(cpl):
         s.close()
 
 
+@pytest.mark.parametrize("rho,rng,want", [(0.05, "keyed", 6), (0.2, "keyed", 5),
+                                          (0.25, "keyed", 7), (0.3, "keyed", 8),
+                                          (0.5, "keyed", 8), (0.25, "stream", 8)])
+def test_agent_default_cars_per_lane(rho, rng, want):
+    """The default width of the agent form's tiling: the fewest rule-3 table
+    passes per car, a wave's 64 q cars spanning about 2.1 q / rho + 2 of the
+    64 blocks a pass draws; the shared stream draws no blocks and takes 8."""
+    L = 1 << 16
+    s = Sim(L, int(rho * L), 5, 0.25, 3, rep="agent", rng=rng)
+    try:
+        assert s.info()["q"] == want
+    finally:
+        s.close()
+
+
 @pytest.mark.parametrize("k", [1, 5, 8, 31, 64, 100])
 def test_agent_kstep_depths(k):
     _run_and_compare(100003, 25000, 5, 0.25, 1, 203, rep="agent", kernel="kstep", k=k, init_v=1)
