@@ -365,7 +365,10 @@ def bench_single(args, cfg, rep, kernels):
         road = dict(boundary="open", alpha=cfg["alpha"], beta=cfg["beta"])
     s = Sim(cfg["L"], cfg["N"], cfg["vmax"], cfg["p"], cfg["seed"], rep=rep,
             init_v=cfg["init_v"], use_graph=True, rng=rng, **road)
-    s.autotune()
+    if args.k and args.q:
+        s.set_tuning("kstep", args.k, args.q)   # q: words per lane (grid) or cars per lane (agent)
+    else:
+        s.autotune()
     info = s.info()
     T = cfg["T"] if args.T_single is None else args.T_single
     res = {}
