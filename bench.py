@@ -455,8 +455,12 @@ def main():
     ap.add_argument("--T", type=int, default=5000)
     ap.add_argument("--warmup-steps", type=int, default=1000)
     ap.add_argument("--T-single", type=int, default=None)
-    ap.add_argument("--k", type=int, default=0, help="steps per launch (0: autotune)")
-    ap.add_argument("--q", type=int, default=0, help="words per lane (0: autotune)")
+    ap.add_argument("--k", type=int, default=0,
+                    help="steps per launch (0: autotune; one-road workloads use --k and --q "
+                         "only when both are given)")
+    ap.add_argument("--q", type=int, default=0,
+                    help="words per lane of the grid kernel, or cars per lane of the agent "
+                         "k-step kernel (0: autotune / by density)")
     ap.add_argument("--plain-stride", type=int, default=8)
     ap.add_argument("--plain-T", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
