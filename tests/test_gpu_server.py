@@ -73,6 +73,23 @@ def test_alone_equals_in_mix_and_queueing_under_small_budget():
         s.close()
 
 
+def test_rings_of_very_different_sizes_in_one_arena():
+    """Rings of 10^3 to 2 x 10^5 cells, submitted together, share the launches:
+    each equals the oracle in its flux log and final grid."""
+    reqs = workloads.requests(24, seed=11, L_exp=(3.0, 5.8), T_exp=(2.0, 3.0))
+    assert min(r["L"] for r in reqs) < 2000 and max(r["L"] for r in reqs) > 150000
+    srv = Server(k=32)
+    ids = [srv.submit(r["L"], r["N"], r["vmax"], r["p"], r["seed"], r["T"], init_v=r["init_v"],
+                      want_grid=True) for r in reqs]
+    res = _drain(srv, len(ids))
+    srv.close()
+    for rid, r in zip(ids, reqs):
+        g, flux = _oracle(r)
+        assert res[rid]["status"] == 0
+        np.testing.assert_array_equal(res[rid]["flux"], flux)
+        np.testing.assert_array_equal(res[rid]["grid"], g)
+
+
 def test_cancel_and_invalid_requests():
     srv = Server(k=32)
     with pytest.raises(NaschError):
