@@ -5,11 +5,12 @@
 //   1. admits queued requests in arrival order while their footprint fits the
 //      HBM budget and a slot is free (state allocated from a device arena,
 //      initialised by the init kernel);
-//   2. runs a burst of launches of the temporal-blocked grid kernel over every
-//      live slot, each slot advancing from its own step counter (the burst
-//      stops where the first slot finishes, and is a single launch while
-//      requests wait for admission); the tile items are rebuilt only when
-//      the set of live slots changes;
+//   2. runs a burst of launches of the temporal-blocked grid kernel over the
+//      live large rings, each slot advancing from its own step counter (the
+//      burst stops where the first slot finishes, and is a single launch while
+//      requests wait for admission), while the small rings run bursts of their
+//      own on a second stream, started and collected as they finish; the tile
+//      items are rebuilt only when a set of live slots changes;
 //   3. hands finished slots back: flux log and final grid are copied to the
 //      caller's buffers, the result is queued for nasch_server_poll, and the
 //      slot's memory is returned to the arena.
@@ -96,6 +97,24 @@ struct Job {
 // Launches run back to back before the host looks at the slots again.
 constexpr uint32_t kMaxBurst = 8;
 
+// Every live slot of a chain of launches advances the same number of steps
+// per launch, so a ring's steps cost as much wall time as the whole chain's.
+// Rings of at most kSmallCells cells therefore run in a chain of their own on a
+// second stream, kSmallBurst launches at a time on its own clock: the host
+// starts it, goes on with the large rings' bursts, and collects it when it has
+// finished.  Its launches are short, so a small ring's latency follows its own
+// work instead of the arena's.
+constexpr uint64_t kSmallCells = 65536;
+constexpr uint32_t kSmallBurst = 4;
+// The small chain takes as few 32-cell words per lane as the steps per launch
+// allow (see small_q): a ring shorter than a wave's segment repeats around it,
+// so the shortest segment wastes the least on them.
+uint32_t small_q(uint32_t k, uint32_t q) {
+    for (uint32_t qq = 1; qq < q; qq *= 2)
+        if (kstep_max_k(NASCH_MAX_VMAX, qq) >= k) return qq;
+    return q;
+}
+
 // Layout of one slot: the byte grid (initial placement, final snapshot), two
 // bit-plane buffers (the state the kernel steps), the flux log; each rounded
 // up to 256 bytes.
@@ -112,19 +131,25 @@ uint64_t log_offset(const nasch_request& r) { return grid_bytes(r) + 2 * plane_b
 
 struct nasch_server {
     nasch_server_opts opts{};
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;     // admission, the large rings, results
     bool own_stream = false;
+    hipStream_t stream_s = nullptr;   // the small rings' chain
+    hipEvent_t ev_admit = nullptr;    // orders the small chain after admission
+    hipEvent_t ev_small = nullptr;    // the small chain's burst has finished
     HipStatus st;
     uint8_t* arena_base = nullptr;
     Arena arena;
     Clock* d_clk = nullptr;   // stays {0, 0}: each slot carries its own t and parity
-    GridEngine eng;
+    GridEngine eng;           // the large rings
+    GridEngine eng_s;         // the small rings
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::unique_ptr<Job>> pending;
-    std::vector<std::unique_ptr<Job>> running;
+    std::vector<std::unique_ptr<Job>> running;     // large rings
+    std::vector<std::unique_ptr<Job>> running_s;   // small rings in the chain (fixed while it runs)
+    std::vector<std::unique_ptr<Job>> ready_s;     // admitted small rings waiting for the chain
     std::deque<nasch_result> done;
     std::vector<uint64_t> cancel_ids;
     uint64_t next_id = 1;
@@ -138,6 +163,9 @@ struct nasch_server {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     void loop();
+    void describe(GridEngine& e, const std::vector<std::unique_ptr<Job>>& set, bool full);
+    bool complete(std::vector<std::unique_ptr<Job>>& set, uint32_t m, std::vector<uint64_t>& flux_host);
+    void fail_all();
     enum class Admit { ok, no_room, device_error };
     Admit admit_one(Job& j);
     void finish(std::unique_ptr<Job> j, int status, uint64_t flux_sum);
@@ -180,10 +208,105 @@ void nasch_server::finish(std::unique_ptr<Job> j, int status, uint64_t flux_sum)
     cv_done.notify_all();
 }
 
+// Ring descriptors of a set of slots, each at its own step and parity; `full`
+// rebuilds them (the set changed), else only the steps and parities move.
+void nasch_server::describe(GridEngine& e, const std::vector<std::unique_ptr<Job>>& set,
+                            bool full) {
+    if (full) e.rings.resize(set.size());
+    for (size_t i = 0; i < set.size(); ++i) {
+        const Job& j = *set[i];
+        const nasch_request& r = j.req;
+        uint8_t* base = arena_base + j.off;
+        RingDesc& d = e.rings[i];
+        if (full) {
+            d = RingDesc{};
+            d.buf[0] = base;
+            d.buf[1] = nullptr;
+            d.pl[0] = reinterpret_cast<uint32_t*>(base + grid_bytes(r));
+            d.pl[1] = reinterpret_cast<uint32_t*>(base + grid_bytes(r) + plane_bytes(r));
+            d.nw = plane_words(r.L);
+            d.flux_log = reinterpret_cast<unsigned long long*>(base + log_offset(r));
+            d.flux_acc = nullptr;
+            d.log_t0 = 0;
+            d.warmup = ~0ull;
+            d.L = (uint32_t)r.L;
+            d.vmax = r.vmax;
+            d.t_end = (uint32_t)r.T;
+            d.sp = slow_params(r.seed, r.replica, r.p);
+        }
+        d.t = j.t;
+        d.parity = j.parity;
+    }
+}
+
+// Advance every slot of a set by the m launches it ran, hand back the finished
+// and cancelled ones (results copied on the main stream) and keep the rest.
+// Returns whether the set changed.
+bool nasch_server::complete(std::vector<std::unique_ptr<Job>>& set, uint32_t m,
+                            std::vector<uint64_t>& flux_host) {
+    const uint32_t k = opts.k;
+    bool changed = false;
+    std::vector<std::unique_ptr<Job>> still;
+    for (auto& jp : set) {
+        Job& j = *jp;
+        const uint64_t ran = std::min<uint64_t>((uint64_t)m * k, j.req.T - j.t);
+        j.t += (uint32_t)ran;
+        j.parity ^= m & 1u;
+        if (j.cancelled) {
+            finish(std::move(jp), NASCH_ESTATE, 0);
+            changed = true;
+            continue;
+        }
+        if (j.t < j.req.T) {
+            still.push_back(std::move(jp));
+            continue;
+        }
+        changed = true;
+        const nasch_request& r = j.req;
+        uint8_t* base = arena_base + j.off;
+        flux_host.resize(r.T);
+        int status = NASCH_OK;
+        if (!st.ok(hipMemcpyAsync(flux_host.data(), base + log_offset(r), r.T * 8,
+                                  hipMemcpyDeviceToHost, stream)))
+            status = NASCH_EDEVICE;
+        if (!status && r.grid_out) {
+            // the final planes into the slot's byte grid, then to the host
+            const ConvJob job{base,
+                              reinterpret_cast<uint32_t*>(base + grid_bytes(r) +
+                                                          (j.parity ? plane_bytes(r) : 0)),
+                              (uint32_t)r.L, plane_words(r.L), r.vmax, 0u};
+            if (!st.ok(launch_planes_to_bytes_one(job, stream)) ||
+                !st.ok(hipMemcpyAsync(r.grid_out, base, r.L, hipMemcpyDeviceToHost, stream)))
+                status = NASCH_EDEVICE;
+        }
+        if (!status && !st.ok(hipStreamSynchronize(stream))) status = NASCH_EDEVICE;
+        uint64_t sum = 0;
+        for (uint64_t f : flux_host) sum += f;
+        if (!status && r.flux_out) std::memcpy(r.flux_out, flux_host.data(), r.T * 8);
+        finish(std::move(jp), status, sum);
+    }
+    set.swap(still);
+    return changed;
+}
+
+// A device failure ends every live request with an error.
+void nasch_server::fail_all() {
+    (void)hipStreamSynchronize(stream);
+    (void)hipStreamSynchronize(stream_s);
+    for (auto* set : {&running, &running_s, &ready_s}) {
+        for (auto& j : *set) finish(std::move(j), NASCH_EDEVICE, 0);
+        set->clear();
+    }
+    n_running = 0;
+}
+
 void nasch_server::loop() {
-    const uint32_t k = opts.k, q = opts.q;
+    const uint32_t k = opts.k, q = opts.q, q_s = small_q(k, q);
     std::vector<uint64_t> flux_host;
-    bool dirty = true;   // the set of live slots changed: rebuild the tile items
+    bool dirty = true;     // the set of large slots changed: rebuild their tile items
+    bool dirty_s = true;   // the same for the small slots
+    bool busy_s = false;   // the small chain has a burst in flight
+    uint32_t m_s = 0;      // its launches
     for (;;) {
         // ---- admission and cancellation
         std::vector<std::unique_ptr<Job>> admitted;
@@ -192,7 +315,10 @@ void nasch_server::loop() {
         bool waiting;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv_work.wait(lk, [&] { return stop || !pending.empty() || !running.empty() || !cancel_ids.empty(); });
+            cv_work.wait(lk, [&] {
+                return stop || !pending.empty() || !running.empty() || !running_s.empty() ||
+                       !ready_s.empty() || !cancel_ids.empty();
+            });
             if (stop) return;
             cancels.swap(cancel_ids);
             for (uint64_t id : cancels) {
@@ -204,7 +330,8 @@ void nasch_server::loop() {
                     }
                 }
             }
-            while (!pending.empty() && running.size() + admitted.size() < opts.max_slots) {
+            const size_t live = running.size() + running_s.size() + ready_s.size();
+            while (!pending.empty() && live + admitted.size() < opts.max_slots) {
                 Job& j = *pending.front();
                 const Admit a = admit_one(j);
                 if (a == Admit::no_room) break;   // head of line waits for memory
@@ -215,100 +342,97 @@ void nasch_server::loop() {
         }
         for (auto& j : cancelled_pending) finish(std::move(j), NASCH_ESTATE, 0);
         for (auto& j : failed) finish(std::move(j), NASCH_EDEVICE, 0);
-        if (!admitted.empty()) dirty = true;
-        for (auto& j : admitted) running.push_back(std::move(j));
-        n_running = running.size();
-        for (uint64_t id : cancels)
-            for (auto& j : running)
-                if (j && j->id == id) j->cancelled = true;
-        if (running.empty()) continue;
-
-        // ---- descriptors of the live slots (each at its own step and parity)
-        eng.rings.resize(running.size());
-        for (size_t i = 0; i < running.size(); ++i) {
-            const Job& j = *running[i];
-            const nasch_request& r = j.req;
-            uint8_t* base = arena_base + j.off;
-            RingDesc& d = eng.rings[i];
-            if (dirty) {
-                d = RingDesc{};
-                d.buf[0] = base;
-                d.buf[1] = nullptr;
-                d.pl[0] = reinterpret_cast<uint32_t*>(base + grid_bytes(r));
-                d.pl[1] = reinterpret_cast<uint32_t*>(base + grid_bytes(r) + plane_bytes(r));
-                d.nw = plane_words(r.L);
-                d.flux_log = reinterpret_cast<unsigned long long*>(base + log_offset(r));
-                d.flux_acc = nullptr;
-                d.log_t0 = 0;
-                d.warmup = ~0ull;
-                d.L = (uint32_t)r.L;
-                d.vmax = r.vmax;
-                d.t_end = (uint32_t)r.T;
-                d.sp = slow_params(r.seed, r.replica, r.p);
+        for (auto& j : admitted) {
+            if (j->req.L <= kSmallCells) {
+                ready_s.push_back(std::move(j));
+            } else {
+                running.push_back(std::move(j));
+                dirty = true;
             }
-            d.t = j.t;
-            d.parity = j.parity;
         }
-        // ---- a burst of launches: none of them runs past the first slot to
-        // finish, and only one while requests wait for admission
-        uint32_t m = kMaxBurst;
-        for (const auto& jp : running)
-            m = std::min<uint64_t>(m, (jp->req.T - jp->t + k - 1) / k);
-        if (waiting) m = 1;
-        const hipError_t e_geo = dirty ? eng.set_geometry(k, q, stream) : eng.upload_rings(stream);
-        dirty = false;
-        if (!st.ok(e_geo) || !st.ok(eng.enqueue((uint64_t)m * k, d_clk, stream)) ||
-            !st.ok(hipStreamSynchronize(stream))) {
-            // a device failure ends every running request with an error
-            for (auto& j : running) finish(std::move(j), NASCH_EDEVICE, 0);
-            running.clear();
-            n_running = 0;
-            dirty = true;
+        for (uint64_t id : cancels)
+            for (auto* set : {&running, &running_s, &ready_s})
+                for (auto& j : *set)
+                    if (j && j->id == id) j->cancelled = true;
+        // admitted small slots join the chain while it is idle
+        if (!busy_s && !ready_s.empty()) {
+            for (auto& j : ready_s) running_s.push_back(std::move(j));
+            ready_s.clear();
+            dirty_s = true;
+        }
+        n_running = running.size() + running_s.size() + ready_s.size();
+
+        // ---- the small chain: when idle, a burst of kSmallBurst launches (or
+        // up to the last of its slots to finish: one that finishes earlier idles,
+        // the kernel stopping its steps at t_end), after the admission work on
+        // the main stream; no launch starts a slot's steps past 2^32 - 1
+        if (!busy_s && !running_s.empty()) {
+            uint64_t most = 0, room = ~0ull;
+            for (const auto& j : running_s) {
+                most = std::max<uint64_t>(most, (j->req.T - j->t + k - 1) / k);
+                room = std::min<uint64_t>(room, (0xFFFFFFFFull - j->t) / k);
+            }
+            m_s = (uint32_t)std::min<uint64_t>({(uint64_t)kSmallBurst, most,
+                                                 std::max<uint64_t>(room, 1)});
+            describe(eng_s, running_s, dirty_s);
+            const hipError_t e_geo =
+                dirty_s ? eng_s.set_geometry(k, q_s, stream_s) : eng_s.upload_rings(stream_s);
+            dirty_s = false;
+            if (!st.ok(hipEventRecord(ev_admit, stream)) ||
+                !st.ok(hipStreamWaitEvent(stream_s, ev_admit, 0)) || !st.ok(e_geo) ||
+                !st.ok(eng_s.enqueue((uint64_t)m_s * k, d_clk, stream_s)) ||
+                !st.ok(hipEventRecord(ev_small, stream_s))) {
+                fail_all();
+                busy_s = false;
+                dirty = dirty_s = true;
+                continue;
+            }
+            busy_s = true;
+            launches += m_s;
+        }
+
+        // ---- the large rings: a burst of launches, none of them past the first
+        // slot to finish, and only one while requests wait for admission; with
+        // no large rings the host waits for the small chain instead
+        if (!running.empty()) {
+            describe(eng, running, dirty);
+            uint32_t m = kMaxBurst;
+            for (const auto& jp : running)
+                m = std::min<uint64_t>(m, (jp->req.T - jp->t + k - 1) / k);
+            if (waiting) m = 1;
+            const hipError_t e_geo = dirty ? eng.set_geometry(k, q, stream) : eng.upload_rings(stream);
+            dirty = false;
+            if (!st.ok(e_geo) || !st.ok(eng.enqueue((uint64_t)m * k, d_clk, stream)) ||
+                !st.ok(hipStreamSynchronize(stream))) {
+                fail_all();
+                busy_s = false;
+                dirty = dirty_s = true;
+                continue;
+            }
+            launches += m;
+            if (complete(running, m, flux_host)) dirty = true;
+        } else if (busy_s && !st.ok(hipEventSynchronize(ev_small))) {
+            fail_all();
+            busy_s = false;
+            dirty = dirty_s = true;
             continue;
         }
-        launches += m;
-        // ---- bookkeeping and completions
-        std::vector<std::unique_ptr<Job>> still;
-        for (auto& jp : running) {
-            Job& j = *jp;
-            const uint64_t ran = std::min<uint64_t>((uint64_t)m * k, j.req.T - j.t);
-            j.t += (uint32_t)ran;
-            j.parity ^= m & 1u;
-            if (j.cancelled) {
-                finish(std::move(jp), NASCH_ESTATE, 0);
-                dirty = true;
+
+        // ---- the small chain's burst, once it has finished
+        if (busy_s) {
+            const hipError_t q_s = hipEventQuery(ev_small);
+            if (q_s == hipSuccess) {
+                busy_s = false;
+                if (complete(running_s, m_s, flux_host)) dirty_s = true;
+            } else if (q_s != hipErrorNotReady) {
+                (void)st.ok(q_s);
+                fail_all();
+                busy_s = false;
+                dirty = dirty_s = true;
                 continue;
             }
-            if (j.t < j.req.T) {
-                still.push_back(std::move(jp));
-                continue;
-            }
-            dirty = true;
-            const nasch_request& r = j.req;
-            uint8_t* base = arena_base + j.off;
-            flux_host.resize(r.T);
-            int status = NASCH_OK;
-            if (!st.ok(hipMemcpyAsync(flux_host.data(), base + log_offset(r), r.T * 8,
-                                      hipMemcpyDeviceToHost, stream)))
-                status = NASCH_EDEVICE;
-            if (!status && r.grid_out) {
-                // the final planes into the slot's byte grid, then to the host
-                const ConvJob job{base,
-                                  reinterpret_cast<uint32_t*>(base + grid_bytes(r) +
-                                                              (j.parity ? plane_bytes(r) : 0)),
-                                  (uint32_t)r.L, plane_words(r.L), r.vmax, 0u};
-                if (!st.ok(launch_planes_to_bytes_one(job, stream)) ||
-                    !st.ok(hipMemcpyAsync(r.grid_out, base, r.L, hipMemcpyDeviceToHost, stream)))
-                    status = NASCH_EDEVICE;
-            }
-            if (!status && !st.ok(hipStreamSynchronize(stream))) status = NASCH_EDEVICE;
-            uint64_t sum = 0;
-            for (uint64_t f : flux_host) sum += f;
-            if (!status && r.flux_out) std::memcpy(r.flux_out, flux_host.data(), r.T * 8);
-            finish(std::move(jp), status, sum);
         }
-        running.swap(still);
-        n_running = running.size();
+        n_running = running.size() + running_s.size() + ready_s.size();
     }
 }
 
@@ -344,6 +468,10 @@ int nasch_server_create(nasch_server** out, const nasch_server_opts* opts) {
         if (!s->st.ok(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking))) return NASCH_EDEVICE;
         s->own_stream = true;
     }
+    if (!s->st.ok(hipStreamCreateWithFlags(&s->stream_s, hipStreamNonBlocking)) ||
+        !s->st.ok(hipEventCreateWithFlags(&s->ev_admit, hipEventDisableTiming)) ||
+        !s->st.ok(hipEventCreateWithFlags(&s->ev_small, hipEventDisableTiming)))
+        return NASCH_EDEVICE;
     if (!s->st.ok(dev_alloc(&s->arena_base, o.hbm_budget))) return NASCH_ENOMEM;
     s->arena.reset(o.hbm_budget);
     if (!s->st.ok(dev_alloc(&s->d_clk, 1))) return NASCH_ENOMEM;
@@ -429,9 +557,14 @@ void nasch_server_destroy(nasch_server* s) {
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->stream_s) (void)hipStreamSynchronize(s->stream_s);
     s->eng.release();
+    s->eng_s.release();
     if (s->arena_base) (void)hipFree(s->arena_base);
     if (s->d_clk) (void)hipFree(s->d_clk);
+    if (s->ev_admit) (void)hipEventDestroy(s->ev_admit);
+    if (s->ev_small) (void)hipEventDestroy(s->ev_small);
+    if (s->stream_s) (void)hipStreamDestroy(s->stream_s);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
