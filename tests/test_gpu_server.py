@@ -98,8 +98,15 @@ def test_cancel_and_invalid_requests():
         srv.submit(100, 20, 5, 0.1, 1, 0)          # T = 0
     big = srv.submit(2_000_000, 400_000, 5, 0.2, 1, 20000, want_flux=True)
     small = srv.submit(1000, 200, 5, 0.13, 1, 50)
+    # a small ring (the second chain of launches) with many steps, cancelled
+    # while that chain runs
+    long_small = srv.submit(5000, 1000, 5, 0.2, 2, 400_000, want_flux=True)
     srv.cancel(big)
-    res = _drain(srv, 2)
+    time.sleep(0.05)
+    srv.cancel(long_small)
+    res = _drain(srv, 3)
     assert res[small]["status"] == 0
     assert res[big]["status"] == -5
+    assert res[long_small]["status"] == -5
+    assert srv.stats()["bytes_in_use"] == 0   # released as each result is queued
     srv.close()
