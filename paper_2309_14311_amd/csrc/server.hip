@@ -420,12 +420,12 @@ void nasch_server::loop() {
 
         // ---- the small chain's burst, once it has finished
         if (busy_s) {
-            const hipError_t q_s = hipEventQuery(ev_small);
-            if (q_s == hipSuccess) {
+            const hipError_t e_s = hipEventQuery(ev_small);
+            if (e_s == hipSuccess) {
                 busy_s = false;
                 if (complete(running_s, m_s, flux_host)) dirty_s = true;
-            } else if (q_s != hipErrorNotReady) {
-                (void)st.ok(q_s);
+            } else if (e_s != hipErrorNotReady) {
+                (void)st.ok(e_s);
                 fail_all();
                 busy_s = false;
                 dirty = dirty_s = true;
