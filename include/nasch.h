@@ -361,6 +361,13 @@ int nasch_server_stats(nasch_server* s, uint64_t* pending, uint64_t* running, ui
                        uint64_t* bytes_in_use, uint64_t* launches);
 /* Monotonic clock of the server in seconds (same clock as nasch_result). */
 double nasch_server_now(nasch_server* s);
+/* Liveness of the scheduling thread, for a watchdog: *since receives the
+ * seconds since it last finished a burst of launches or picked up new work (0
+ * when no request is queued or running) and *live the requests queued or
+ * running.  A value that keeps growing while requests are live means a launch
+ * has not returned; the server cannot abort a kernel, so a caller that sees
+ * this stops submitting and reports.  Either pointer may be NULL. */
+int nasch_server_health(nasch_server* s, double* since, uint64_t* live);
 /* Stop the scheduling thread and release everything; unfinished requests are dropped. */
 void nasch_server_destroy(nasch_server* s);
 

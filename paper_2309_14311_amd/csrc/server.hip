@@ -156,6 +156,7 @@ struct nasch_server {
     uint64_t n_done = 0;
     // read by nasch_server_stats while the scheduling thread runs
     std::atomic<uint64_t> n_running{0}, launches{0};
+    std::atomic<double> t_alive{0.0};   // last burst finished or work picked up
     bool stop = false;
     std::thread worker;
 
@@ -320,6 +321,7 @@ void nasch_server::loop() {
                        !ready_s.empty() || !cancel_ids.empty();
             });
             if (stop) return;
+            t_alive = now();
             cancels.swap(cancel_ids);
             for (uint64_t id : cancels) {
                 for (auto it = pending.begin(); it != pending.end(); ++it) {
@@ -410,6 +412,7 @@ void nasch_server::loop() {
                 continue;
             }
             launches += m;
+            t_alive = now();
             if (complete(running, m, flux_host)) dirty = true;
         } else if (busy_s && !st.ok(hipEventSynchronize(ev_small))) {
             fail_all();
@@ -423,6 +426,7 @@ void nasch_server::loop() {
             const hipError_t e_s = hipEventQuery(ev_small);
             if (e_s == hipSuccess) {
                 busy_s = false;
+                t_alive = now();
                 if (complete(running_s, m_s, flux_host)) dirty_s = true;
             } else if (e_s != hipErrorNotReady) {
                 (void)st.ok(e_s);
@@ -503,6 +507,8 @@ int nasch_server_submit(nasch_server* s, const nasch_request* req, uint64_t* id)
         std::lock_guard<std::mutex> lk(s->mu);
         j->id = s->next_id++;
         if (id) *id = j->id;
+        // an idle server starts its liveness clock at the first new request
+        if (s->pending.empty() && s->n_running == 0) s->t_alive = s->now();
         s->pending.push_back(std::move(j));
     }
     s->cv_work.notify_one();
@@ -547,6 +553,18 @@ int nasch_server_stats(nasch_server* s, uint64_t* pending, uint64_t* running, ui
 }
 
 double nasch_server_now(nasch_server* s) { return s ? s->now() : 0.0; }
+
+int nasch_server_health(nasch_server* s, double* since, uint64_t* live) {
+    if (!s) return NASCH_EINVAL;
+    uint64_t n;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        n = s->pending.size() + s->n_running;
+    }
+    if (live) *live = n;
+    if (since) *since = n ? std::max(0.0, s->now() - s->t_alive.load()) : 0.0;
+    return NASCH_OK;
+}
 
 void nasch_server_destroy(nasch_server* s) {
     if (!s) return;

@@ -117,6 +117,7 @@ _SIGS = {
     "nasch_server_cancel": (I32, [VP, U64]),
     "nasch_server_stats": (I32, [VP, u64p, u64p, u64p, u64p, u64p]),
     "nasch_server_now": (DBL, [VP]),
+    "nasch_server_health": (I32, [VP, ctypes.POINTER(ctypes.c_double), u64p]),
     "nasch_server_destroy": (None, [VP]),
     "nasch_ini_read": (I32, [ctypes.c_char_p, ctypes.POINTER(Ini)]),
     "nasch_writer_open": (I32, [vpp, ctypes.c_char_p, U64]),
@@ -441,6 +442,15 @@ class Server:
 
     def now(self) -> float:
         return _lib.nasch_server_now(self._h)
+
+    def health(self) -> dict:
+        """Seconds since the scheduling thread last made progress (0 when idle)
+        and the requests queued or running: a watchdog's view."""
+        since, live = ctypes.c_double(), ctypes.c_uint64()
+        rc = _lib.nasch_server_health(self._h, ctypes.byref(since), ctypes.byref(live))
+        if rc:
+            raise NaschError(rc, "nasch_server_health")
+        return {"since_progress_s": since.value, "live": live.value}
 
     def close(self):
         if getattr(self, "_h", None):

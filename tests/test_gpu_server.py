@@ -110,3 +110,26 @@ def test_cancel_and_invalid_requests():
     assert res[long_small]["status"] == -5
     assert srv.stats()["bytes_in_use"] == 0   # released as each result is queued
     srv.close()
+
+
+def test_health_for_a_watchdog():
+    """While a long request runs, the seconds since the scheduling thread last
+    finished a burst stay far below the request's run time and the live count
+    covers it; once the server is idle both are zero."""
+    srv = Server(k=32)
+    assert srv.health() == {"since_progress_s": 0.0, "live": 0}
+    rid = srv.submit(10_000_000, 2_000_000, 5, 0.2, 1, 100_000)
+    worst, saw_live, res = 0.0, False, []
+    deadline = time.time() + 60
+    while not res and time.time() < deadline:
+        h = srv.health()
+        worst = max(worst, h["since_progress_s"])
+        saw_live = saw_live or h["live"] >= 1
+        res = srv.poll(wait_ms=5)
+    assert res and res[0]["id"] == rid and res[0]["status"] == 0
+    assert saw_live and worst < 0.5
+    deadline = time.time() + 5
+    while srv.health()["live"] and time.time() < deadline:
+        time.sleep(0.01)
+    assert srv.health() == {"since_progress_s": 0.0, "live": 0}
+    srv.close()
