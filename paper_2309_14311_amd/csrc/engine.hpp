@@ -169,14 +169,23 @@ struct GridEngine {
         return true;
     }
 
-    // Recompute every ring's geometry for (k, q), rebuild the items (rings of
-    // larger vmax first, so the heavier waves start first) and upload both.
+    // Work of one 32-cell word and step of a ring, in VALU instructions as
+    // measured: 8 per unit of vmax for rules 1-4 and F(t), about 33 for the
+    // rule-3 block draw when p > 0, and about 35 more for the tie refinement
+    // when thr has bits below its top nibble.
+    static uint32_t word_step_cost(const RingDesc& r) {
+        return 8u * r.vmax + (r.sp.thr ? 33u : 0u) + ((r.sp.thr & 0x0FFFFFFFu) ? 35u : 0u);
+    }
+
+    // Recompute every ring's geometry for (k, q), rebuild the items (the rings
+    // whose waves take longest first, so the launch's tail is light) and
+    // upload both.
     hipError_t set_geometry(uint32_t kk, uint32_t qq, hipStream_t s) {
         items.clear();
         std::vector<uint32_t> order(rings.size());
         for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-            return rings[a].vmax > rings[b].vmax;
+            return word_step_cost(rings[a]) > word_step_cost(rings[b]);
         });
         uint32_t vmin = 0xFF, vmaxx = 0, n_open = 0;
         for (RingDesc& r : rings) {
