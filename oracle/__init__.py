@@ -74,6 +74,7 @@ def _load():
         "oracle_open_window_from_init": (I32, [U64, U64, U32, DBL, DBL, DBL, U64, U32, U32,
                                                U64, U64, U64, u8p]),
         "oracle_num_threads_available": (I32, []),
+        "oracle_fnv1a64": (U64, [u8p, U64, U64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -184,16 +185,21 @@ def mlcg_threshold(p: float) -> int:
     return int(_load().oracle_mlcg_threshold(float(p)))
 
 
-def run_agent_mlcg(L, x, v, vmax, p, seed, T, t0=0):
+def run_agent_mlcg(L, x, v, vmax, p, seed, T, t0=0, state0=None):
     """T steps with the shared minstd stream, starting at step t0 (the stream
     is first advanced serially past the t0 * N draws of the earlier steps).
-    Returns (x, v, flux[T])."""
+    With state0 given, the stream starts from that generator state instead
+    and seed and t0 are not used: a caller that jumps far into the stream
+    passes the state it computed.  Returns (x, v, flux[T])."""
     x = np.array(x, dtype=np.int32, copy=True, order="C")
     v = np.array(v, dtype=np.uint8, copy=True, order="C")
     lib = _load()
-    st = ctypes.c_uint32(lib.oracle_mlcg_seed(seed))
-    for _ in range(t0 * x.size):
-        st.value = lib.oracle_mlcg_next(st.value)
+    if state0 is not None:
+        st = ctypes.c_uint32(int(state0))
+    else:
+        st = ctypes.c_uint32(lib.oracle_mlcg_seed(seed))
+        for _ in range(t0 * x.size):
+            st.value = lib.oracle_mlcg_next(st.value)
     flux = np.zeros(max(T, 1), np.uint64)
     rc = lib.oracle_run_agent_mlcg(L, x.size, vmax, float(p), ctypes.byref(st), T,
                                    _ptr(x, i32p), _ptr(v, u8p), _ptr(flux, u64p))
@@ -286,6 +292,17 @@ def open_window_from_init(L, N, vmax, p, alpha, beta, seed, T, a, w, replica=0, 
     if rc:
         raise MemoryError("oracle_open_window_from_init")
     return out
+
+
+FNV64_OFFSET = 14695981039346656037
+
+
+def fnv1a64(data, h: int = FNV64_OFFSET) -> int:
+    """64-bit FNV-1a of the bytes of `data` (any C-contiguous numpy array, in
+    its in-memory little-endian layout), continuing from running hash h."""
+    a = np.ascontiguousarray(data)
+    b = a.view(np.uint8).reshape(-1) if a.size else np.zeros(0, np.uint8)
+    return int(_load().oracle_fnv1a64(_ptr(b, u8p), b.size, h))
 
 
 def num_threads_available() -> int:

@@ -603,3 +603,19 @@ int oracle_num_threads_available(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------- */
+/* FNV-1a, 64-bit (Fowler, Noll & Vo): offset basis 14695981039346656037,    */
+/* prime 2^40 + 2^8 + 0xb3.  Each byte is XORed in, then the hash is          */
+/* multiplied by the prime mod 2^64.  A checksum of a whole final state for   */
+/* the full-size parity records: h is the running hash (the offset basis to   */
+/* start), and the result is the hash after the n further bytes.             */
+/* ------------------------------------------------------------------------- */
+uint64_t oracle_fnv1a64(const uint8_t *bytes, uint64_t n, uint64_t h)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        h ^= bytes[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}

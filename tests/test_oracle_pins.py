@@ -331,6 +331,24 @@ def test_light_cone_window_matches_full_ring(orc):
     assert np.array_equal(out, full2[a:a + w])
 
 
+# --------------------------------------------------------------------------- checksum
+def test_fnv1a64_known_answers(orc):
+    """The checksum of the full-size parity records is 64-bit FNV-1a: the
+    published test vectors, and a hash continued over two pieces equals the
+    hash of their concatenation."""
+    with open(os.path.join(GOLDEN, "fnv1a64_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            text, want = line.rsplit(None, 1)
+            data = np.frombuffer(text.strip('"').encode("ascii"), np.uint8)
+            assert orc.fnv1a64(data) == int(want, 16)
+    rng = np.random.default_rng(5)
+    a = rng.integers(0, 256, 1000, dtype=np.uint8)
+    assert orc.fnv1a64(a[600:], orc.fnv1a64(a[:600])) == orc.fnv1a64(a)
+    assert orc.fnv1a64(np.array([1], np.uint64)) == orc.fnv1a64(np.array([1] + [0] * 7, np.uint8))
+
+
 # --------------------------------------------------------------------------- shared stream
 def test_minstd_rand_known_answer(orc):
     """The shared-stream generator is minstd_rand: its 10000th output from the
