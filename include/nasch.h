@@ -225,6 +225,37 @@ void nasch_free(nasch_sim* h);
 const char* nasch_strerror(int status);
 
 /* ======================================================================= */
+/* One step of a road held in caller-owned device memory: no handle and no   */
+/* state in the library.  For callers that keep their roads in their own     */
+/* device buffers (torch tensors, an arena of their own) instead of the      */
+/* handle's.                                                                 */
+/* ======================================================================= */
+
+/*
+ * Step t of the ring (rules 1-4 as above, synchronous update, the same R and
+ * therefore the same result as step t of a handle holding this state) from
+ * d_in to d_out.
+ *   d_in   device, L bytes, grid form (0xFF = empty, else v <= vmax); read only.
+ *          Other byte values give unspecified cells but no fault.
+ *   d_out  device, L bytes; receives the road after the step.  Must not
+ *          overlap d_in.  Both pointers 16-byte aligned.
+ *   L, vmax, p, seed, replica   as in nasch_init (1 <= L < 2^31, vmax <= 8,
+ *          0 <= p < 1); the car count is whatever d_in holds.
+ *   t      the step's index (R depends on it); t <= 2^32 - 2.
+ *   d_flux device uint64 (may be NULL): receives F(t).
+ *   stream hipStream_t to run on (NULL = the null stream).
+ * Asynchronous: enqueues the launches and returns.  The per-tile flux
+ * partials are scratch allocated and freed on the stream (stream-ordered
+ * allocation).  The caller owns every buffer.  Returns NASCH_EINVAL for bad
+ * parameters, a NULL, misaligned or overlapping road, NASCH_ERANGE for
+ * t > 2^32 - 2, NASCH_ENOMEM if the scratch cannot be allocated,
+ * NASCH_EDEVICE if a launch fails (nasch_thread_last_device_error).
+ */
+int nasch_grid_step_device(const uint8_t* d_in, uint8_t* d_out, uint64_t L, uint32_t vmax,
+                           double p, uint64_t seed, uint32_t replica, uint64_t t,
+                           uint64_t* d_flux, void* stream);
+
+/* ======================================================================= */
 /* Batched ensemble: many independent rings ("replicas") advanced together.  */
 /* The paper suggests running parameter-study cases as embarrassingly       */
 /* parallel jobs (section "Variations"); here every replica keeps its own   */

@@ -18,9 +18,12 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnasch.so")
 
-SOURCES = ["init.hip", "grid_kstep.hip", "agent.hip", "runtime.hip",
-           "batch.hip", "server.hip", "output.hip"]
+SOURCES = ["init.hip", "grid_kstep.hip", "grid_onestep.hip", "agent.hip", "runtime.hip",
+           "batch.hip", "server.hip", "output.hip", "device_api.hip"]
 CLI_SRC = "traffic_main.cpp"
+# measurement companion: the vector-ALU throughput probe (include/nasch_probe.h)
+PROBE_SRC = "valu_probe.hip"
+PROBE_LIB = os.path.join(PKG, "libnasch_probe.so")
 CLI = os.path.join(PKG, "nasch_traffic")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -53,6 +56,12 @@ def build(jobs: int | None = None) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    pobj = _compile(PROBE_SRC)
+    r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o",
+                        PROBE_LIB + ".tmp", pobj], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"probe link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     # the command-line driver, linked against the library next to it
     cmd = [HIPCC, "-O2", "-std=c++17", "-I", INCLUDE, os.path.join(CSRC, CLI_SRC), "-o",
            CLI + ".tmp", "-L", PKG, "-lnasch", "-Wl,-rpath,$ORIGIN"]

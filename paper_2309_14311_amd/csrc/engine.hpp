@@ -140,6 +140,7 @@ struct GridEngine {
     uint32_t launch_vmax = kMixedVmax;  // single specialisation when all rings agree
     bool launch_open = false;           // the rings are open roads (all or none)
     bool io_bytes = false;              // kernels read and write the byte form (one vmax)
+    bool onestep = false;               // the dedicated one-step kernel (bytes, k = 1, rings)
     uint32_t version = 0;               // bumped whenever d_items / geometry change
     // per-launch F(t) partials of every item and step, and the rings that keep a log
     uint32_t* d_partials = nullptr;
@@ -163,6 +164,7 @@ struct GridEngine {
     }
 
     bool geometry_ok(uint32_t kk, uint32_t qq) const {
+        if (onestep) return kk == 1 && (qq == 1 || qq == 2);
         uint32_t o, h, n;
         for (const RingDesc& r : rings)
             if (!kstep_geometry(r.L, r.vmax, kk, qq, &o, &h, &n)) return false;
@@ -189,7 +191,8 @@ struct GridEngine {
         });
         uint32_t vmin = 0xFF, vmaxx = 0, n_open = 0;
         for (RingDesc& r : rings) {
-            kstep_geometry(r.L, r.vmax, kk, qq, &r.own, &r.halo, &r.ntiles);
+            if (onestep) onestep_geometry(r.L, qq, &r.own, &r.halo, &r.ntiles);
+            else kstep_geometry(r.L, r.vmax, kk, qq, &r.own, &r.halo, &r.ntiles);
             vmin = std::min(vmin, r.vmax);
             vmaxx = std::max(vmaxx, r.vmax);
             n_open += r.open ? 1u : 0u;
@@ -276,7 +279,9 @@ struct GridEngine {
         for (uint32_t i = 0; i < n; ++i) {
             const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
             hipError_t e =
-                io_bytes ? launch_grid_kstep_bytes(launch_vmax, launch_open, q, d_rings, d_items,
+                onestep ? launch_grid_onestep(launch_vmax, q, d_rings, d_items,
+                                              (uint32_t)items.size(), d_partials, d_clk, i, i, s)
+                : io_bytes ? launch_grid_kstep_bytes(launch_vmax, launch_open, q, d_rings, d_items,
                                                    (uint32_t)items.size(), d_partials, ki, d_clk,
                                                    i * k, i, s)
                          : launch_grid_kstep(launch_vmax, launch_open, q, d_rings, d_items,

@@ -73,8 +73,39 @@ hipError_t launch_grid_kstep_bytes(uint32_t vmax, bool open, uint32_t q, const R
                                    const TileItem* items, uint32_t n_items, uint32_t* partials,
                                    uint32_t k, const Clock* clk, uint32_t s_off,
                                    uint32_t launch_idx, hipStream_t s);
-// Words per lane of the one-step kernel (q = 1 measured 7-20 % faster than 2).
+
+// ---- grid, one step per launch on the byte form (grid_onestep.hip) -----------
+// A block of kOneStepThreads lanes handles a segment of kOneStepThreads * q
+// words: one halo word at each end and the owned words in between.
+constexpr uint32_t kOneStepThreads = 256;
+// Words per lane of the one-step kernel.
 constexpr uint32_t kOneStepQ = 1;
+// Tile geometry of the one-step kernel: owned cells per tile (a ring that fits
+// one tile is one tile owning all L cells), the one-word halo, tile count.
+inline void onestep_geometry(uint32_t L, uint32_t q, uint32_t* own, uint32_t* halo,
+                             uint32_t* ntiles) {
+    const uint32_t own_full = 32u * (kOneStepThreads * q - 2u);
+    if (L <= own_full) {
+        *own = L;
+        *ntiles = 1;
+    } else {
+        *own = own_full;
+        *ntiles = (uint32_t)(((uint64_t)L + own_full - 1) / own_full);
+    }
+    *halo = 32u;
+}
+// One step of every tile of rings of one vmax (ring roads only; q = 1 or 2):
+// reads ring.buf[parity], writes the other buffer, F(t) partial per tile in
+// partials[item] (folded like the k-step kernel's with k = 1).
+// One step t of a single ring given by value: reads R.buf[0], writes R.buf[1]
+// (R.own from onestep_geometry with q = kOneStepQ, R.flux_acc null), tile F(t)
+// partials in partials[ntiles], then *flux = their sum when flux is not null.
+hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t ntiles, uint32_t* partials,
+                                      uint32_t t, unsigned long long* flux, hipStream_t s);
+hipError_t launch_grid_onestep(uint32_t vmax, uint32_t q, const RingDesc* rings,
+                               const TileItem* items, uint32_t n_items, uint32_t* partials,
+                               const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                               hipStream_t s);
 
 // ---- agent (agent.hip) --------------------------------------------------------
 // k steps per launch: each wave holds 64 * cpl consecutive cars (cpl cars per

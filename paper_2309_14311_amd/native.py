@@ -124,6 +124,7 @@ _SIGS = {
     "nasch_writer_frame": (I32, [VP, VP]),
     "nasch_writer_frame_host": (I32, [VP, u8p, U64]),
     "nasch_writer_close": (I32, [VP]),
+    "nasch_grid_step_device": (I32, [VP, VP, U64, U32, DBL, U64, U32, U64, VP, VP]),
 }
 
 SYMBOLS = tuple(_SIGS)
@@ -512,3 +513,61 @@ class Writer:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------- device buffers
+def _dptr(x) -> int | None:
+    """A device address: an int, or a tensor's data pointer (None for None)."""
+    if x is None:
+        return None
+    return x if isinstance(x, int) else x.data_ptr()
+
+
+def grid_step_device(d_in, d_out, L, vmax, p, seed, t, *, d_flux=None, replica=0, stream=None):
+    """nasch_grid_step_device: step t of the road in device buffer d_in into
+    d_out (device addresses or torch uint8 tensors); F(t) into d_flux (a device
+    uint64, optional).  Asynchronous on `stream`."""
+    lib = load()
+    rc = lib.nasch_grid_step_device(_dptr(d_in), _dptr(d_out), L, vmax, p, seed, replica, t,
+                                    _dptr(d_flux), _stream_ptr(stream))
+    if rc:
+        raise NaschError(rc, "nasch_grid_step_device", lib.nasch_thread_last_device_error())
+
+
+# --------------------------------------------------------------------------- measurement
+PROBE_PATH = os.path.join(_PKG, "libnasch_probe.so")
+PROBE_KINDS = {"bitop3": 0, "alignbit": 1, "bcnt": 2, "mul_lo": 3, "mul_hi": 4, "mad_u64": 5,
+               "dpp": 6, "add": 7, "xor": 8, "shift": 9, "lshl_or": 10, "perm": 11,
+               "mul_u24": 12, "add_u64": 13}
+_probe = None
+
+
+class ProbeResult(ctypes.Structure):
+    _fields_ = [("ms", DBL), ("wave_instructions", DBL), ("lane_ops_per_s", DBL),
+                ("sclk_hz", DBL)]
+
+
+def load_probe(path: str = PROBE_PATH) -> ctypes.CDLL:
+    """Load libnasch_probe.so (include/nasch_probe.h), after torch's HIP runtime."""
+    global _probe
+    if _probe is not None:
+        return _probe
+    if not os.path.exists(path):
+        raise RuntimeError(f"libnasch_probe.so not built ({path}); run python -m "
+                           "paper_2309_14311_amd.build")
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    lib.nasch_probe_valu.restype = I32
+    lib.nasch_probe_valu.argtypes = [U32, U32, U32, ctypes.POINTER(ProbeResult)]
+    _probe = lib
+    return lib
+
+
+def probe_valu(kind: str, blocks: int, iters: int) -> dict:
+    """nasch_probe_valu: sustained issue rate of one vector-ALU instruction kind."""
+    r = ProbeResult()
+    rc = load_probe().nasch_probe_valu(PROBE_KINDS[kind], blocks, iters, ctypes.byref(r))
+    if rc:
+        raise RuntimeError(f"nasch_probe_valu({kind}): status {rc}")
+    return {"ms": r.ms, "wave_instructions": r.wave_instructions,
+            "lane_ops_per_s": r.lane_ops_per_s, "sclk_hz": r.sclk_hz}

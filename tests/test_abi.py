@@ -99,3 +99,24 @@ def test_open_road_options_are_checked_before_any_device_call():
         h = ctypes.c_void_p(1)
         assert lib.nasch_init(ctypes.byref(h), 100, 10, 5, 0.1, 1, ctypes.byref(o)) == -1
         assert not h.value
+
+
+def test_probe_library_exports_its_header():
+    """libnasch_probe.so (the vector-ALU throughput probe) exports what
+    include/nasch_probe.h declares, and the binding's result struct matches."""
+    from paper_2309_14311_amd import native
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "nasch_probe.h")).read(),
+                  flags=re.S)
+    names = set(re.findall(r"\b(nasch_[a-z_]+)\s*\(", text))
+    assert names == {"nasch_probe_valu"}
+    lib = native.load_probe()
+    for n in names:
+        assert hasattr(lib, n)
+    src = ('#include "nasch_probe.h"\n#include <stdio.h>\n'
+           'int main(void){printf("%zu", sizeof(nasch_probe_result));return 0;}\n')
+    exe = os.path.join(ROOT, "_build", "sizeof_probe")
+    os.makedirs(os.path.dirname(exe), exist_ok=True)
+    subprocess.run(["gcc", "-x", "c", "-I", os.path.join(ROOT, "include"), "-o", exe, "-"],
+                   input=src, text=True, check=True)
+    size = int(subprocess.run([exe], capture_output=True, text=True, check=True).stdout)
+    assert size == ctypes.sizeof(native.ProbeResult)

@@ -55,3 +55,35 @@ def test_stream_mode_restore_agent_resumes_exactly():
 def test_stream_mode_only_in_agent_form():
     with pytest.raises(NaschError):
         Sim(1000, 100, 5, 0.1, 1, rep="grid", rng="stream")
+
+
+@pytest.fixture(scope="module")
+def far_stream_case():
+    """2^24 + 2^20 cars on 2^26 cells restored at step 2^32 - 60: their numbers
+    n = t N + i + 1 lie near 2^56, so the device's jump-ahead reads the
+    digits of n up to 16^14.  The oracle starts from the generator state
+    x0 a^(t N) mod m, computed with Python's exact modular power (the state
+    after t N draws of the stream), and then draws serially."""
+    L, N, vmax, p, seed, t0, T = 1 << 26, (1 << 24) + (1 << 20), 5, 0.13, 9, (1 << 32) - 60, 50
+    g0 = oracle.init_grid(L, N, vmax, seed, init_v=1)
+    x0, v0 = oracle.grid_to_agent(g0)
+    m = (1 << 31) - 1
+    state = oracle.mlcg_seed(seed) * pow(48271, t0 * N, m) % m
+    assert (t0 + T) * N >= 16 ** 14
+    want = oracle.run_agent_mlcg(L, x0, v0, vmax, p, seed, T, state0=state)
+    return dict(L=L, N=N, vmax=vmax, p=p, seed=seed, t0=t0, T=T, x0=x0, v0=v0, want=want)
+
+
+@pytest.mark.parametrize("kernel,k", [("kstep", 16), ("onestep", 0)])
+def test_stream_mode_far_into_the_stream(far_stream_case, kernel, k):
+    c = far_stream_case
+    s = Sim(c["L"], c["N"], c["vmax"], c["p"], c["seed"], rep="agent", rng="stream",
+            kernel=kernel, k=k)
+    s.restore_agent(c["x0"], c["v0"], c["t0"])
+    s.step(c["T"])
+    x, v = s.agent_state()
+    xo, vo, fo = c["want"]
+    np.testing.assert_array_equal(x, xo)
+    np.testing.assert_array_equal(v, vo)
+    np.testing.assert_array_equal(s.flux(c["t0"], c["T"]), fo)
+    s.close()

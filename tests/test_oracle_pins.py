@@ -364,6 +364,26 @@ def test_minstd_rand_known_answer(orc):
             assert x == want
 
 
+def test_mlcg_closed_form_state(orc):
+    """x_n = x0 a^n mod m is the closed form of a multiplicative LCG: a stream
+    started from that state (Python's exact modular power) continues exactly
+    as the stream advanced draw by draw, so tests may start it far along."""
+    m = 2**31 - 1
+    x = orc.mlcg_seed(11)
+    for _ in range(777):
+        x = orc.mlcg_next(x)
+    assert x == orc.mlcg_seed(11) * pow(48271, 777, m) % m
+    rng = np.random.default_rng(4)
+    L, N = 300, 70
+    g = _random_grid(rng, L, N, 4)
+    xs, vs = orc.grid_to_agent(g)
+    a = orc.run_agent_mlcg(L, xs, vs, 4, 0.3, 11, 12, t0=9)
+    b = orc.run_agent_mlcg(L, xs, vs, 4, 0.3, 11, 12,
+                           state0=orc.mlcg_seed(11) * pow(48271, 9 * N, m) % m)
+    for u, w in zip(a, b):
+        assert np.array_equal(u, w)
+
+
 def test_mlcg_threshold_is_ceil_p_m(orc):
     m = 2**31 - 1
     for p in (0.0, 0.13, 0.25, 0.5, 0.999):
