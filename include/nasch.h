@@ -255,6 +255,24 @@ int nasch_grid_step_device(const uint8_t* d_in, uint8_t* d_out, uint64_t L, uint
                            double p, uint64_t seed, uint32_t replica, uint64_t t,
                            uint64_t* d_flux, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * step as nasch_grid_step_device, same arguments, layout, ownership and
+ * errors, but it allocates nothing.  Its scratch (one uint32 flux partial per
+ * tile of 8128 cells) is a static device array of 264212 words (about 1 MiB)
+ * that each device the library runs on holds until the process ends; every L
+ * the library accepts fits it (a larger tile count would be NASCH_EINVAL).
+ * All calls on one device share that array, so calls that overlap on one
+ * device (different streams, or threads without ordering) race and must not
+ * be issued; calls ordered on one stream are safe.  The array's contents
+ * after a call are unspecified.  The first call on a device looks up the
+ * array's device address (hipGetSymbolAddress) with that device current.
+ */
+int nasch_grid_step_device_noalloc(const uint8_t* d_in, uint8_t* d_out, uint64_t L,
+                                   uint32_t vmax, double p, uint64_t seed, uint32_t replica,
+                                   uint64_t t, uint64_t* d_flux, void* stream);
+
 /* ======================================================================= */
 /* Batched ensemble: many independent rings ("replicas") advanced together.  */
 /* The paper suggests running parameter-study cases as embarrassingly       */

@@ -19,7 +19,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnasch.so")
 
 SOURCES = ["init.hip", "grid_kstep.hip", "grid_onestep.hip", "agent.hip", "runtime.hip",
-           "batch.hip", "server.hip", "output.hip", "device_api.hip"]
+           "batch.hip", "server.hip", "output.hip", "device_api.hip",
+           "device_noalloc.hip"]
 CLI_SRC = "traffic_main.cpp"
 # measurement companion: the vector-ALU throughput probe (include/nasch_probe.h)
 PROBE_SRC = "valu_probe.hip"

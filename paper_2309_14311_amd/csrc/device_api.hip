@@ -14,11 +14,11 @@
 
 using namespace nasch;
 
-namespace {
+namespace nasch {
 
 // Validates the arguments of a device-buffer step and describes the ring.
-int describe_ring(const uint8_t* d_in, const uint8_t* d_out, uint64_t L, uint32_t vmax, double p,
-                  uint64_t seed, uint32_t replica, uint64_t t, RingDesc* R) {
+int describe_device_ring(const uint8_t* d_in, const uint8_t* d_out, uint64_t L, uint32_t vmax,
+                         double p, uint64_t seed, uint32_t replica, uint64_t t, RingDesc* R) {
     int rc = validate_params(L, 0, vmax, p);
     if (rc) return rc;
     if (!d_in || !d_out) return NASCH_EINVAL;
@@ -40,6 +40,10 @@ int describe_ring(const uint8_t* d_in, const uint8_t* d_out, uint64_t L, uint32_
     return NASCH_OK;
 }
 
+}  // namespace nasch
+
+namespace {
+
 int device_error(hipError_t e) {
     thread_last_hip_error() = (int)e;
     return NASCH_EDEVICE;
@@ -53,7 +57,7 @@ int nasch_grid_step_device(const uint8_t* d_in, uint8_t* d_out, uint64_t L, uint
                            double p, uint64_t seed, uint32_t replica, uint64_t t,
                            uint64_t* d_flux, void* stream) {
     RingDesc R;
-    int rc = describe_ring(d_in, d_out, L, vmax, p, seed, replica, t, &R);
+    int rc = describe_device_ring(d_in, d_out, L, vmax, p, seed, replica, t, &R);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     uint32_t* partials = nullptr;

@@ -329,6 +329,11 @@ struct GraphCache {
     }
 };
 
+// Argument checks of the device-buffer step entry points and the descriptor of
+// their ring (device_api.hip): buf[0] = d_in, buf[1] = d_out, one-step tiling.
+int describe_device_ring(const uint8_t* d_in, const uint8_t* d_out, uint64_t L, uint32_t vmax,
+                         double p, uint64_t seed, uint32_t replica, uint64_t t, RingDesc* R);
+
 }  // namespace nasch
 
 namespace nasch {

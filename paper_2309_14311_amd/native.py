@@ -125,6 +125,7 @@ _SIGS = {
     "nasch_writer_frame_host": (I32, [VP, u8p, U64]),
     "nasch_writer_close": (I32, [VP]),
     "nasch_grid_step_device": (I32, [VP, VP, U64, U32, DBL, U64, U32, U64, VP, VP]),
+    "nasch_grid_step_device_noalloc": (I32, [VP, VP, U64, U32, DBL, U64, U32, U64, VP, VP]),
 }
 
 SYMBOLS = tuple(_SIGS)
@@ -532,6 +533,18 @@ def grid_step_device(d_in, d_out, L, vmax, p, seed, t, *, d_flux=None, replica=0
                                     _dptr(d_flux), _stream_ptr(stream))
     if rc:
         raise NaschError(rc, "nasch_grid_step_device", lib.nasch_thread_last_device_error())
+
+
+def grid_step_device_noalloc(d_in, d_out, L, vmax, p, seed, t, *, d_flux=None, replica=0,
+                             stream=None):
+    """nasch_grid_step_device_noalloc: grid_step_device with no allocation (the
+    flux partials live in the library's static device scratch)."""
+    lib = load()
+    rc = lib.nasch_grid_step_device_noalloc(_dptr(d_in), _dptr(d_out), L, vmax, p, seed,
+                                            replica, t, _dptr(d_flux), _stream_ptr(stream))
+    if rc:
+        raise NaschError(rc, "nasch_grid_step_device_noalloc",
+                         lib.nasch_thread_last_device_error())
 
 
 # --------------------------------------------------------------------------- measurement

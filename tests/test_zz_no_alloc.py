@@ -1,0 +1,67 @@
+"""The no-allocation entry point (nasch_grid_step_device_noalloc) against the
+allocating one (nasch_grid_step_device), through the C ABI: same inputs, same
+road and F(t) bit for bit, on consecutive calls whose sizes shrink (the static
+scratch keeps the previous call's contents, which must not leak into the next
+result), and against the oracle on a few steps."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2309_14311_amd.native import grid_step_device, grid_step_device_noalloc
+
+pytestmark = pytest.mark.gpu
+
+
+def _road(L, N, vmax, seed):
+    return torch.from_numpy(oracle.init_grid(L, N, vmax, seed, init_v=1)).to("cuda")
+
+
+def _one(fn, d_in, L, vmax, p, seed, t, replica):
+    out = torch.empty(L, dtype=torch.uint8, device="cuda")
+    flux = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    fn(d_in, out, L, vmax, p, seed, t, d_flux=flux, replica=replica,
+       stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), int(flux.cpu().numpy()[0])
+
+
+@pytest.mark.parametrize("sizes", [[(1 << 24) + 77, 5000, 100003, 33],
+                                   [2_000_003, 8128, 1, 8129]])
+def test_noalloc_equals_allocating_entry_point(sizes):
+    vmax, p, seed = 5, 0.13, 21
+    for i, L in enumerate(sizes):
+        d_in = _road(L, L // 5, vmax, seed + i)
+        t = 1000 + i
+        want = _one(grid_step_device, d_in, L, vmax, p, seed, t, i)
+        got = _one(grid_step_device_noalloc, d_in, L, vmax, p, seed, t, i)
+        np.testing.assert_array_equal(got[0], want[0], err_msg=f"call {i}: L={L}")
+        assert got[1] == want[1], (i, L)
+
+
+def test_noalloc_steps_match_oracle():
+    L, N, vmax, p, seed, T = 30011, 7000, 8, 0.25, 5, 12
+    g0 = oracle.init_grid(L, N, vmax, seed, init_v=1)
+    want, want_flux = oracle.run_grid(g0, vmax, p, seed, T)
+    a = torch.from_numpy(g0).to("cuda")
+    b = torch.empty_like(a)
+    flux = torch.zeros(T, dtype=torch.int64, device="cuda")
+    for s in range(T):
+        grid_step_device_noalloc(a, b, L, vmax, p, seed, s, d_flux=flux[s:],
+                                 stream=torch.cuda.current_stream())
+        a, b = b, a
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a.cpu().numpy(), want)
+    np.testing.assert_array_equal(flux.cpu().numpy().astype(np.uint64), want_flux)
+
+
+def test_noalloc_argument_errors():
+    from paper_2309_14311_amd import NaschError
+    a = torch.full((2048,), 0xFF, dtype=torch.uint8, device="cuda")
+    b = torch.empty(2048, dtype=torch.uint8, device="cuda")
+    with pytest.raises(NaschError) as e:
+        grid_step_device_noalloc(a[3:], b, 1000, 5, 0.1, 1, 0)
+    assert e.value.code == -1
+    with pytest.raises(NaschError) as e:
+        grid_step_device_noalloc(a, b, 1000, 5, 0.1, 1, (1 << 32) - 1)
+    assert e.value.code == -4
