@@ -15,7 +15,13 @@ Workloads (the sizes of the benchmark's one-road workloads):
   agent_stream  the agent ring with the shared minstd stream: the serial
                 stream oracle, one draw after another;
   open_road     the large ring opened at both ends (alpha 0.3, beta 0.9):
-                the serial open-road oracle (hours on one core).
+                the serial open-road oracle (hours on one core);
+  ensemble      the benchmark's 4096-replica ensemble (T = 5000, flux summed
+                from t = 1000): the serial oracle per replica, replicas spread
+                over worker processes.  The road checksum runs over every
+                replica's final road back to back in replica order (the layout
+                of a whole-batch snapshot), the flux checksum over the uint64
+                flux sums of all replicas.
 
 For each, the record holds the 64-bit FNV-1a of the final grid (L bytes,
 0xFF = empty, else v) and of the flux log (T uint64, little-endian), plus the
@@ -27,6 +33,7 @@ Existing records of other workloads are kept.
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import fcntl
 import importlib.util
 import json
@@ -69,8 +76,38 @@ def _record(cfg, grid, flux, how, seconds):
     }
 
 
+def _ensemble_replica(r):
+    """Final road and flux sum (t >= warm-up) of one ensemble replica."""
+    g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
+                          init_v=r["init_v"])
+    g, flux = oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], r["T"], replica=r["replica"])
+    return g.tobytes(), int(flux[r["warmup"]:].astype(np.uint64).sum())
+
+
+def run_ensemble(wl, workers):
+    t0 = time.time()
+    reps = wl.ensemble(4096, seed=1, T=5000, warmup=1000)
+    h = oracle.FNV64_OFFSET
+    sums = np.zeros(len(reps), np.uint64)
+    with cf.ProcessPoolExecutor(workers) as ex:
+        for i, (g, fsum) in enumerate(ex.map(_ensemble_replica, reps, chunksize=4)):
+            h = oracle.fnv1a64(np.frombuffer(g, np.uint8), h)
+            sums[i] = fsum
+    return {
+        "replicas": len(reps), "seed": 1, "T": 5000, "warmup": 1000,
+        "cells": int(sum(r["L"] for r in reps)),
+        "grid_fnv1a64": f"{h:016x}",
+        "flux_sums_fnv1a64": f"{oracle.fnv1a64(sums.astype('<u8')):016x}",
+        "flux_sums_total": int(sums.sum()),
+        "oracle": f"oracle.run_grid per replica, serial, {workers} worker processes",
+        "oracle_seconds": round(time.time() - t0, 1),
+    }
+
+
 def run(name, wl, threads):
     t0 = time.time()
+    if name == "ensemble":
+        return run_ensemble(wl, threads)
     if name in ("large_ring", "agent_ring"):
         cfg = wl.LARGE_RING if name == "large_ring" else wl.AGENT_RING
         g = oracle.init_grid(cfg["L"], cfg["N"], cfg["vmax"], cfg["seed"],

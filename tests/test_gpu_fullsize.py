@@ -1,5 +1,9 @@
 """Parity at the full workload sizes, in the launch configuration the benchmark
-times.  The oracle cannot run these rings whole, so the checks are:
+times:
+  - the whole final road and the whole flux log against the oracle, through
+    64-bit FNV-1a checksums that tests/golden/make_fullsize.py computed with
+    the oracle alone (the all-core twin of the grid step, or the serial stream
+    run) and stored in tests/golden/fullsize.json;
   - sampled windows of the final road against the oracle's light-cone
     evaluation (a cell after T steps depends only on cells within T*vmax);
   - the temporal-blocked, one-step and agent paths agree on the whole state;
@@ -7,6 +11,9 @@ times.  The oracle cannot run these rings whole, so the checks are:
     final velocities, and F(t) <= min(N vmax, L - N) (no car exceeds vmax or
     its gap, and the gaps add up to L - N).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -15,6 +22,20 @@ from paper_2309_14311_amd import Batch, Sim, workloads
 
 pytestmark = pytest.mark.gpu
 EMPTY = 0xFF
+with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "fullsize.json")) as _f:
+    GOLDEN = json.load(_f)
+
+
+def _assert_golden(name, cfg, grid, flux):
+    """The whole final road and flux log equal the oracle's (by checksum)."""
+    g = GOLDEN[name]
+    for key in ("L", "N", "vmax", "p", "seed", "replica", "init_v", "T"):
+        assert g[key] == cfg[key], (name, key)
+    assert f"{oracle.fnv1a64(grid):016x}" == g["grid_fnv1a64"], f"{name}: final road differs"
+    assert int(flux[-1]) == g["flux_last"] and int(flux.sum()) == g["flux_sum"]
+    assert f"{oracle.fnv1a64(flux.astype('<u8')):016x}" == g["flux_fnv1a64"], \
+        f"{name}: flux log differs"
 
 
 def _windows(L, n, w, seed):
@@ -50,12 +71,14 @@ def test_large_ring_kstep_onestep_and_oracle_windows():
     fa = a.flux(0, T)
     a.close()
     _flux_properties(fa, ga, N, cfg["vmax"])
-    b = Sim(L, N, cfg["vmax"], cfg["p"], cfg["seed"], init_v=cfg["init_v"], kernel="onestep")
+    _assert_golden("large_ring", cfg, ga, fa)
+    b = Sim(L, N, cfg["vmax"], cfg["p"], cfg["seed"], init_v=cfg["init_v"], kernel="onestep",
+            use_graph=True)
     b.step(T)
     gb, _ = b.snapshot()
-    np.testing.assert_array_equal(b.flux(0, T), fa)
+    fb = b.flux(0, T)
     b.close()
-    assert np.array_equal(ga, gb)
+    _assert_golden("large_ring", cfg, gb, fb)
 
 
 def test_open_road_kstep_onestep_and_oracle_windows():
@@ -117,6 +140,7 @@ def test_agent_ring_equals_grid_and_oracle_windows():
     L, N, T = cfg["L"], cfg["N"], cfg["T"]
     a = Sim(L, N, cfg["vmax"], cfg["p"], cfg["seed"], rep="agent", init_v=cfg["init_v"],
             use_graph=True)
+    a.autotune()
     a.step(T)
     _check_windows(a.snapshot_range, cfg, T, _windows(L, 4, 160, 2))
     ga, _ = a.snapshot()
@@ -125,12 +149,38 @@ def test_agent_ring_equals_grid_and_oracle_windows():
     a.close()
     assert int((np.diff(x) < 0).sum()) <= 1          # order kept: one cyclic descent
     _flux_properties(fa, ga, N, cfg["vmax"])
+    _assert_golden("agent_ring", cfg, ga, fa)
+    b = Sim(L, N, cfg["vmax"], cfg["p"], cfg["seed"], rep="agent", init_v=cfg["init_v"],
+            kernel="onestep", use_graph=True)
+    b.step(T)
+    gb, _ = b.snapshot()
+    fb = b.flux(0, T)
+    b.close()
+    _assert_golden("agent_ring", cfg, gb, fb)
     g = Sim(L, N, cfg["vmax"], cfg["p"], cfg["seed"], init_v=cfg["init_v"])
     g.step(T)
     gg, _ = g.snapshot()
     np.testing.assert_array_equal(g.flux(0, T), fa)
     g.close()
     assert np.array_equal(ga, gg)
+
+
+@pytest.mark.parametrize("kernel", ["kstep", "onestep"])
+def test_agent_ring_shared_stream_whole_state(kernel):
+    """The agent ring with the paper's shared minstd stream (car numbers up to
+    1000 N = 6.7e10), as the benchmark's --rng stream run: the whole final road
+    and flux log equal the serial stream oracle's."""
+    cfg = workloads.AGENT_RING
+    L, N, T = cfg["L"], cfg["N"], cfg["T"]
+    a = Sim(L, N, cfg["vmax"], cfg["p"], cfg["seed"], rep="agent", rng="stream",
+            init_v=cfg["init_v"], use_graph=True, kernel=kernel)
+    if kernel == "kstep":
+        a.autotune()
+    a.step(T)
+    ga, _ = a.snapshot()
+    fa = a.flux(0, T)
+    a.close()
+    _assert_golden("agent_stream", cfg, ga, fa)
 
 
 def test_ensemble_in_bench_configuration():
