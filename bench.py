@@ -30,12 +30,27 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+try:
+    _CPUS_AT_START = len(os.sched_getaffinity(0))
+except (AttributeError, OSError):
+    _CPUS_AT_START = os.cpu_count() or 1
+
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 BYTES_PER_CELL_UPDATE = 2.0  # read 1 B + write 1 B of uint8 state per cell per step
-# 32-bit vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-operations/s)
-VALU_PEAK = 256 * 4 * 16 * 2.4e9
-KSTEP_SRC = os.path.join(ROOT, "paper_2309_14311_amd", "csrc", "grid_kstep.hip")
+# 32-bit vector ALU, lane-operations/s.  gfx950 issues a wave64 add, xor or
+# three-input bitwise op (v_bitop3_b32) in 2 cycles per SIMD, the datapath of the
+# published 157.3 TFLOP/s fp32 vector peak: 256 CU x 4 SIMD x 32 lanes x 2.4 GHz.
+# Shifts, funnel shifts, byte permutes, popcounts, multiplies (v_mad_u64_u32),
+# 64-bit adds and DPP lane moves take 4 cycles, half that rate
+# (libnasch_probe measures both on the device, with the clock).
+VALU_PEAK = 256 * 4 * 32 * 2.4e9
+VALU_PEAK_4CYCLE = VALU_PEAK / 2
+CSRC = os.path.join(ROOT, "paper_2309_14311_amd", "csrc")
+# the sources the k-step kernel is compiled from
+KSTEP_SRCS = [os.path.join(CSRC, f) for f in ("grid_kstep.hip", "grid_common.hpp",
+                                               "bitplanes.hpp", "nasch_device.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grid_kstep_ensemble.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_grid_kstep_ensemble.json")
 
 
 def _log(msg):
@@ -55,51 +70,57 @@ def kstep_ops_per_cell_update(vmax, p):
     return (8 * vmax + (44 if thr > 0 else 0)) / 32.0
 
 
-def _src_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def _src_hash(paths):
+    """First 16 hex digits of the sha256 of the concatenated sources."""
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _profile_record(path, k, q):
+    """The committed counter record of the k-step kernel at (k, q), if it was
+    taken on the current kernel sources; else None."""
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_src_sha256_16") != _src_hash(KSTEP_SRCS):
+        return None
+    for r in rec.get("records", []):
+        if r.get("k") == k and r.get("q") == q:
+            return r
+    return None
 
 
 def _traffic(k, q, launch_cell_updates):
     """Counter-measured HBM bytes of one launch of the k-step kernel, scaled from
-    the committed counter summary (bytes per cell-update at the same (k, q)), if
-    it was taken on the current kernel source; else None."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            rec = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if rec.get("kernel_src_sha256_16") != _src_hash(KSTEP_SRC):
-        return None
-    for r in rec.get("records", []):
-        if r.get("k") == k and r.get("q") == q:
-            return r["bytes_per_cell_update"] * launch_cell_updates
-    return None
+    the committed counter summary (bytes per cell-update at the same (k, q))."""
+    r = _profile_record(TRAFFIC_FILE, k, q)
+    return None if r is None else r["bytes_per_cell_update"] * launch_cell_updates
 
 
-def _time_oracle(reps, nthreads, budget_s, steps):
-    """Run the oracle on replicas taken in order, each `steps` steps from its
-    initial state, until `budget_s` seconds of CPU work have been spent; returns
-    (cell-updates done, seconds spent, replicas run, threads used)."""
-    import oracle
-    done_cells, spent, n = 0, 0.0, 0
-    for r in reps:
-        g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
-                              init_v=r["init_v"])
-        t0 = time.perf_counter()
-        if r.get("boundary") == "open":   # the serial open-road step (no threaded twin)
-            oracle.run_open(g0, r["vmax"], r["p"], r["alpha"], r["beta"], r["seed"], steps,
-                            replica=r["replica"])
-            nthreads = 1
-        else:
-            oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], steps, replica=r["replica"],
-                            nthreads=nthreads)
-        spent += time.perf_counter() - t0
-        done_cells += r["L"] * steps
-        n += 1
-        if spent >= budget_s:
-            break
-    return done_cells, spent, n, nthreads
+def _issued_valu(k, q, launch_cell_updates):
+    """VALU lane-instructions one launch of the k-step kernel issues
+    (SQ_INSTS_VALU x 64 from the committed counter summary, per cell-update)."""
+    r = _profile_record(VALU_FILE, k, q)
+    return None if r is None else r["valu_lane_instructions_per_cell_update"] * launch_cell_updates
+
+
+def measure_valu():
+    """The vector-ALU ceilings measured live (libnasch_probe): lane-ops/s of a
+    2-cycle instruction (v_bitop3_b32) and of a 4-cycle one (v_alignbit_b32),
+    each with the shader clock during its run."""
+    from paper_2309_14311_amd import native
+    out = {}
+    for kind in ("bitop3", "alignbit"):
+        r = native.probe_valu(kind, 4096, 4000)
+        out[kind] = {"lane_ops_per_s": r["lane_ops_per_s"], "sclk_ghz": r["sclk_hz"] / 1e9,
+                     "frac_of_derived": r["lane_ops_per_s"] / (
+                         VALU_PEAK if kind == "bitop3" else VALU_PEAK_4CYCLE)}
+    return out
 
 
 def _host_info():
@@ -123,65 +144,167 @@ def _host_info():
             "physical_cores": len(cores) or None, "logical_cpus": os.cpu_count()}
 
 
-def cpu_baseline_ensemble(reps, budget_s=15.0, steps=100):
-    """The oracle on a bounded sample of the ensemble: the all-core OpenMP twin
-    for `budget_s` seconds (the reported value), then the serial oracle for
-    half as long on the same replicas."""
-    def sample(cells, spent, n):
-        return (f"first {n} of {len(reps)} replicas, {steps} steps each from t=0, "
-                f"{cells:.3g} cell-updates in {spent:.1f} s")
+def _cpu_threads():
+    """Threads of the all-core oracle: one per physical core (no SMT), within the
+    CPUs this process could use when it started (an OpenMP runtime that binds
+    its threads narrows the affinity later)."""
+    phys = _host_info()["physical_cores"] or os.cpu_count() or 1
+    return max(1, min(phys, _CPUS_AT_START))
 
-    cells, spent, n, threads = _time_oracle(reps, min(16, os.cpu_count() or 1), budget_s, steps)
-    s_cells, s_spent, s_n, _ = _time_oracle(reps, 1, budget_s / 2, steps)
-    return {"value": cells / spent, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle", "sample": sample(cells, spent, n),
-            "serial": {"value": s_cells / s_spent, "unit": "cell-updates/s", "cores": 1,
-                       "sample": sample(s_cells, s_spent, s_n)},
+
+def _median_of_chunks(advance, cells, warm_s, chunk_s, repeats=3):
+    """The oracle's step loop timed the way the CPU baseline protocol asks:
+    untimed warm-up steps (1, 2, 4, ... at a time) until warm_s seconds have
+    passed, which also gives the rate, then `repeats` consecutive chunks of
+    timed steps, each sized for about chunk_s seconds at that rate.  Returns
+    (median chunk rate in cell-updates/s, the chunk rates, warm-up steps, chunk
+    steps).  advance(t0, steps) runs the sample."""
+    t, n, spent, rate = 0, 1, 0.0, 0.0
+    while spent < warm_s:
+        t0 = time.perf_counter()
+        advance(t, n)
+        dt = time.perf_counter() - t0
+        spent += dt
+        rate = cells * n / max(dt, 1e-9)
+        t += n
+        n *= 2
+    chunk = max(1, int(round(rate * chunk_s / cells)))
+    warm, rates = t, []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        advance(t, chunk)
+        rates.append(cells * chunk / (time.perf_counter() - t0))
+        t += chunk
+    return float(np.median(rates)), rates, warm, chunk
+
+
+def _stratified(reps, target_cells):
+    """Every m-th replica in order of L (all sizes represented), m chosen so the
+    sample holds about target_cells cells."""
+    order = sorted(range(len(reps)), key=lambda i: reps[i]["L"])
+    total = sum(r["L"] for r in reps)
+    m = min(len(order), max(1, int(round(total / max(1.0, target_cells)))))
+    return [reps[i] for i in order[m // 2::m]], m
+
+
+def cpu_baseline_ensemble(reps, T, budget_s=15.0):
+    """The oracle on a bounded, L-stratified sample of the ensemble: the all-core
+    OpenMP twin on one thread per physical core (OMP_PLACES=cores,
+    OMP_PROC_BIND=spread), 10 warm-up steps, then the median of 3 chunks of 20
+    timed steps (the reported value); the serial oracle the same way on a
+    smaller sample.  The sample's rate stands for the whole workload, whose
+    time is extrapolated from it (labelled as such)."""
+    import oracle
+    threads = _cpu_threads()
+    total = sum(r["L"] for r in reps)
+
+    def run(sample, nthreads, warm, chunk):
+        grids = [oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
+                                  init_v=r["init_v"]) for r in sample]
+
+        def advance(t0, steps):
+            for i, r in enumerate(sample):
+                if r.get("boundary") == "open":
+                    grids[i] = oracle.run_open(grids[i], r["vmax"], r["p"], r["alpha"],
+                                               r["beta"], r["seed"], steps, t0=t0,
+                                               replica=r["replica"])[0]
+                else:
+                    grids[i] = oracle.run_grid(grids[i], r["vmax"], r["p"], r["seed"], steps,
+                                               t0=t0, replica=r["replica"], nthreads=nthreads)[0]
+        cells = sum(r["L"] for r in sample)
+        return _median_of_chunks(advance, cells, warm, chunk), cells
+
+    # the sample: about 20 steps of it per timed chunk at a rate typical of such
+    # hosts (1e8 cell-updates/s per core); a fifth of the budget warms up, each
+    # of the 3 chunks takes about a quarter
+    is_open = any(r.get("boundary") == "open" for r in reps)
+    nthreads = 1 if is_open else threads
+    sample, m = _stratified(reps, 1.0e8 * nthreads * budget_s / 4 / 20)
+    (value, rates, warm, chunk), cells = run(sample, nthreads, budget_s / 5, budget_s / 4)
+    s_sample, s_m = _stratified(reps, 1.0e8 * budget_s / 8 / 20)
+    (s_value, s_rates, s_warm, s_chunk), s_cells = run(s_sample, 1, budget_s / 10, budget_s / 8)
+
+    def desc(mm, smp, c, w, ch, rr):
+        return (f"every {mm}th of {len(reps)} replicas in order of L ({len(smp)}, {c:.3g} "
+                f"cells): {w} warm-up steps, then median of 3 chunks of {ch} steps "
+                f"(chunk rates {', '.join(f'{x:.3g}' for x in rr)})")
+    return {"value": value, "unit": "cell-updates/s", "cores": nthreads, "kind": "oracle",
+            "sample": desc(m, sample, cells, warm, chunk, rates),
+            "omp": {"OMP_PLACES": os.environ.get("OMP_PLACES"),
+                    "OMP_PROC_BIND": os.environ.get("OMP_PROC_BIND"), "threads": nthreads},
+            "extrapolated_full_workload_s": total * T / value, "extrapolated": True,
+            "serial": {"value": s_value, "unit": "cell-updates/s", "cores": 1,
+                       "sample": desc(s_m, s_sample, s_cells, s_warm, s_chunk, s_rates),
+                       "extrapolated_full_workload_s": total * T / s_value,
+                       "extrapolated": True},
             "host": _host_info()}
 
 
-def cpu_baseline_single(cfg, budget_s=15.0, rng="keyed", max_cells=1 << 22):
+def cpu_baseline_single(cfg, T, budget_s=15.0, rng="keyed", max_cells=1 << 22):
     """The oracle on a bounded sample of a one-road workload: a road of at most
-    max_cells cells with the workload's density, vmax, p and seed, stepped a
-    chunk of steps at a time for `budget_s` seconds on all cores (the reported
-    value), then for half as long serially.  The keyed grid oracle stands for
-    both representations (they give identical results); an open road and the
-    shared stream have only serial oracles."""
+    max_cells cells with the workload's density, vmax, p and seed.  After a
+    warm-up chunk, the median of 3 timed chunks on one thread per physical core
+    (the reported value), then the same serially.  The keyed grid oracle stands
+    for both representations (they give identical results); an open road and
+    the shared stream have only serial oracles.  The full workload's time is
+    extrapolated from the rate (labelled as such)."""
     import oracle
     L = min(cfg["L"], max_cells)
     N = int(round(cfg["N"] * L / cfg["L"]))
     g0 = oracle.init_grid(L, N, cfg["vmax"], cfg["seed"], init_v=cfg["init_v"])
-    chunk = max(10, (1 << 20) // L)
     is_open = "alpha" in cfg
     stream = rng == "stream"
+    threads = 1 if (is_open or stream) else _cpu_threads()
 
-    def timed(nthreads, budget):
-        g, t, spent = g0, 0, 0.0
-        x, v = oracle.grid_to_agent(g0) if stream else (None, None)
-        while spent < budget:
-            t0 = time.perf_counter()
+    def measure(nthreads, budget):
+        state = {"g": g0}
+        if stream:
+            state["x"], state["v"] = oracle.grid_to_agent(g0)
+
+        def advance(t0, steps):
             if is_open:
-                g = oracle.run_open(g, cfg["vmax"], cfg["p"], cfg["alpha"], cfg["beta"],
-                                    cfg["seed"], chunk, t0=t)[0]
+                state["g"] = oracle.run_open(state["g"], cfg["vmax"], cfg["p"], cfg["alpha"],
+                                             cfg["beta"], cfg["seed"], steps, t0=t0)[0]
             elif stream:
-                # each chunk starts a stream of its own (seed + t): fast-forwarding
-                # one past t N draws is serial work that would dwarf the chunk
-                x, v, _ = oracle.run_agent_mlcg(L, x, v, cfg["vmax"], cfg["p"],
-                                                cfg["seed"] + t, chunk)
+                # the chunk continues the stream from its state after t0 N draws
+                m = (1 << 31) - 1
+                st = oracle.mlcg_seed(cfg["seed"]) * pow(48271, t0 * N, m) % m
+                state["x"], state["v"], _ = oracle.run_agent_mlcg(
+                    L, state["x"], state["v"], cfg["vmax"], cfg["p"], cfg["seed"], steps,
+                    state0=st)
             else:
-                g = oracle.run_grid(g, cfg["vmax"], cfg["p"], cfg["seed"], chunk, t0=t,
-                                    nthreads=nthreads)[0]
-            spent += time.perf_counter() - t0
-            t += chunk
-        return L * t / spent, f"L = {L}, N = {N}, {t} steps from t = 0 in {spent:.1f} s"
+                state["g"] = oracle.run_grid(state["g"], cfg["vmax"], cfg["p"], cfg["seed"],
+                                             steps, t0=t0, nthreads=nthreads)[0]
+        rate, rates, warm, chunk = _median_of_chunks(advance, L, budget / 5, budget / 4)
+        return rate, (f"L = {L}, N = {N}: {warm} warm-up steps, then median of 3 chunks of "
+                      f"{chunk} steps (chunk rates {', '.join(f'{x:.3g}' for x in rates)})")
 
-    threads = 1 if (is_open or stream) else min(16, os.cpu_count() or 1)
-    value, smp = timed(threads, budget_s)
-    s_value, s_smp = timed(1, budget_s / 2)
+    value, smp = measure(threads, budget_s)
+    s_value, s_smp = measure(1, budget_s / 2)
     return {"value": value, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": smp, "serial": {"value": s_value, "unit": "cell-updates/s", "cores": 1,
-                                      "sample": s_smp},
+            "sample": smp,
+            "omp": {"OMP_PLACES": os.environ.get("OMP_PLACES"),
+                    "OMP_PROC_BIND": os.environ.get("OMP_PROC_BIND"), "threads": threads},
+            "extrapolated_full_workload_s": cfg["L"] * T / value, "extrapolated": True,
+            "serial": {"value": s_value, "unit": "cell-updates/s", "cores": 1, "sample": s_smp,
+                       "extrapolated_full_workload_s": cfg["L"] * T / s_value,
+                       "extrapolated": True},
             "host": _host_info()}
+
+
+def _cpu_baseline(job):
+    """Run a CPU baseline in a child process of its own: the OpenMP runtime
+    there starts with OMP_PLACES=cores and OMP_PROC_BIND=spread and every CPU
+    of the process, which this process (torch's own OpenMP runtime binds its
+    main thread once those variables are set) could not offer."""
+    import subprocess
+    env = dict(os.environ, OMP_PLACES="cores", OMP_PROC_BIND="spread",
+               OMP_NUM_THREADS=str(_cpu_threads()))
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                        json.dumps(job)], capture_output=True, text=True, env=env, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"CPU baseline child failed:\n{r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def bench_ensemble(args):
@@ -229,7 +352,10 @@ def bench_ensemble(args):
     ops_per_cu = sum(r["L"] * kstep_ops_per_cell_update(r["vmax"], r["p"]) for r in reps) / cells
     ops_achieved = ops_per_cu * cell_updates / launches / (kernel_ms * 1e-3)
     is_open = args.workload == "open_ensemble"
-    traffic = None if is_open else _traffic(k, q, cells * k)   # counters cover the ring kernel
+    # counters cover the ring kernel
+    traffic = None if is_open else _traffic(k, q, cells * k)
+    issued = None if is_open else _issued_valu(k, q, cells * k)
+    probe = measure_valu()
 
     extra = {"batched_kernel_cups": cell_updates / (np.mean(step_ms) * 1e-3),
              "k": k, "q": q, "launches_per_pass": launches,
@@ -273,17 +399,30 @@ def bench_ensemble(args):
                                f"[1e3,1e6], rho U[0.05,0.6], p in {{0,.13,.25,.5}}, vmax U{{1..8}}, "
                                f"T={args.T} ({args.warmup_steps} warm-up)",
                    "cells": cells, "T": args.T},
-        "hbm_roofline_frac": value * BYTES_PER_CELL_UPDATE / HBM_PEAK,
+        # the whole pass's cell-updates priced at the one-step kernel's 2 B each:
+        # a cell-update equivalent, not bytes that crossed HBM (see roofline.traffic)
+        "cell_update_equiv_hbm_frac": value * BYTES_PER_CELL_UPDATE / HBM_PEAK,
         "roofline": {"bound": "alu", "achieved": ops_achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "TOP/s", "frac": ops_achieved / VALU_PEAK, "traffic": traffic,
                      "kernel": f"grid_kstep_mixed_kernel<{q}, {'true' if is_open else 'false'}>",
                      "kernel_ms": kernel_ms, "ops_per_cell_update": ops_per_cu,
-                     "hbm_algorithmic_GBps": achieved / 1e9,
-                     "hbm_algorithmic_frac": achieved / HBM_PEAK},
+                     "issued_valu_lane_instr_per_s": None if issued is None
+                     else issued / (kernel_ms * 1e-3),
+                     "issued_frac": None if issued is None
+                     else issued / (kernel_ms * 1e-3) / VALU_PEAK,
+                     "probe": probe,
+                     "hbm_counter_GBps": None if traffic is None
+                     else traffic / (kernel_ms * 1e-3) / 1e9,
+                     "hbm_counter_frac": None if traffic is None
+                     else traffic / (kernel_ms * 1e-3) / HBM_PEAK,
+                     "cell_update_equiv_GBps": achieved / 1e9,
+                     "cell_update_equiv_frac": achieved / HBM_PEAK},
         "extra": extra,
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline_ensemble(reps, budget_s=args.cpu_budget)
+        line["cpu_baseline"] = _cpu_baseline(dict(
+            kind="ensemble", open=is_open, replicas=args.replicas, T=args.T,
+            warmup=args.warmup_steps, budget=args.cpu_budget))
     return line
 
 
@@ -338,6 +477,33 @@ def bench_serving(args):
     work = sum(r["L"] * r["T"] for r in reqs)
     bad = sum(1 for r in results.values() if r["status"] != 0)
     value = work / (last - first)
+    # latency per decade of L
+    bands = {}
+    for lo in (1e3, 1e4, 1e5, 1e6):
+        sel = np.array([r["t_done"] - r["t_submit"] for rid, r in results.items()
+                        if lo <= submitted[rid]["L"] < lo * 10 or (lo == 1e6 and
+                                                                   submitted[rid]["L"] >= 1e7)])
+        if sel.size:
+            bands[f"L_{lo:.0e}"] = {"n": int(sel.size), "p50_s": float(np.percentile(sel, 50)),
+                                    "p99_s": float(np.percentile(sel, 99))}
+    # untimed tail: every 50th request's flux sum against the oracle (the
+    # all-core twin), within a CPU budget; requests of more than 5e9
+    # cell-updates are left to the unit tests
+    import oracle
+    checked, mismatched, spent = 0, 0, 0.0
+    threads = _cpu_threads()
+    for i, (rid, r) in enumerate(sorted(submitted.items())):
+        if i % 50 or r["L"] * r["T"] > 5e9 or spent > args.cpu_budget * 2:
+            continue
+        t0 = time.perf_counter()
+        g0 = oracle.init_grid(r["L"], r["N"], r["vmax"], r["seed"], replica=r["replica"],
+                              init_v=r["init_v"])
+        _, f = oracle.run_grid(g0, r["vmax"], r["p"], r["seed"], r["T"], replica=r["replica"],
+                               nthreads=threads)
+        spent += time.perf_counter() - t0
+        checked += 1
+        if results[rid]["status"] != 0 or int(f.sum()) != int(results[rid]["flux_sum"]):
+            mismatched += 1
     return {
         "metric": "cell-updates/s and % HBM roofline, batched vs plain on 1 GPU, bit-exact",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": len(reqs),
@@ -346,10 +512,13 @@ def bench_serving(args):
         "data": "synthetic",
         "config": {"workload": f"serving: Poisson arrivals at {args.rate_frac} x capacity "
                                f"({rate:.1f} requests/s), {len(reqs)} requests"},
-        "hbm_roofline_frac": value * BYTES_PER_CELL_UPDATE / HBM_PEAK,
+        "cell_update_equiv_hbm_frac": value * BYTES_PER_CELL_UPDATE / HBM_PEAK,
         "extra": {"latency_p50_s": float(np.percentile(lat, 50)),
                   "latency_p99_s": float(np.percentile(lat, 99)),
-                  "latency_mean_s": float(lat.mean()), "failed": bad,
+                  "latency_mean_s": float(lat.mean()), "latency_by_L": bands, "failed": bad,
+                  "oracle_checked": checked, "oracle_mismatches": mismatched,
+                  "oracle_check": "every 50th request of at most 5e9 cell-updates, flux sum "
+                                  "over all T steps against the oracle's all-core twin",
                   "capacity_cups": cap_cups, "rate_per_s": rate, "launches": st["launches"],
                   "makespan_s": last - first, "server_clock_origin": s0},
     }
@@ -387,6 +556,7 @@ def bench_single(args, cfg, rep, kernels):
     if "onestep" in res:
         # one step per launch moves all of them every step: HBM-bound
         res["onestep_hbm_frac"] = res["onestep"] * bpcu / HBM_PEAK
+    ms_T = {kern: cfg["L"] * T / res[kern] * 1e3 for kern in kernels}
     if rep == "grid" and cfg["L"] >= 1 << 24:
         # achievable HBM bandwidth, bytes read + written over 1 GiB, timed with
         # events: the runtime's device-to-device copy, and an elementwise
@@ -432,12 +602,28 @@ def bench_single(args, cfg, rep, kernels):
                                f"p={cfg['p']} T={T}" + (" shared-stream rng" if rng == "stream"
                                                         else ""),
                    "k": info["k"], "q": info["q"]},
-        "hbm_roofline_frac": value * bpcu / HBM_PEAK,
+        # the k-step rate priced at the one-step kernel's algorithmic bytes: a
+        # cell-update equivalent, not bytes that crossed HBM
+        "cell_update_equiv_hbm_frac": value * bpcu / HBM_PEAK,
         "bytes_per_cell_update": bpcu,
         "extra": {(k if k.endswith(("frac", "GBps")) else f"{k}_cups"): v for k, v in res.items()},
     }
+    line["extra"].update({f"{kern}_ms_for_T": v for kern, v in ms_T.items()})
+    if rep == "grid" and not road:
+        # the k-step kernel is bound by vector-ALU issue (see the ensemble)
+        ops = kstep_ops_per_cell_update(cfg["vmax"], cfg["p"]) * value
+        line["roofline"] = {"bound": "alu", "achieved": ops / 1e12, "peak": VALU_PEAK / 1e12,
+                            "unit": "TOP/s", "frac": ops / VALU_PEAK, "traffic": None,
+                            "kernel": f"grid_kstep_kernel<{cfg['vmax']}, {info['q']}, false, "
+                                      f"false>"}
+        if "onestep" in res:
+            line["roofline_onestep"] = {
+                "bound": "hbm", "achieved": res["onestep"] * bpcu / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": res["onestep"] * bpcu / HBM_PEAK, "traffic": None,
+                "kernel": f"grid_onestep_kernel<{cfg['vmax']}, 1>"}
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline_single(cfg, budget_s=args.cpu_budget, rng=rng)
+        line["cpu_baseline"] = _cpu_baseline(dict(kind="single", cfg=cfg, T=T,
+                                                  budget=args.cpu_budget, rng=rng))
     return line
 
 
@@ -469,7 +655,21 @@ def main():
     ap.add_argument("--rng", default="keyed", choices=["keyed", "stream"],
                     help="rule-3 numbers of the agent workload: keyed draws or the shared "
                          "minstd stream")
+    ap.add_argument("--cpu-baseline-child", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_baseline_child:
+        # the CPU baseline's own process (see _cpu_baseline): no torch, no GPU
+        job = json.loads(args.cpu_baseline_child)
+        from paper_2309_14311_amd import workloads
+        if job["kind"] == "ensemble":
+            make = workloads.open_ensemble if job["open"] else workloads.ensemble
+            reps = make(job["replicas"], seed=1, T=job["T"], warmup=job["warmup"])
+            out = cpu_baseline_ensemble(reps, job["T"], budget_s=job["budget"])
+        else:
+            out = cpu_baseline_single(job["cfg"], job["T"], budget_s=job["budget"],
+                                      rng=job["rng"])
+        print(json.dumps(out), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the NaSch hot path here is measured per GPU "
               "(--gpus 1)", file=sys.stderr)

@@ -338,13 +338,33 @@ int describe_device_ring(const uint8_t* d_in, const uint8_t* d_out, uint64_t L, 
 
 namespace nasch {
 
-// Candidate settings the autotuner times.
-inline std::vector<std::pair<uint32_t, uint32_t>> kstep_candidates() {
+// Candidate settings the autotuner times.  Rings that fit one segment at q
+// take one wave each, so their launches are latency-bound: for them the
+// deepest temporal block that still keeps every ring in a single tile (and
+// half of it) is a candidate too, beyond the fixed set.
+inline std::vector<std::pair<uint32_t, uint32_t>> kstep_candidates(
+    const std::vector<RingDesc>& rings) {
     std::vector<std::pair<uint32_t, uint32_t>> c;
     const uint32_t ks[] = {8, 16, 24, 32, 48, 64};
     const uint32_t qs[] = {1, 2, 3, 4};
-    for (uint32_t q : qs)
+    for (uint32_t q : qs) {
         for (uint32_t k : ks) c.emplace_back(k, q);
+        if (rings.empty()) continue;
+        uint32_t kmax = 1u << 20;
+        for (const RingDesc& r : rings) kmax = std::min(kmax, kstep_max_k(r.vmax, q));
+        for (uint32_t k = kmax; k > 64u; k = k * 7u / 8u) {
+            bool one_tile = true;
+            for (const RingDesc& r : rings) {
+                uint32_t o, h, n;
+                one_tile = one_tile && kstep_geometry(r.L, r.vmax, k, q, &o, &h, &n) && n == 1;
+            }
+            if (one_tile) {
+                c.emplace_back(k, q);
+                if (k / 2u > 64u) c.emplace_back(k / 2u, q);
+                break;
+            }
+        }
+    }
     return c;
 }
 
@@ -399,7 +419,7 @@ inline hipError_t autotune_grid(const std::vector<RingDesc>& rings, uint32_t t_n
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_clk, &c0, sizeof(Clock), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    for (auto kq : kstep_candidates()) {
+    for (auto kq : kstep_candidates(rings)) {
         if (e != hipSuccess) break;
         if (!scratch.geometry_ok(kq.first, kq.second)) continue;
         e = scratch.set_geometry(kq.first, kq.second, s);

@@ -36,6 +36,46 @@ static int check_kstep() {
     return 0;
 }
 
+// The autotuner's candidates: the fixed set for every q, and for rings that
+// fit one segment the deepest single-tile block (and half of it).
+static int check_candidates() {
+    RingDesc r{};
+    r.L = 1000;
+    r.vmax = 5;
+    const std::vector<RingDesc> ref{r};
+    uint32_t deepest = 0;
+    for (auto kq : kstep_candidates(ref)) {
+        uint32_t o, h, n;
+        if (!kstep_geometry(r.L, r.vmax, kq.first, kq.second, &o, &h, &n))
+            return printf("candidate (%u, %u) has no geometry\n", kq.first, kq.second), 1;
+        if (kq.first > 64u && n != 1)
+            return printf("deep candidate (%u, %u) is not one tile\n", kq.first, kq.second), 1;
+        deepest = std::max(deepest, kq.first);
+    }
+    // q = 4: a 8192-cell segment holds L = 1000 beside halos of up to 3584 cells
+    if (deepest < 600u) return printf("deepest candidate %u\n", deepest), 1;
+    RingDesc big = r;
+    big.L = 1u << 20;
+    for (auto kq : kstep_candidates({big}))
+        if (kq.first > 64u) return printf("deep candidate for a multi-tile ring\n"), 1;
+    return 0;
+}
+
+// The one-step kernel's tiles: cover L, owned cells a multiple of 32 when there
+// are several tiles, a one-word halo.
+static int check_onestep() {
+    const uint32_t Ls[] = {1, 31, 32, 8127, 8128, 8129, 16288, 100003, 1u << 30, 2147483647u};
+    for (uint32_t q = 1; q <= 2; ++q)
+        for (uint32_t L : Ls) {
+            uint32_t own, halo, nt;
+            onestep_geometry(L, q, &own, &halo, &nt);
+            if ((uint64_t)nt * own < L || (uint64_t)(nt - 1) * own >= L || halo != 32u ||
+                (nt > 1 && (own % 32u || own != 32u * (kOneStepThreads * q - 2u))))
+                return printf("onestep geometry: L %u q %u\n", L, q), 1;
+        }
+    return 0;
+}
+
 static int check_agent() {
     const uint32_t Ns[] = {1, 7, 8, 255, 256, 257, 1000, 65536, 67108864u};
     for (uint32_t cpl = 1; cpl <= 10; ++cpl)
@@ -73,7 +113,7 @@ static int check_agent() {
 }
 
 int main() {
-    if (check_kstep() || check_agent()) return 1;
+    if (check_kstep() || check_agent() || check_candidates() || check_onestep()) return 1;
     printf("ok\n");
     return 0;
 }
