@@ -244,7 +244,7 @@ const char* nasch_strerror(int status);
  *   t      the step's index (R depends on it); t <= 2^32 - 2.
  *   d_flux device uint64 (may be NULL): receives F(t).
  *   stream hipStream_t to run on (NULL = the null stream).
- * Asynchronous: enqueues the launches and returns.  The per-tile flux
+ * Asynchronous: enqueues the launches and returns.  The per-wave flux
  * partials are scratch allocated and freed on the stream (stream-ordered
  * allocation).  The caller owns every buffer.  Returns NASCH_EINVAL for bad
  * parameters, a NULL, misaligned or overlapping road, NASCH_ERANGE for
@@ -260,9 +260,10 @@ int nasch_grid_step_device(const uint8_t* d_in, uint8_t* d_out, uint64_t L, uint
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * step as nasch_grid_step_device, same arguments, layout, ownership and
  * errors, but it allocates nothing.  Its scratch (one uint32 flux partial per
- * tile of 8128 cells) is a static device array of 264212 words (about 1 MiB)
- * that each device the library runs on holds until the process ends; every L
- * the library accepts fits it (a larger tile count would be NASCH_EINVAL).
+ * block of four 1984-cell tiles, and the fold's per-block sums and counter) is
+ * a static device array of 270731 words (about 1 MiB) that each device the
+ * library runs on holds until the process ends; every L the library accepts
+ * fits it (a launch needing more would be NASCH_EINVAL).
  * All calls on one device share that array, so calls that overlap on one
  * device (different streams, or threads without ordering) race and must not
  * be issued; calls ordered on one stream are safe.  The array's contents

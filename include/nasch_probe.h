@@ -34,7 +34,11 @@ extern "C" {
 #define NASCH_PROBE_PERM    11u /* v_perm_b32: byte select from two words           */
 #define NASCH_PROBE_MUL_U24 12u /* v_mul_u32_u24: 24 x 24 -> low 32 bits             */
 #define NASCH_PROBE_ADD_U64 13u /* v_lshl_add_u64: 64-bit add (address arithmetic)   */
-#define NASCH_PROBE_KINDS   14u
+#define NASCH_PROBE_MIN     14u /* v_min_u32                                         */
+#define NASCH_PROBE_SUB     15u /* v_sub_u32                                         */
+#define NASCH_PROBE_CNDMASK 16u /* v_cndmask_b32: select by a lane mask              */
+#define NASCH_PROBE_AND_OR  17u /* v_and_or_b32: (a & b) | c                         */
+#define NASCH_PROBE_KINDS   18u
 
 typedef struct {
     double ms;                 /* device time of the timed launch (HIP events)          */

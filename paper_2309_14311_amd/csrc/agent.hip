@@ -160,35 +160,36 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
     uint32_t x[CPL], v[CPL];
     if ((uint64_t)first + CPL <= N) {
         if constexpr (CPL == 8) {
-            const uint4* p = reinterpret_cast<const uint4*>(xs + first);
-            const uint4 a = p[0], b = p[1];
+            const u32x4 a = *gmem(reinterpret_cast<const u32x4*>(xs + first));
+            const u32x4 b = *gmem(reinterpret_cast<const u32x4*>(xs + first + 4));
             x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
             x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
-            const uint2 vv = *reinterpret_cast<const uint2*>(vs + first);
+            typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+            const u32x2 vv = *gmem(reinterpret_cast<const u32x2*>(vs + first));
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 v[q] = (vv.x >> (8 * q)) & 0xFFu;
                 v[q + 4] = (vv.y >> (8 * q)) & 0xFFu;
             }
         } else if constexpr (CPL == 4) {
-            const uint4 a = *reinterpret_cast<const uint4*>(xs + first);
+            const u32x4 a = *gmem(reinterpret_cast<const u32x4*>(xs + first));
             x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-            const uint32_t vv = *reinterpret_cast<const uint32_t*>(vs + first);
+            const uint32_t vv = *gmem(reinterpret_cast<const uint32_t*>(vs + first));
 #pragma unroll
             for (int q = 0; q < 4; ++q) v[q] = (vv >> (8 * q)) & 0xFFu;
         } else {
 #pragma unroll
             for (int q = 0; q < CPL; ++q) {
-                x[q] = (uint32_t)xs[first + q];
-                v[q] = vs[first + q];
+                x[q] = (uint32_t)*gmem(xs + first + q);
+                v[q] = *gmem(vs + first + q);
             }
         }
     } else {
 #pragma unroll
         for (int q = 0; q < (int)CPL; ++q) {
             const uint32_t idx = (uint32_t)(((uint64_t)first + q) % N);
-            x[q] = (uint32_t)xs[idx];
-            v[q] = vs[idx];
+            x[q] = (uint32_t)*gmem(xs + idx);
+            v[q] = *gmem(vs + idx);
         }
     }
 
@@ -255,33 +256,33 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
     // write back the owned cars
     if (lane * CPL + CPL <= own_len) {
         if constexpr (CPL == 8) {
-            uint4* p = reinterpret_cast<uint4*>(xd + first);
-            p[0] = make_uint4(x[0], x[1], x[2], x[3]);
-            p[1] = make_uint4(x[4], x[5], x[6], x[7]);
+            *gmem(reinterpret_cast<u32x4*>(xd + first)) = u32x4{x[0], x[1], x[2], x[3]};
+            *gmem(reinterpret_cast<u32x4*>(xd + first + 4)) = u32x4{x[4], x[5], x[6], x[7]};
             uint32_t lo = 0, hi = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 lo |= v[q] << (8 * q);
                 hi |= v[q + 4] << (8 * q);
             }
-            *reinterpret_cast<uint2*>(vd + first) = make_uint2(lo, hi);
+            typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+            *gmem(reinterpret_cast<u32x2*>(vd + first)) = u32x2{lo, hi};
         } else if constexpr (CPL == 4) {
-            *reinterpret_cast<uint4*>(xd + first) = make_uint4(x[0], x[1], x[2], x[3]);
-            *reinterpret_cast<uint32_t*>(vd + first) =
+            *gmem(reinterpret_cast<u32x4*>(xd + first)) = u32x4{x[0], x[1], x[2], x[3]};
+            *gmem(reinterpret_cast<uint32_t*>(vd + first)) =
                 v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
         } else {
 #pragma unroll
             for (int q = 0; q < CPL; ++q) {
-                xd[first + q] = (int32_t)x[q];
-                vd[first + q] = (uint8_t)v[q];
+                *gmem(xd + first + q) = (int32_t)x[q];
+                *gmem(vd + first + q) = (uint8_t)v[q];
             }
         }
     } else {
 #pragma unroll
         for (int q = 0; q < (int)CPL; ++q) {
             if (lane * CPL + q < own_len) {
-                xd[first + q] = (int32_t)x[q];
-                vd[first + q] = (uint8_t)v[q];
+                *gmem(xd + first + q) = (int32_t)x[q];
+                *gmem(vd + first + q) = (uint8_t)v[q];
             }
         }
     }

@@ -1,7 +1,8 @@
 // device_noalloc.hip -- nasch_grid_step_device_noalloc: the device-buffer step
 // of device_api.hip for callers that must not allocate (code under HIP graph
 // capture, tight serving loops, harnesses that forbid hipMalloc).  Its only
-// scratch, the per-tile F(t) partials, lives in a file-scope device array
+// scratch, the per-block F(t) partials and the fold's stage and counter, lives
+// in a file-scope device array
 // instead of a stream-ordered allocation; the call itself allocates nothing.
 //
 // In host code `scratch` names a host-side stand-in, not device memory: its
@@ -20,15 +21,17 @@
 using namespace nasch;
 
 namespace {
-// Tiles of the largest ring (L = 2^31 - 1) at the one-step kernel's tile size:
-// the scratch holds one uint32 partial per tile, about 1 MiB per device.
-constexpr uint32_t kOwnPerTile = 32u * (kOneStepThreads * kOneStepQ - 2u);
-constexpr uint32_t kScratchTiles =
-    (uint32_t)((NASCH_MAX_L + kOwnPerTile - 1u) / kOwnPerTile);
+// The fold's counter and per-block sums, then one uint32 F(t) partial per block
+// of 4 tiles of 1984 cells, for the longest ring (L = 2^31 - 1): about 1 MiB.
+constexpr uint32_t kTileCells = 32u * (64u * kOneStepQ - 2u);
+constexpr uint32_t kMaxBlocks =
+    (uint32_t)(((NASCH_MAX_L + kTileCells - 1u) / kTileCells + 3u) / 4u);
+constexpr uint32_t kScratchWords = kFoldScratchWords + kMaxBlocks;
 }  // namespace
 
-// The scratch of every call on a device: one F(t) partial per tile.
-static __device__ __align__(256) uint32_t scratch[kScratchTiles];
+// The scratch of every call on a device: F(t) partials and the fold's counter,
+// which static storage starts at 0 and every fold leaves at 0.
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
 
 namespace {
 
@@ -64,11 +67,11 @@ int nasch_grid_step_device_noalloc(const uint8_t* d_in, uint8_t* d_out, uint64_t
     RingDesc R;
     int rc = describe_device_ring(d_in, d_out, L, vmax, p, seed, replica, t, &R);
     if (rc) return rc;
-    if (R.ntiles > kScratchTiles) return NASCH_EINVAL;   // beyond the static scratch
+    if (onestep_partials(R.ntiles) > kScratchWords) return NASCH_EINVAL;   // beyond the scratch
     uint32_t* partials = nullptr;
     hipError_t e = scratch_on_current_device(&partials);
     if (e == hipSuccess)
-        e = launch_grid_onestep_direct(R, R.ntiles, partials, (uint32_t)t,
+        e = launch_grid_onestep_direct(R, partials, (uint32_t)t,
                                        reinterpret_cast<unsigned long long*>(d_flux),
                                        (hipStream_t)stream);
     if (e != hipSuccess) {

@@ -164,7 +164,7 @@ struct GridEngine {
     }
 
     bool geometry_ok(uint32_t kk, uint32_t qq) const {
-        if (onestep) return kk == 1 && (qq == 1 || qq == 2);
+        if (onestep) return kk == 1 && qq == kOneStepQ && rings.size() == 1;
         uint32_t o, h, n;
         for (const RingDesc& r : rings)
             if (!kstep_geometry(r.L, r.vmax, kk, qq, &o, &h, &n)) return false;
@@ -209,7 +209,8 @@ struct GridEngine {
         ++version;
         hipError_t e = upload_rings(s);
         if (e != hipSuccess) return e;
-        const size_t np = items.size() * (size_t)kk;
+        size_t np = items.size() * (size_t)kk;
+        if (onestep && !rings.empty()) np = std::max<size_t>(np, onestep_partials(rings[0].ntiles));
         if (np > partials_cap) {
             if (d_partials) (void)hipFree(d_partials);
             d_partials = nullptr;
@@ -217,6 +218,10 @@ struct GridEngine {
             e = dev_alloc(&d_partials, np);
             if (e != hipSuccess) return e;
             partials_cap = np;
+            // the one-step fold's counter (and everything else) starts at 0
+            e = launch_fill_u8(reinterpret_cast<uint8_t*>(d_partials), np * sizeof(uint32_t), 0u,
+                               s);
+            if (e != hipSuccess) return e;
         }
         if (items.size() > d_items_cap) {
             if (d_items) (void)hipFree(d_items);
@@ -278,10 +283,15 @@ struct GridEngine {
         const uint32_t n = launches_for(T);
         for (uint32_t i = 0; i < n; ++i) {
             const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
+            if (onestep) {
+                // one ring; F(t) folded by the launch itself
+                hipError_t e = launch_grid_onestep(launch_vmax, rings[0].ntiles, d_rings,
+                                                   d_partials, n_log_rings != 0, d_clk, i, i, s);
+                if (e != hipSuccess) return e;
+                continue;
+            }
             hipError_t e =
-                onestep ? launch_grid_onestep(launch_vmax, q, d_rings, d_items,
-                                              (uint32_t)items.size(), d_partials, d_clk, i, i, s)
-                : io_bytes ? launch_grid_kstep_bytes(launch_vmax, launch_open, q, d_rings, d_items,
+                io_bytes ? launch_grid_kstep_bytes(launch_vmax, launch_open, q, d_rings, d_items,
                                                    (uint32_t)items.size(), d_partials, ki, d_clk,
                                                    i * k, i, s)
                          : launch_grid_kstep(launch_vmax, launch_open, q, d_rings, d_items,

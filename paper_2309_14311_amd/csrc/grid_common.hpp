@@ -244,7 +244,7 @@ __device__ __forceinline__ void gather_ring(const uint32_t* __restrict__ src, ui
         const uint32_t mask = run >= 32u ? 0xFFFFFFFFu : ((1u << run) - 1u);
         const uint32_t w = pos >> 5;
 #pragma unroll
-        for (int m = 0; m <= VMAX; ++m) T[m] |= ((src[(size_t)m * nw + w] >> off) & mask) << i;
+        for (int m = 0; m <= VMAX; ++m) T[m] |= ((*gmem(src + (size_t)m * nw + w) >> off) & mask) << i;
         i += run;
         pos += run;
         if (pos >= L) pos = 0;
@@ -256,8 +256,8 @@ __device__ __forceinline__ void gather_ring(const uint32_t* __restrict__ src, ui
 
 // The 32 bytes of an aligned 32-cell word (16-byte loads).
 __device__ __forceinline__ void load_bytes32(const uint8_t* __restrict__ p, uint32_t (&d)[8]) {
-    const uint4 a = *reinterpret_cast<const uint4*>(p);
-    const uint4 b = *reinterpret_cast<const uint4*>(p + 16);
+    const u32x4 a = *gmem(reinterpret_cast<const u32x4*>(p));
+    const u32x4 b = *gmem(reinterpret_cast<const u32x4*>(p + 16));
     d[0] = a.x; d[1] = a.y; d[2] = a.z; d[3] = a.w;
     d[4] = b.x; d[5] = b.y; d[6] = b.z; d[7] = b.w;
 }
@@ -272,7 +272,7 @@ __device__ __forceinline__ void gather_bytes_ring(const uint8_t* __restrict__ sr
         uint32_t w = 0u;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            w |= (uint32_t)src[pos] << (8 * b);
+            w |= (uint32_t)*gmem(src + pos) << (8 * b);
             pos = pos + 1u == L ? 0u : pos + 1u;
         }
         d[i] = w;
@@ -293,7 +293,7 @@ __device__ __forceinline__ void load_bytes_open(const uint8_t* __restrict__ src,
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const uint32_t c = p0 + 4u * i + b;
-            w |= (uint32_t)(c < L ? src[c] : (uint8_t)kEmpty) << (8 * b);
+            w |= (uint32_t)(c < L ? *gmem(src + c) : (uint8_t)kEmpty) << (8 * b);
         }
         d[i] = w;
     }
@@ -304,13 +304,13 @@ __device__ __forceinline__ void load_bytes_open(const uint8_t* __restrict__ src,
 __device__ __forceinline__ void store_bytes(uint8_t* __restrict__ dst, uint32_t c0, uint32_t own,
                                             const uint32_t (&d)[8]) {
     if (own == 0xFFFFFFFFu) {
-        *reinterpret_cast<uint4*>(dst + c0) = make_uint4(d[0], d[1], d[2], d[3]);
-        *reinterpret_cast<uint4*>(dst + c0 + 16) = make_uint4(d[4], d[5], d[6], d[7]);
+        *gmem(reinterpret_cast<u32x4*>(dst + c0)) = u32x4{d[0], d[1], d[2], d[3]};
+        *gmem(reinterpret_cast<u32x4*>(dst + c0 + 16)) = u32x4{d[4], d[5], d[6], d[7]};
         return;
     }
 #pragma unroll
     for (int i = 0; i < 32; ++i)
-        if ((own >> i) & 1u) dst[c0 + i] = (uint8_t)(d[i >> 2] >> (8 * (i & 3)));
+        if ((own >> i) & 1u) *gmem(dst + c0 + i) = (uint8_t)(d[i >> 2] >> (8 * (i & 3)));
 }
 
 }  // namespace grid

@@ -147,7 +147,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                 const uint32_t v = valid & keep[q];
                 const uint32_t w = (uint32_t)p0 >> 5;
 #pragma unroll
-                for (int m = 0; m <= VMAX; ++m) T[q][m] = src[(size_t)m * nw + w] & v;
+                for (int m = 0; m <= VMAX; ++m) T[q][m] = *gmem(src + (size_t)m * nw + w) & v;
             } else {
 #pragma unroll
                 for (int m = 0; m <= VMAX; ++m) T[q][m] = 0u;
@@ -155,7 +155,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
         } else if (aligned[q]) {
             const uint32_t w = x0 >> 5;
 #pragma unroll
-            for (int m = 0; m <= VMAX; ++m) T[q][m] = src[(size_t)m * nw + w] & valid;
+            for (int m = 0; m <= VMAX; ++m) T[q][m] = *gmem(src + (size_t)m * nw + w) & valid;
         } else {
             gather_ring<VMAX>(src, nw, L, x0, T[q]);
 #pragma unroll
@@ -304,7 +304,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
             store_bytes(R.buf[par ^ 1u], 32u * w, own[q], d);
         } else {
 #pragma unroll
-            for (int m = 0; m <= VMAX; ++m) dst[(size_t)m * nw + w] = T[q][m] & own[q];
+            for (int m = 0; m <= VMAX; ++m) *gmem(dst + (size_t)m * nw + w) = T[q][m] & own[q];
         }
     }
 }

@@ -8,14 +8,21 @@
 // same rules as the k-step kernel, see grid_kstep.hip) and one Philox call for
 // the top nibble of R of the word's 32 cars.
 //
-// Layout.  A block of four waves handles one tile: a segment of 256 Q
-// consecutive 32-cell words, lane l of wave w holding words (64 w + l) Q ..
-// +Q-1.  Segment word 0 and the last word are a one-word halo: the first only
-// supplies the cars that drive into the tile (at most vmax <= 8 cells), the
-// last only the occupancy that the tile's front cars see.  The tile owns the
-// 32 (256 Q - 2) cells in between, so the halo re-reads 2 words of every 256 Q.
-// Inside a wave neighbouring words come through DPP lane shifts; the waves of a
-// block swap their edge words through LDS (two barriers per step).
+// Tiles.  A wave handles a tile as a segment of 64 Q consecutive 32-cell
+// words, lane l holding words l Q .. l Q + Q - 1.  Segment word 0 and the last
+// word are a one-word halo: the first only supplies the cars that drive into
+// the tile (at most vmax <= 8 cells), the last only the occupancy that the
+// tile's front cars see; the tile owns the 32 (64 Q - 2) cells in between.
+// Neighbouring words come through DPP lane shifts, so the waves never wait
+// for each other.
+//
+// Streaming.  One tile per wave and one launch over all tiles: on this GPU a
+// launch whose waves each move one tile and exit streams faster (5.8 TB/s for
+// the bare copy of this access pattern) than persistent waves that loop over
+// tiles (5.0 - 5.3 TB/s, with or without prefetching the next tile).  The 4
+// waves of a block take 4 consecutive tiles and add their F(t) into one
+// partial; blocks dealt to one XCD (the 8 XCDs take blocks in turn) take
+// consecutive tiles.  A fold kernel sums the partials.
 //
 // Segment cell i is ring cell (own_start - 32 + i) mod L.  A tile whose
 // segment lies inside [0, L) is the common case and takes aligned 16-byte
@@ -23,11 +30,7 @@
 // runs past the end of the ring and every ring shorter than a segment read the
 // segment cell by cell where it crosses the end (the periodic images of a
 // short ring are exact by periodicity) and draw rule 3 across block edges.
-// The branch is uniform over the block.
-//
-// Tiles map to blocks so that the blocks dispatched to one XCD (blocks are
-// handed to the 8 XCDs in turn) take consecutive tiles, whose shared halo words
-// then meet in the same L2.
+// The branch is uniform over the wave.
 #include "grid_common.hpp"
 #include "launchers.hpp"
 
@@ -37,7 +40,8 @@ using namespace grid;
 
 namespace {
 
-constexpr uint32_t kOsWaves = kOneStepThreads / 64u;
+constexpr uint32_t kOsWaves = kOneStepThreads / 64u;   // independent waves per block
+
 
 // Item of block b when n blocks are dealt to the 8 XCDs in turn: XCD x gets the
 // x-th contiguous run of items (runs of ceil(n/8) items first, then floor(n/8)).
@@ -47,72 +51,72 @@ __device__ __forceinline__ uint32_t xcd_item(uint32_t b, uint32_t n) {
     return xcd < rem ? xcd * (per + 1u) + idx : rem * (per + 1u) + (xcd - rem) * per + idx;
 }
 
-template <int Q>
-struct OneStepLds {
-    RefineLds<Q> ref[kOsWaves];   // tied draws, per wave
-    uint32_t occ[kOsWaves];       // occupancy of each wave's first word
-    uint32_t eq[kOsWaves][8];     // cars with v3 == j (j = 1..8) of each wave's last word
-    uint32_t flux[kOsWaves];
+// Where a tile's segment lies on the ring.
+struct OsTile {
+    uint32_t own_start, own_len;
+    uint32_t s0;       // ring cell of segment cell 0
+    bool inside;       // the segment lies inside [0, L): aligned, no reduction mod L
 };
 
-}  // namespace
+template <int Q>
+__device__ __forceinline__ OsTile os_tile(const RingDesc& R, uint32_t tile) {
+    OsTile g;
+    const uint32_t L = R.L;
+    g.own_start = tile * R.own;
+    g.own_len = min(R.own, L - g.own_start);
+    g.s0 = (g.own_start + L - (32u % L)) % L;
+    g.inside = g.own_start >= 32u && g.own_start - 32u + 32u * 64u * Q <= L;
+    return g;
+}
 
-// Step t of tile `tile` of ring R, from R.buf[par] to R.buf[par ^ 1].  The
-// block's F(t) goes to *partial (if not null) and, from the warm-up on, into
-// R.flux_acc.
+// Ring cell of the first cell of segment word j (< 64 Q).
+__device__ __forceinline__ uint32_t os_word_cell(const OsTile& g, uint32_t j, uint32_t L) {
+    const uint32_t x0 = g.s0 + 32u * j;   // s0 < 2^31, 32 j < 2^14: no overflow
+    return g.inside ? x0 : x0 % L;
+}
+
+// The bytes of the lane's Q words of a tile.
+template <int Q>
+__device__ __forceinline__ void os_load(const RingDesc& R, const uint8_t* __restrict__ src,
+                                        uint32_t tile, uint32_t lane, uint32_t (&d)[Q][8]) {
+    const OsTile g = os_tile<Q>(R, tile);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t x0 = os_word_cell(g, lane * Q + q, R.L);
+        if (g.inside || ((x0 & 31u) == 0u && x0 + 32u <= R.L)) load_bytes32(src + x0, d[q]);
+        else gather_bytes_ring(src, R.L, x0, d[q]);
+    }
+}
+
+// Step t of one tile from the bytes d of the lane's words: writes the owned
+// cells to dst and returns the lane's share of F(t) (owned cars only).
 template <int VMAX, int Q>
-__device__ __forceinline__ void onestep_tile(const RingDesc& R, uint32_t tile, uint32_t t,
-                                             uint32_t par, uint32_t* __restrict__ partial,
-                                             OneStepLds<Q>& lds) {
-    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t lane = threadIdx.x & 63u;
+__device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restrict__ dst,
+                                            uint32_t tile, uint32_t t, bool run, uint32_t lane,
+                                            const uint32_t (&d)[Q][8], RefineLds<Q>& rl) {
     const uint32_t L = R.L;
     const SlowParams sp = R.sp;
-    const uint8_t* __restrict__ src = R.buf[par];
-    uint8_t* __restrict__ dst = R.buf[par ^ 1u];
-    const uint32_t own_start = tile * R.own;
-    const uint32_t own_len = min(R.own, L - own_start);
-    const uint32_t s0 = (own_start + L - (32u % L)) % L;   // ring cell of segment cell 0
-    // the segment lies inside [0, L): aligned words, no reduction mod L
-    const bool inside = own_start >= 32u && own_start - 32u + 32u * kOneStepThreads * Q <= L;
-    const bool run = t < R.t_end;   // no step at or past t_end (the state is copied)
-
+    const OsTile g = os_tile<Q>(R, tile);
     uint32_t T[Q][VMAX + 1];
     uint32_t xw[Q];     // ring cell of each word's first cell
     bool aligned[Q];    // the word is one aligned 32-cell block of the ring
     uint32_t own[Q];    // owned cells of each word
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const uint32_t j = (wv * 64u + lane) * Q + q;
-        uint32_t x0 = s0 + 32u * j;   // s0 < 2^31, 32 j < 2^15: no overflow
-        uint32_t d[8];
-        if (inside) {
-            aligned[q] = true;
-            load_bytes32(src + x0, d);
-        } else {
-            x0 %= L;
-            aligned[q] = (x0 & 31u) == 0u && x0 + 32u <= L;
-            if (aligned[q]) load_bytes32(src + x0, d);
-            else gather_bytes_ring(src, L, x0, d);
-        }
-        xw[q] = x0;
-        bytes_to_thermo<VMAX>(d, T[q]);
-        const uint32_t lo = max(32u, 32u * j), hi = min(32u + own_len, 32u * j + 32u);
+        const uint32_t j = lane * Q + q;
+        xw[q] = os_word_cell(g, j, L);
+        aligned[q] = g.inside || ((xw[q] & 31u) == 0u && xw[q] + 32u <= L);
+        bytes_to_thermo<VMAX>(d[q], T[q]);
+        const uint32_t lo = max(32u, 32u * j), hi = min(32u + g.own_len, 32u * j + 32u);
         own[q] = lo < hi ? bit_range(lo - 32u * j, hi - 32u * j) : 0u;
     }
-    RefineLds<Q>& rl = lds.ref[wv];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) rl.slow[lane * Q + q] = 0u;
-    if (lane == 0u) lds.occ[wv] = T[0][0];
-    __syncthreads();
 
     uint32_t fl = 0u;
     if constexpr (VMAX > 0) {
         if (run) {
-            // occupancy of the word after the lane's last one
-            const uint32_t occ_wave = lds.occ[wv + 1u < kOsWaves ? wv + 1u : wv];
-            uint32_t occ_next = from_next_lane(T[0][0]);
-            if (lane == 63u) occ_next = wv + 1u < kOsWaves ? occ_wave : 0u;
+            // occupancy of the word after the lane's last one (lane 63's is the
+            // halo word's, whose own results are not kept)
+            const uint32_t occ_next = from_next_lane(T[0][0]);
             uint32_t T2[Q][VMAX + 2];
             uint32_t S[Q], U[Q], moving[Q];
 #pragma unroll
@@ -121,9 +125,9 @@ __device__ __forceinline__ void onestep_tile(const RingDesc& R, uint32_t tile, u
                 const uint32_t nxt = (q + 1 < Q) ? T[(q + 1) % Q][0] : occ_next;
                 uint32_t A = 0u;
 #pragma unroll
-                for (int g = 1; g <= VMAX; ++g) {
-                    A |= __builtin_amdgcn_alignbit(nxt, occ, g);   // car in cell i+g
-                    T2[q][g] = T[q][g - 1] & ~A;                    // rules 1 and 2
+                for (int gg = 1; gg <= VMAX; ++gg) {
+                    A |= __builtin_amdgcn_alignbit(nxt, occ, gg);   // car in cell i+gg
+                    T2[q][gg] = T[q][gg - 1] & ~A;                   // rules 1 and 2
                 }
                 T2[q][VMAX + 1] = 0u;
                 moving[q] = T2[q][1];
@@ -133,14 +137,11 @@ __device__ __forceinline__ void onestep_tile(const RingDesc& R, uint32_t tile, u
             // rule 3: the top nibble of R of 32 cars per Philox call, then the
             // wave's tied cars
             if (sp.thr != 0u) {
-                const uint32_t draw_mode = inside ? kDrawAligned : kDrawGeneric;
-                slow_hi<Q>(moving, xw, aligned, draw_mode, t, L, sp, S, U);
+                slow_hi<Q>(moving, xw, aligned, g.inside ? kDrawAligned : kDrawGeneric, t, L, sp,
+                           S, U);
             }
-            if ((sp.thr & 0x0FFFFFFFu) != 0u) {
-                uint32_t seg0 = s0 + 2048u * Q * wv;   // ring cell of the wave's first cell
-                if (!inside) seg0 %= L;
-                slow_lo_wave<Q>(S, U, xw, L, seg0, inside ? kXNone : kXMod, t, sp, rl, lane);
-            }
+            if ((sp.thr & 0x0FFFFFFFu) != 0u)
+                slow_lo_wave<Q>(S, U, xw, L, g.s0, g.inside ? kXNone : kXMod, t, sp, rl, lane);
             uint32_t Eq[Q][VMAX + 1];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
@@ -155,19 +156,11 @@ __device__ __forceinline__ void onestep_tile(const RingDesc& R, uint32_t tile, u
 #pragma unroll
                 for (int j = 0; j <= VMAX; ++j) Eq[q][j] = T3[j] & ~T3[j + 1];
             }
-            if (lane == 63u) {
-#pragma unroll
-                for (int j = 1; j <= VMAX; ++j) lds.eq[wv][j - 1] = Eq[Q - 1][j];
-            }
-            __syncthreads();
-            // rule 4: cars with v3 == j move j cells right
+            // rule 4: cars with v3 == j move j cells right (lane 0's incoming
+            // cars are unknown: its word is the halo)
             uint32_t prevEq[VMAX + 1];
 #pragma unroll
-            for (int j = 1; j <= VMAX; ++j) {
-                const uint32_t from_wave = wv > 0u ? lds.eq[wv - 1u][j - 1] : 0u;
-                prevEq[j] = from_prev_lane(Eq[Q - 1][j]);
-                if (lane == 0u) prevEq[j] = from_wave;
-            }
+            for (int j = 1; j <= VMAX; ++j) prevEq[j] = from_prev_lane(Eq[Q - 1][j]);
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 uint32_t accm = 0u;
@@ -182,141 +175,185 @@ __device__ __forceinline__ void onestep_tile(const RingDesc& R, uint32_t tile, u
         }
     }
 
-    // F(t) of the tile: one partial per block, folded per ring by the fold kernel
-    const uint32_t wtot = wave_total(fl);
-    if (lane == 0u) lds.flux[wv] = wtot;
-    __syncthreads();
-    if (threadIdx.x == 0u) {
-        uint32_t total = 0u;
-#pragma unroll
-        for (uint32_t w = 0; w < kOsWaves; ++w) total += lds.flux[w];
-        if (partial) *partial = total;
-        if (R.flux_acc && run && (uint64_t)t >= R.warmup && total)
-            atomicAdd(R.flux_acc, (unsigned long long)total);
-    }
-
     // store the owned cells (they lie in [0, L) and start on a word boundary)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         if (own[q] == 0u) continue;
-        uint32_t d[8];
-        thermo_to_bytes<VMAX>(T[q], d);
-        store_bytes(dst, xw[q], own[q], d);
+        uint32_t dd[8];
+        thermo_to_bytes<VMAX>(T[q], dd);
+        store_bytes(dst, xw[q], own[q], dd);
+    }
+    return fl;
+}
+
+// Step t of tile 4 b + wave of ring R (b: the block's tile group), from
+// R.buf[par] to R.buf[par ^ 1].  The block's F(t) goes to *partial (if not
+// null) and, from the warm-up on, into R.flux_acc.
+template <int VMAX, int Q>
+__device__ __forceinline__ void os_block(const RingDesc& R, uint32_t b, uint32_t t, uint32_t par,
+                                         uint32_t* __restrict__ partial, RefineLds<Q>* ref,
+                                         uint32_t* s_flux) {
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t tile = b * kOsWaves + wib;
+    const bool run = t < R.t_end;   // no step at or past t_end (the state is copied)
+    uint32_t fl = 0u;
+    if (tile < R.ntiles) {
+        RefineLds<Q>& rl = ref[wib];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) rl.slow[lane * Q + q] = 0u;
+        uint32_t d[Q][8];
+        os_load<Q>(R, R.buf[par], tile, lane, d);
+        fl = os_step<VMAX, Q>(R, R.buf[par ^ 1u], tile, t, run, lane, d, rl);
+    }
+    const uint32_t wtot = wave_total(fl);
+    if (lane == 0u) s_flux[wib] = wtot;
+    __syncthreads();
+    if (threadIdx.x == 0u) {
+        uint32_t total = 0u;
+#pragma unroll
+        for (uint32_t w = 0; w < kOsWaves; ++w) total += s_flux[w];
+        if (partial) *partial = total;
+        if (R.flux_acc && run && (uint64_t)t >= R.warmup && total)
+            atomicAdd(R.flux_acc, (unsigned long long)total);
     }
 }
 
-// One step of every item (ring, tile) of a launch sequence: step and buffer
-// parity from the device clock, F(t) partials per item for the fold kernel.
+}  // namespace
+
+// One step of a ring (RingDesc at `ring`, step and buffer parity from the
+// device clock), F(t) partials of every block in partials[block].
 template <int VMAX, int Q>
 __global__ __launch_bounds__(kOneStepThreads) void grid_onestep_kernel(
-    const RingDesc* __restrict__ rings, const TileItem* __restrict__ items, uint32_t n_items,
-    uint32_t* __restrict__ partials, const Clock* __restrict__ clk, uint32_t s_off,
-    uint32_t launch_idx) {
-    __shared__ OneStepLds<Q> lds;
-    const uint32_t item = xcd_item(blockIdx.x, n_items);
-    const TileItem it = items[item];
-    const RingDesc& R = rings[it.ring];
+    const RingDesc* __restrict__ ring, uint32_t* __restrict__ partials,
+    const Clock* __restrict__ clk, uint32_t s_off, uint32_t launch_idx) {
+    __shared__ RefineLds<Q> s_ref[kOsWaves];
+    __shared__ uint32_t s_flux[kOsWaves];
+    const uint32_t b = xcd_item(blockIdx.x, gridDim.x);
+    const RingDesc& R = *ring;
     const uint32_t t = clk->t + R.t + s_off;
     const uint32_t par = (clk->parity + R.parity + launch_idx) & 1u;
-    onestep_tile<VMAX, Q>(R, it.tile, t, par, R.flux_log ? partials + item : nullptr, lds);
+    os_block<VMAX, Q>(R, b, t, par, R.flux_log ? partials + b : nullptr, s_ref, s_flux);
 }
 
-// One step t of every tile of one ring described by value (buf[0] is read,
-// buf[1] written): the launch of the stateless device-buffer entry points.
-// partials[tile] receives each tile's F(t).
+// One step t of a ring described by value (buf[0] is read, buf[1] written):
+// the launch of the stateless device-buffer entry points.
 template <int VMAX, int Q>
 __global__ __launch_bounds__(kOneStepThreads) void grid_onestep_direct_kernel(
-    const RingDesc R, uint32_t ntiles, uint32_t* __restrict__ partials, uint32_t t) {
-    __shared__ OneStepLds<Q> lds;
-    const uint32_t tile = xcd_item(blockIdx.x, ntiles);
-    onestep_tile<VMAX, Q>(R, tile, t, 0u, partials + tile, lds);
+    const RingDesc R, uint32_t* __restrict__ partials, uint32_t t) {
+    __shared__ RefineLds<Q> s_ref[kOsWaves];
+    __shared__ uint32_t s_flux[kOsWaves];
+    const uint32_t b = xcd_item(blockIdx.x, gridDim.x);
+    os_block<VMAX, Q>(R, b, t, 0u, partials + b, s_ref, s_flux);
 }
 
-// *out = the sum of n uint32 partials (one block).
-__global__ __launch_bounds__(256) void sum_partials_kernel(const uint32_t* __restrict__ partials,
-                                                           uint32_t n,
-                                                           unsigned long long* __restrict__ out) {
+// F(t) = the sum of n uint32 partials, into *out or into the ring's flux log at
+// the launch's step (when ring is given).  kFoldBlocks blocks each add a
+// contiguous range and store their sum in stage[block]; the last block to
+// finish (a device-scope counter) adds the stage, writes F(t) and resets the
+// counter for the next launch.
+__global__ __launch_bounds__(256) void fold_partials_kernel(const uint32_t* __restrict__ partials,
+                                                            uint32_t n,
+                                                            unsigned long long* __restrict__ stage,
+                                                            uint32_t* __restrict__ counter,
+                                                            unsigned long long* __restrict__ out,
+                                                            const RingDesc* __restrict__ ring,
+                                                            const Clock* __restrict__ clk,
+                                                            uint32_t s_off) {
     __shared__ unsigned long long s[4];
+    __shared__ bool last;
+    const uint32_t per = (n + gridDim.x - 1u) / gridDim.x;
+    const uint32_t lo = min(blockIdx.x * per, n), hi = min(lo + per, n);
     unsigned long long acc = 0;
-    for (uint32_t i = threadIdx.x; i < n; i += 256u) acc += partials[i];
-    // F(t) can pass 2^32 (up to 2^31 cars of v <= 8), so a lane's sum (below
-    // 2^27) is added across the wave as its low 16 bits and the rest separately
-    const uint32_t lo = wave_total((uint32_t)(acc & 0xFFFFu));
-    const uint32_t hi = wave_total((uint32_t)(acc >> 16));
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256u) acc += partials[i];
+    // a block's range sums to below 2^32 only per lane; add the low 16 bits and
+    // the rest of each lane's sum separately across the wave
+    const uint32_t wl = wave_total((uint32_t)(acc & 0xFFFFu));
+    const uint32_t wh = wave_total((uint32_t)(acc >> 16));
     if ((threadIdx.x & 63u) == 0u)
-        s[threadIdx.x >> 6] = (unsigned long long)lo + ((unsigned long long)hi << 16);
+        s[threadIdx.x >> 6] = (unsigned long long)wl + ((unsigned long long)wh << 16);
     __syncthreads();
-    if (threadIdx.x == 0u) *out = s[0] + s[1] + s[2] + s[3];
+    if (threadIdx.x == 0u) {
+        stage[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+        __threadfence();
+        last = atomicAdd(counter, 1u) == gridDim.x - 1u;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x == 0u) {
+        unsigned long long total = 0;
+        for (uint32_t i = 0; i < gridDim.x; ++i)
+            total += __hip_atomic_load(&stage[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ring) {
+            const uint64_t t = (uint64_t)clk->t + ring->t + s_off;
+            ring->flux_log[t - ring->log_t0] = total;
+        } else {
+            *out = total;
+        }
+    }
 }
 
 namespace {
-template <int Q>
-hipError_t launch_os_q(uint32_t vmax, dim3 grid, hipStream_t s, const RingDesc* rings,
-                       const TileItem* items, uint32_t n_items, uint32_t* partials,
-                       const Clock* clk, uint32_t s_off, uint32_t launch_idx) {
-#define NASCH_ONESTEP_CASE(V)                                                                   \
-    case V:                                                                                     \
-        NASCH_LAUNCH((grid_onestep_kernel<V, Q>), grid, dim3(kOneStepThreads), 0, s, rings,     \
-                     items, n_items, partials, clk, s_off, launch_idx);                         \
-        break;
-    switch (vmax) {
-        NASCH_ONESTEP_CASE(0)
-        NASCH_ONESTEP_CASE(1)
-        NASCH_ONESTEP_CASE(2)
-        NASCH_ONESTEP_CASE(3)
-        NASCH_ONESTEP_CASE(4)
-        NASCH_ONESTEP_CASE(5)
-        NASCH_ONESTEP_CASE(6)
-        NASCH_ONESTEP_CASE(7)
-        NASCH_ONESTEP_CASE(8)
-        default:
-            return hipErrorInvalidValue;
+
+// Blocks of a one-step launch: one tile per wave.
+uint32_t os_blocks(uint32_t ntiles) { return std::max(1u, (ntiles + kOsWaves - 1u) / kOsWaves); }
+
+#define NASCH_OS_VMAX_SWITCH(KERNEL, Q, ...)                                                   \
+    switch (vmax) {                                                                            \
+        case 0: NASCH_LAUNCH((KERNEL<0, Q>), __VA_ARGS__); break;                               \
+        case 1: NASCH_LAUNCH((KERNEL<1, Q>), __VA_ARGS__); break;                               \
+        case 2: NASCH_LAUNCH((KERNEL<2, Q>), __VA_ARGS__); break;                               \
+        case 3: NASCH_LAUNCH((KERNEL<3, Q>), __VA_ARGS__); break;                               \
+        case 4: NASCH_LAUNCH((KERNEL<4, Q>), __VA_ARGS__); break;                               \
+        case 5: NASCH_LAUNCH((KERNEL<5, Q>), __VA_ARGS__); break;                               \
+        case 6: NASCH_LAUNCH((KERNEL<6, Q>), __VA_ARGS__); break;                               \
+        case 7: NASCH_LAUNCH((KERNEL<7, Q>), __VA_ARGS__); break;                               \
+        case 8: NASCH_LAUNCH((KERNEL<8, Q>), __VA_ARGS__); break;                               \
+        default: return hipErrorInvalidValue;                                                  \
     }
-#undef NASCH_ONESTEP_CASE
+
+// The scratch of a one-step launch: word 0 the fold's counter, words 2 ..
+// 2 kFoldBlocks + 1 its per-block sums, then one partial per block of tiles.
+// The counter has a fixed place so that it stays 0 between launches of any size.
+hipError_t fold(uint32_t* scratch, uint32_t n, unsigned long long* out, const RingDesc* ring,
+                const Clock* clk, uint32_t s_off, hipStream_t s) {
+    NASCH_LAUNCH(fold_partials_kernel, dim3(kFoldBlocks), dim3(256), 0, s,
+                 scratch + kFoldScratchWords, n,
+                 reinterpret_cast<unsigned long long*>(scratch + 2), scratch, out, ring, clk,
+                 s_off);
     return hipGetLastError();
 }
+
 }  // namespace
 
-hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t ntiles, uint32_t* partials,
-                                      uint32_t t, unsigned long long* flux, hipStream_t s) {
+uint32_t onestep_partials(uint32_t ntiles) { return kFoldScratchWords + os_blocks(ntiles); }
+
+hipError_t launch_grid_onestep(uint32_t vmax, uint32_t ntiles, const RingDesc* ring,
+                               uint32_t* partials, bool log, const Clock* clk, uint32_t s_off,
+                               uint32_t launch_idx, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
-    const dim3 grid(ntiles);
-#define NASCH_ONESTEP_DIRECT_CASE(V)                                                            \
-    case V:                                                                                     \
-        NASCH_LAUNCH((grid_onestep_direct_kernel<V, kOneStepQ>), grid, dim3(kOneStepThreads),   \
-                     0, s, R, ntiles, partials, t);                                             \
-        break;
-    switch (R.vmax) {
-        NASCH_ONESTEP_DIRECT_CASE(0)
-        NASCH_ONESTEP_DIRECT_CASE(1)
-        NASCH_ONESTEP_DIRECT_CASE(2)
-        NASCH_ONESTEP_DIRECT_CASE(3)
-        NASCH_ONESTEP_DIRECT_CASE(4)
-        NASCH_ONESTEP_DIRECT_CASE(5)
-        NASCH_ONESTEP_DIRECT_CASE(6)
-        NASCH_ONESTEP_DIRECT_CASE(7)
-        NASCH_ONESTEP_DIRECT_CASE(8)
-        default:
-            return hipErrorInvalidValue;
-    }
-#undef NASCH_ONESTEP_DIRECT_CASE
+    const uint32_t nb = os_blocks(ntiles);
+    NASCH_OS_VMAX_SWITCH(grid_onestep_kernel, kOneStepQ, dim3(nb), dim3(kOneStepThreads), 0, s,
+                         ring, partials + kFoldScratchWords, clk, s_off, launch_idx)
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !flux) return e;
-    NASCH_LAUNCH(sum_partials_kernel, dim3(1), dim3(256), 0, s, partials, ntiles, flux);
-    return hipGetLastError();
+    if (e != hipSuccess || !log) return e;
+    return fold(partials, nb, nullptr, ring, clk, s_off, s);
 }
 
-hipError_t launch_grid_onestep(uint32_t vmax, uint32_t q, const RingDesc* rings,
-                               const TileItem* items, uint32_t n_items, uint32_t* partials,
-                               const Clock* clk, uint32_t s_off, uint32_t launch_idx,
-                               hipStream_t s) {
-    if (n_items == 0) return hipSuccess;
-    const dim3 grid(n_items);
-    switch (q) {
-        case 1: return launch_os_q<1>(vmax, grid, s, rings, items, n_items, partials, clk, s_off, launch_idx);
-        case 2: return launch_os_q<2>(vmax, grid, s, rings, items, n_items, partials, clk, s_off, launch_idx);
-        default: return hipErrorInvalidValue;
-    }
+hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t* partials, uint32_t t,
+                                      unsigned long long* flux, hipStream_t s) {
+    if (R.ntiles == 0) return hipSuccess;
+    const uint32_t vmax = R.vmax;
+    const uint32_t nb = os_blocks(R.ntiles);
+    NASCH_OS_VMAX_SWITCH(grid_onestep_direct_kernel, kOneStepQ, dim3(nb), dim3(kOneStepThreads),
+                         0, s, R, partials + kFoldScratchWords, t)
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !flux) return e;
+    return fold(partials, nb, flux, nullptr, nullptr, 0u, s);
 }
+
+#undef NASCH_OS_VMAX_SWITCH
 
 }  // namespace nasch

@@ -75,16 +75,20 @@ hipError_t launch_grid_kstep_bytes(uint32_t vmax, bool open, uint32_t q, const R
                                    uint32_t launch_idx, hipStream_t s);
 
 // ---- grid, one step per launch on the byte form (grid_onestep.hip) -----------
-// A block of kOneStepThreads lanes handles a segment of kOneStepThreads * q
-// words: one halo word at each end and the owned words in between.
+// A wave handles a tile of 64 q words: a halo word at each end and the owned
+// words in between; blocks of kOneStepThreads lanes hold independent waves.
 constexpr uint32_t kOneStepThreads = 256;
 // Words per lane of the one-step kernel.
 constexpr uint32_t kOneStepQ = 1;
+// The fold of a launch's F(t) partials: blocks, and the scratch words it needs
+// ahead of the partials (a counter that must start at 0, and a uint64 per block).
+constexpr uint32_t kFoldBlocks = 64;
+constexpr uint32_t kFoldScratchWords = 2u + 2u * kFoldBlocks;
 // Tile geometry of the one-step kernel: owned cells per tile (a ring that fits
 // one tile is one tile owning all L cells), the one-word halo, tile count.
 inline void onestep_geometry(uint32_t L, uint32_t q, uint32_t* own, uint32_t* halo,
                              uint32_t* ntiles) {
-    const uint32_t own_full = 32u * (kOneStepThreads * q - 2u);
+    const uint32_t own_full = 32u * (64u * q - 2u);
     if (L <= own_full) {
         *own = L;
         *ntiles = 1;
@@ -94,18 +98,23 @@ inline void onestep_geometry(uint32_t L, uint32_t q, uint32_t* own, uint32_t* ha
     }
     *halo = 32u;
 }
-// One step of every tile of rings of one vmax (ring roads only; q = 1 or 2):
-// reads ring.buf[parity], writes the other buffer, F(t) partial per tile in
-// partials[item] (folded like the k-step kernel's with k = 1).
+// Scratch words of a one-step launch over ntiles tiles: the fold's counter
+// (word 0, which must be 0 when the scratch is first used; every fold leaves
+// it 0) and per-block sums, then one F(t) partial per block of tiles.
+uint32_t onestep_partials(uint32_t ntiles);
+// One step of the ring at `ring` (geometry from onestep_geometry with q =
+// kOneStepQ, ntiles tiles): reads ring.buf[parity], writes the other buffer;
+// with `log`, F(t) goes to the ring's flux log (scratch `partials` of
+// onestep_partials(ntiles) words in between).  Ring roads only.
+hipError_t launch_grid_onestep(uint32_t vmax, uint32_t ntiles, const RingDesc* ring,
+                               uint32_t* partials, bool log, const Clock* clk, uint32_t s_off,
+                               uint32_t launch_idx, hipStream_t s);
 // One step t of a single ring given by value: reads R.buf[0], writes R.buf[1]
-// (R.own from onestep_geometry with q = kOneStepQ, R.flux_acc null), tile F(t)
-// partials in partials[ntiles], then *flux = their sum when flux is not null.
-hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t ntiles, uint32_t* partials,
-                                      uint32_t t, unsigned long long* flux, hipStream_t s);
-hipError_t launch_grid_onestep(uint32_t vmax, uint32_t q, const RingDesc* rings,
-                               const TileItem* items, uint32_t n_items, uint32_t* partials,
-                               const Clock* clk, uint32_t s_off, uint32_t launch_idx,
-                               hipStream_t s);
+// (R.own and R.ntiles from onestep_geometry, R.flux_acc null), with scratch
+// `partials` of onestep_partials(R.ntiles) words; *flux = F(t) when flux is not
+// null.
+hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t* partials, uint32_t t,
+                                      unsigned long long* flux, hipStream_t s);
 
 // ---- agent (agent.hip) --------------------------------------------------------
 // k steps per launch: each wave holds 64 * cpl consecutive cars (cpl cars per

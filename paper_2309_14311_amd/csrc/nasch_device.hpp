@@ -19,6 +19,19 @@ struct Word4 {
     uint32_t w0, w1, w2, w3;
 };
 
+// The roads, planes and agent vectors live in device (global) memory, but a
+// pointer read out of a descriptor struct is generic to the compiler, which
+// then emits flat loads and stores; those also count against the LDS wait
+// counter, so every wait for an LDS access would wait for them too.  Accesses
+// through gmem() are global ones.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+// 16-byte vector of the global accesses (a built-in vector type: HIP's uint4
+// class has no address-space-qualified copies)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 // a ^ b ^ c in one gfx950 three-input bitwise instruction (truth table 0x96).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);

@@ -50,6 +50,14 @@ __device__ __forceinline__ uint32_t op(uint32_t a, uint32_t b, uint32_t c) {
         return __builtin_amdgcn_perm(a, b, 0x05010400u);
     } else if constexpr (OP == NASCH_PROBE_MUL_U24) {
         return __umul24(a, b);
+    } else if constexpr (OP == NASCH_PROBE_MIN) {
+        return min(a, b);
+    } else if constexpr (OP == NASCH_PROBE_SUB) {
+        return a - b;
+    } else if constexpr (OP == NASCH_PROBE_AND_OR) {
+        return (a & b) | (c & ~b);   // v_and_or_b32 (c & ~b is loop-invariant)
+    } else if constexpr (OP == NASCH_PROBE_CNDMASK) {
+        return c > 7u ? a : b;   // v_cndmask_b32 on a loop-invariant condition
     } else {
         return a;
     }
@@ -134,6 +142,10 @@ hipError_t launch_op(uint32_t kind, uint32_t blocks, uint32_t* out, uint64_t* cl
         case NASCH_PROBE_PERM: return launch<NASCH_PROBE_PERM>(blocks, out, clocks, iters, seed, s);
         case NASCH_PROBE_MUL_U24: return launch<NASCH_PROBE_MUL_U24>(blocks, out, clocks, iters, seed, s);
         case NASCH_PROBE_ADD_U64: return launch<NASCH_PROBE_ADD_U64>(blocks, out, clocks, iters, seed, s);
+        case NASCH_PROBE_MIN: return launch<NASCH_PROBE_MIN>(blocks, out, clocks, iters, seed, s);
+        case NASCH_PROBE_SUB: return launch<NASCH_PROBE_SUB>(blocks, out, clocks, iters, seed, s);
+        case NASCH_PROBE_CNDMASK: return launch<NASCH_PROBE_CNDMASK>(blocks, out, clocks, iters, seed, s);
+        case NASCH_PROBE_AND_OR: return launch<NASCH_PROBE_AND_OR>(blocks, out, clocks, iters, seed, s);
         default: return hipErrorInvalidValue;
     }
 }

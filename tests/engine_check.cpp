@@ -64,13 +64,13 @@ static int check_candidates() {
 // The one-step kernel's tiles: cover L, owned cells a multiple of 32 when there
 // are several tiles, a one-word halo.
 static int check_onestep() {
-    const uint32_t Ls[] = {1, 31, 32, 8127, 8128, 8129, 16288, 100003, 1u << 30, 2147483647u};
+    const uint32_t Ls[] = {1, 31, 32, 1983, 1984, 1985, 4000, 8128, 100003, 1u << 30, 2147483647u};
     for (uint32_t q = 1; q <= 2; ++q)
         for (uint32_t L : Ls) {
             uint32_t own, halo, nt;
             onestep_geometry(L, q, &own, &halo, &nt);
             if ((uint64_t)nt * own < L || (uint64_t)(nt - 1) * own >= L || halo != 32u ||
-                (nt > 1 && (own % 32u || own != 32u * (kOneStepThreads * q - 2u))))
+                (nt > 1 && (own % 32u || own != 32u * (64u * q - 2u))))
                 return printf("onestep geometry: L %u q %u\n", L, q), 1;
         }
     return 0;

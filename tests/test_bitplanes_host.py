@@ -1,8 +1,9 @@
 """The byte <-> bit-plane conversions of the bit-sliced kernels (bitplanes.hpp),
-built for the host and checked against cell-by-cell definitions: the nibble
-transpose bit by bit, the code planes and occupancy of random road words and
-their round trip, and the thermometer planes of every vmax (0xFF empty, else
-v <= vmax) with their way back to bytes."""
+built for the host with a model of the device's byte permute and checked
+against cell-by-cell definitions: the 4 x 4 byte transpose, the code planes and
+occupancy of random road words and their round trip, and the thermometer
+planes of every vmax (0xFF empty, else v <= vmax) with their way back to
+bytes."""
 import os
 import shutil
 import subprocess

@@ -115,17 +115,19 @@ def test_rule3_draws_at_the_ring_end(q, vmax):
 
 @pytest.mark.parametrize("vmax,p", [(1, 0.13), (5, 0.13), (8, 0.13), (5, 0.25), (3, 0.0)])
 def test_onestep_tile_edges(vmax, p):
-    """The one-step kernel's tiles: blocks of 256 words, a halo word at each
-    end and 8128 owned cells.  Rings just below, at and above one and several
-    tiles; last tiles that end inside the ring's last word; a tile whose
-    segment ends exactly at the ring's end (16288 = 8128 + 8160) or one cell
-    past it; and whole multiples of the tile."""
-    own = 32 * (256 - 2)
-    lengths = [own - 1, own, own + 1, own + 31, own + 32, own + 33, 8191, 8192, 8193,
-               2 * own, 2 * own + 5, 16287, 16288, 16289, 3 * own, 3 * own + 8161, 5 * own + 77]
+    """The one-step kernel's tiles: a wave's 64 words, a halo word at each end
+    and 1984 owned cells, each wave walking a run of tiles.  Rings just below,
+    at and above one and several tiles; last tiles that end inside the ring's
+    last word; a tile whose segment ends exactly at the ring's end (4000 =
+    1984 + 2016) or one cell past it; whole multiples of the tile; and rings
+    of more tiles than a launch has waves (each wave takes several)."""
+    own = 32 * (64 - 2)
+    lengths = [own - 1, own, own + 1, own + 31, own + 32, own + 33, 2047, 2048, 2049,
+               2 * own, 2 * own + 5, 3999, 4000, 4001, 3 * own, 3 * own + 2017, 5 * own + 77,
+               9000 * own + 13]
     for i, L in enumerate(lengths):
-        _run_and_compare(L, L // 4 + i, vmax, p, 300 + i, 25, kernel="onestep", init_v=1,
-                         replica=i % 3)
+        _run_and_compare(L, L // 4 + i, vmax, p, 300 + i, 25 if L < 10**6 else 5,
+                         kernel="onestep", init_v=1, replica=i % 3)
 
 
 @pytest.mark.parametrize("L", [1, 2, 3, 5, 8, 31, 32, 33, 63, 64, 100, 1023, 2047, 2048, 2049])

@@ -13,10 +13,6 @@ from paper_2309_14311_amd.native import grid_step_device, grid_step_device_noall
 pytestmark = pytest.mark.gpu
 
 
-def _road(L, N, vmax, seed):
-    return torch.from_numpy(oracle.init_grid(L, N, vmax, seed, init_v=1)).to("cuda")
-
-
 def _one(fn, d_in, L, vmax, p, seed, t, replica):
     out = torch.empty(L, dtype=torch.uint8, device="cuda")
     flux = torch.full((1,), -1, dtype=torch.int64, device="cuda")
@@ -27,16 +23,23 @@ def _one(fn, d_in, L, vmax, p, seed, t, replica):
 
 
 @pytest.mark.parametrize("sizes", [[(1 << 24) + 77, 5000, 100003, 33],
-                                   [2_000_003, 8128, 1, 8129]])
+                                   [2_000_003, 8128, 1, 8129, (1 << 24) + 77, 1985]])
 def test_noalloc_equals_allocating_entry_point(sizes):
+    """Consecutive calls of changing size (the scratch keeps what the last call
+    left): the same road and F(t) as the allocating entry point, and F(t) as
+    the oracle's."""
     vmax, p, seed = 5, 0.13, 21
     for i, L in enumerate(sizes):
-        d_in = _road(L, L // 5, vmax, seed + i)
+        g0 = oracle.init_grid(L, L // 5, vmax, seed + i, init_v=1)
+        d_in = torch.from_numpy(g0).to("cuda")
         t = 1000 + i
         want = _one(grid_step_device, d_in, L, vmax, p, seed, t, i)
         got = _one(grid_step_device_noalloc, d_in, L, vmax, p, seed, t, i)
         np.testing.assert_array_equal(got[0], want[0], err_msg=f"call {i}: L={L}")
         assert got[1] == want[1], (i, L)
+        _, f = oracle.step_grid(g0, vmax, p, seed, t, replica=i,
+                                nthreads=oracle.num_threads_available())
+        assert got[1] == f, (i, L)
 
 
 def test_noalloc_steps_match_oracle():
