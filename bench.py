@@ -524,6 +524,30 @@ def bench_serving(args):
     }
 
 
+def bench_valu_probe(args):
+    """The vector-ALU ceiling: sustained lane-ops/s of every instruction kind the
+    step kernels use (libnasch_probe), with the shader clock of each run, against
+    the unit-count peaks (2-cycle and 4-cycle issue)."""
+    from paper_2309_14311_amd import native
+    kinds = {}
+    for kind in native.PROBE_KINDS:
+        r = native.probe_valu(kind, 4096, 4000)
+        per_cycle = r["lane_ops_per_s"] / r["sclk_hz"] / 256 / 64
+        kinds[kind] = {"lane_ops_per_s": r["lane_ops_per_s"], "sclk_ghz": r["sclk_hz"] / 1e9,
+                       "wave_instr_per_cycle_per_cu": per_cycle,
+                       "issue_cycles": 2 if per_cycle > 1.25 else 4}
+    best = max(v["lane_ops_per_s"] for v in kinds.values())
+    return {
+        "metric": "vector-ALU lane-ops/s by instruction kind", "value": best,
+        "unit": "lane-ops/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "VALU probe: 4096 blocks x 256 lanes, 8 independent chains of "
+                               "one instruction kind per lane"},
+        "peak_2cycle": VALU_PEAK, "peak_4cycle": VALU_PEAK_4CYCLE, "kinds": kinds,
+    }
+
+
 def bench_single(args, cfg, rep, kernels):
     """One ring: value = k-step (autotuned) CUPS; the one-step kernel beside it."""
     import torch
@@ -634,7 +658,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ensemble",
                     choices=["ensemble", "large_ring", "agent", "reference", "serving",
-                             "open_road", "open_ensemble"])
+                             "open_road", "open_ensemble", "valu_probe"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate-frac", type=float, default=0.5)
     ap.add_argument("--replicas", type=int, default=4096)
@@ -681,6 +705,8 @@ def main():
         line = bench_ensemble(args)
     elif args.workload == "serving":
         line = bench_serving(args)
+    elif args.workload == "valu_probe":
+        line = bench_valu_probe(args)
     elif args.workload == "large_ring":
         line = bench_single(args, workloads.LARGE_RING, "grid", ["kstep", "onestep"])
     elif args.workload == "open_road":
