@@ -35,16 +35,18 @@ struct AgentLds {
 
 // Rule 3 for C consecutive cars per lane (keyed draw), shared by the wave.
 // The wave's cars are cyclically sorted, so the 32-cell blocks they start in
-// form one run of blocks from the block of lane 0's first car (mod the number
-// of blocks).  The lanes draw the first kBlockSlots blocks of that run
-// together (one Philox call per lane and 64 blocks), compare each block's 32
-// top nibbles with thr's at once, and keep two masks per block in LDS: cars
-// below thr's nibble and cars tying with it.  A car reads its two bits from
-// its block's entry; a car further along (a sparse road) draws its own block.
-// The cars whose nibble ties with thr's are then numbered across the wave and
-// have their low 28 bits drawn 64 at a time.  `nv` holds each car's velocity after rules 1-2 and receives
-// the result of rule 3.  All 64 lanes must be active; cars with nv == 0 draw
-// nothing.
+// form one run from the block of lane 0's first car (mod the number of
+// blocks): a car's slot in that run is its block minus lane 0's, and the run
+// ends at the slot of lane 63's last car.  The lanes draw the first
+// kBlockSlots blocks of the run together (one Philox call per lane and 64
+// blocks), compare each block's 32 top nibbles with thr's at once, and keep
+// two masks per block in LDS: cars below thr's nibble and cars tying with it.
+// A car reads its two bits from its block's entry; a car past the table (a
+// sparse road, or a wave whose cars go round a short ring) draws its own
+// block.  The cars whose nibble ties with thr's are then numbered across the
+// wave and have their low 28 bits drawn 64 at a time.  `nv` holds each car's
+// velocity after rules 1-2 and receives the result of rule 3.  All 64 lanes
+// must be active; a car with nv == 0 never slows.
 template <int C>
 __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&x)[C],
                                             uint32_t L, uint32_t t, const SlowParams& sp,
@@ -53,14 +55,13 @@ __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&
     const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(x[0] >> 5));
     const uint32_t cap = min(kBlockSlots, nblk);
     uint32_t slot[C];
-    uint32_t top = 0;
 #pragma unroll
     for (int q = 0; q < C; ++q) {
-        const int32_t dlt = (int32_t)(x[q] >> 5) - (int32_t)b0;
-        slot[q] = dlt < 0 ? (uint32_t)(dlt + (int32_t)nblk) : (uint32_t)dlt;
-        if (nv[q] > 0u && slot[q] < cap) top = max(top, slot[q] + 1u);
+        const uint32_t dlt = (x[q] >> 5) - b0;   // wraps above nblk when the block is below b0
+        slot[q] = min(dlt, dlt + nblk);
     }
-    const uint32_t n = wave_max(top);   // table entries used, <= cap
+    const uint32_t n =
+        min(cap, (uint32_t)__builtin_amdgcn_readlane((int)(slot[C - 1] + 1u), 63));
     const uint32_t th = sp.thr >> 28;
     for (uint32_t j = lane; j < n; j += 64u) {
         uint32_t blk = b0 + j;
@@ -72,24 +73,19 @@ __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
     uint32_t tie = 0;
 #pragma unroll
     for (int q = 0; q < C; ++q) {
-        if (nv[q] > 0u) {
-            uint2 e;
-            if (slot[q] < n) {
-                e = lds.blk[slot[q]];
-            } else {
-                block_lt_eq(slow_hi_planes(x[q] >> 5, t, sp), th, e.x, e.y);
-            }
-            const uint32_t sh = x[q] & 31u;
-            if ((e.x >> sh) & 1u) --nv[q];
-            else if ((e.y >> sh) & 1u) tie |= 1u << q;
-        }
+        uint2 e = lds.blk[min(slot[q], kBlockSlots - 1u)];
+        if (slot[q] >= n) block_lt_eq(slow_hi_planes(x[q] >> 5, t, sp), th, e.x, e.y);
+        const uint32_t sh = x[q] & 31u;
+        const uint32_t moving = min(nv[q], 1u);
+        nv[q] -= ((e.x >> sh) & 1u) & moving;
+        if (lo_thr != 0u) tie |= (((e.y >> sh) & moving) & 1u) << q;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
     if (lo_thr == 0u) return;   // a tie then never slows (the low bits cannot be below 0)
     const uint32_t cnt = __popc(tie);
     const uint32_t incl = wave_scan_incl(cnt);
@@ -201,18 +197,28 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
     uint32_t xs_first = 0u;
     if (A->rng)
         xs_first = mlcg_mul(mlcg_pow(A->mlcg_pow, (uint64_t)t0 * N + idx0 + 1u), A->mlcg_x0);
+    // owned cars (F(t) counts them only), as masks
+    uint32_t ownm[CPL];
+#pragma unroll
+    for (int q = 0; q < (int)CPL; ++q) ownm[q] = lane * CPL + q < own_len ? 0xFFFFFFFFu : 0u;
     for (uint32_t s = 0; s < k; ++s) {
         const uint32_t t = t0 + s;
         const uint32_t x_next_lane = from_next_lane(x[0]);
         uint32_t nv[CPL];
+        if (N > 1) {
 #pragma unroll
-        for (int q = 0; q < (int)CPL; ++q) {
-            uint32_t d = L;
-            if (N > 1 && !(q == (int)CPL - 1 && lane == 63u)) {
+            for (int q = 0; q < (int)CPL; ++q) {
+                // d = (x_next - x) mod L: the difference wraps above the sum
+                // when the car ahead is past the end of the ring.  Lane 63's
+                // last car reads 0 for the next lane's car: a halo car, whose
+                // results are discarded.
                 const uint32_t xn = (q + 1 < (int)CPL) ? x[(q + 1) % CPL] : x_next_lane;
-                d = xn >= x[q] ? xn - x[q] : xn + L - x[q];
+                const uint32_t dd = xn - x[q];
+                nv[q] = accel_brake(v[q], min(dd, dd + L), vmax);
             }
-            nv[q] = accel_brake(v[q], d, vmax);
+        } else {
+#pragma unroll
+            for (int q = 0; q < (int)CPL; ++q) nv[q] = accel_brake(v[q], L, vmax);
         }
         if (A->rng) {
             // rule 3 from the shared stream
@@ -236,10 +242,9 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
         uint32_t fl = 0u;
 #pragma unroll
         for (int q = 0; q < (int)CPL; ++q) {
-            if (lane * CPL + q < own_len) fl += nv[q];
-            uint32_t xn = x[q] + nv[q];     // rule 4
-            if (xn >= L) xn -= L;
-            x[q] = xn;
+            fl += nv[q] & ownm[q];
+            const uint32_t xn = x[q] + nv[q];   // rule 4; x + v < 2L < 2^32
+            x[q] = min(xn, xn - L);             // xn - L wraps above xn unless xn >= L
             v[q] = nv[q];
         }
         if (log) {
