@@ -38,7 +38,11 @@ extern "C" {
 #define NASCH_PROBE_SUB     15u /* v_sub_u32                                         */
 #define NASCH_PROBE_CNDMASK 16u /* v_cndmask_b32: select by a lane mask              */
 #define NASCH_PROBE_AND_OR  17u /* v_and_or_b32: (a & b) | c                         */
-#define NASCH_PROBE_KINDS   18u
+#define NASCH_PROBE_BFI     18u /* v_bfi_b32: bitwise select (a & b) | (~a & c)     */
+#define NASCH_PROBE_OR      19u /* v_or_b32                                          */
+#define NASCH_PROBE_AND     20u /* v_and_b32                                         */
+#define NASCH_PROBE_ADD3    21u /* v_add3_u32: a + b + c                             */
+#define NASCH_PROBE_KINDS   22u
 
 typedef struct {
     double ms;                 /* device time of the timed launch (HIP events)          */

@@ -31,6 +31,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # an LDS atomic that every lane of a wave issues on one address stays
+          # one instruction (the step kernels reserve queue slots that way); the
+          # default rewrites it into a scalar loop over the active lanes
+          "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
           "-I", INCLUDE, "-I", CSRC]
 
 

@@ -31,6 +31,7 @@ struct AgentLds {
     uint2 blk[kBlockSlots];   // (lt, eq) masks of each tabulated block
     uint32_t tie_x[kTieCap];
     uint8_t tie_r[kTieCap];
+    uint32_t n;               // tied cars of the step (0 between steps)
 };
 
 // Rule 3 for C consecutive cars per lane (keyed draw), shared by the wave.
@@ -43,8 +44,10 @@ struct AgentLds {
 // two masks per block in LDS: cars below thr's nibble and cars tying with it.
 // A car reads its two bits from its block's entry; a car past the table (a
 // sparse road, or a wave whose cars go round a short ring) draws its own
-// block.  The cars whose nibble ties with thr's are then numbered across the
-// wave and have their low 28 bits drawn 64 at a time.  `nv` holds each car's
+// block.  The cars whose nibble ties with thr's are then queued in LDS (each
+// lane reserving its slots with one LDS atomic add; the queue's order does not
+// matter, a draw is keyed by the car's cell) and have their low 28 bits drawn
+// 64 at a time.  `nv` holds each car's
 // velocity after rules 1-2 and receives the result of rule 3.  All 64 lanes
 // must be active; a car with nv == 0 never slows.
 template <int C>
@@ -88,11 +91,15 @@ __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&
     __builtin_amdgcn_wave_barrier();
     if (lo_thr == 0u) return;   // a tie then never slows (the low bits cannot be below 0)
     const uint32_t cnt = __popc(tie);
-    const uint32_t incl = wave_scan_incl(cnt);
-    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    uint32_t base = 0u;
+    if (cnt) base = atomicAdd(&lds.n, cnt);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t total = __builtin_amdgcn_readfirstlane(lds.n);
     if (total == 0u) return;
     const uint32_t nq = min(total, kTieCap);
-    uint32_t idx = incl - cnt;
+    uint32_t idx = base;
 #pragma unroll
     for (int q = 0; q < C; ++q) {
         if ((tie >> q) & 1u) {
@@ -108,7 +115,7 @@ __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    idx = incl - cnt;
+    idx = base;
 #pragma unroll
     for (int q = 0; q < C; ++q) {
         if ((tie >> q) & 1u) {
@@ -117,6 +124,7 @@ __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&
             ++idx;
         }
     }
+    if (lane == 0u) lds.n = 0u;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
@@ -140,6 +148,7 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
     const uint32_t wave = blockIdx.x * 4u + wib;
     if (wave >= ntiles) return;
     AgentLds& lds = s_lds[wib];
+    if (lane == 0u) lds.n = 0u;
     const uint32_t N = A->N, L = A->L, vmax = A->vmax;
     const SlowParams sp = A->sp;
     const uint32_t t0 = clk->t + A->t + s_off;

@@ -168,6 +168,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     for (int q = 0; q < Q; ++q) {
         rl.slow[lane * Q + q] = 0u;
     }
+    if (lane == 0u) rl.n = 0u;
     wave_sync_lds();
     uint32_t draw_mode = kDrawAligned;   // open roads: every word is aligned
     if constexpr (!OPEN) {
@@ -190,6 +191,10 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
 
     // ---- k steps
     uint32_t acc = 0u;
+    // F(t) as binary digit counts (add_speed_digits), summed over the steps
+    // that count: every step with a flux log, else the steps past the warm-up
+    uint32_t dig[4] = {0u, 0u, 0u, 0u};
+    uint32_t sum_prev = 0u;   // flux log: speed_sum(dig) after the previous step
     const bool log = R.flux_log != nullptr;
     // steps of this launch before the warm-up ends (their flux is not summed)
     // (compared as integers: min<uint64_t> here compiled to double-precision instructions)
@@ -197,7 +202,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     const uint32_t s_warm = to_warm < nsteps ? (uint32_t)to_warm : nsteps;
     for (uint32_t s = 0; s < nsteps; ++s) {
         const uint32_t t = t0 + s;
-        uint32_t fl = 0;
+        const bool need_fl = log || s >= s_warm;   // uniform over the wave
         bool enter = false;
         uint32_t empty0[Q];   // open road: cell 0, if it is empty at the start of the step
         if constexpr (OPEN) {
@@ -245,17 +250,13 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                 T3[0] = T[q][0];
 #pragma unroll
                 for (int m = 1; m <= VMAX; ++m)
-                    T3[m] = (T2[q][m] & ~S[q]) | (T2[q][m + 1] & S[q]);
+                    T3[m] = select_bits(S[q], T2[q][m + 1], T2[q][m]);
                 T3[VMAX + 1] = 0u;
-                if (own[q] == 0xFFFFFFFFu) {
+                // (skipped in a warm-up step of a ring without a flux log)
+                if (need_fl) add_speed_digits<VMAX, true>(T3, own[q], dig);
 #pragma unroll
-                    for (int m = 1; m <= VMAX; ++m) fl += __popc(T3[m]);
-                } else if (own[q]) {
-#pragma unroll
-                    for (int m = 1; m <= VMAX; ++m) fl += __popc(T3[m] & own[q]);
-                }
-#pragma unroll
-                for (int j = 0; j <= VMAX; ++j) Eq[q][j] = T3[j] & ~T3[j + 1];
+                for (int j = 1; j <= VMAX; ++j) Eq[q][j] = T3[j] & ~T3[j + 1];
+                Eq[q][0] = T3[1];   // the moving cars; the stopped ones are T3[0] & ~T3[1]
             }
             // rule 4: cars with v3 == j move j cells right
             uint32_t prevEq[VMAX + 1];
@@ -270,7 +271,8 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
                     accm |= __builtin_amdgcn_alignbit(Eq[q][j], prv, 32 - j);
                     T[q][j] = accm;
                 }
-                T[q][0] = accm | Eq[q][0];
+                // occupancy: the moved cars and the stopped ones, accm | (T3[0] & ~T3[1])
+                T[q][0] = __builtin_amdgcn_bitop3_b32(T[q][0], Eq[q][0], accm, 0xBA);
             }
         }
         if constexpr (OPEN) {
@@ -280,11 +282,15 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
             }
         }
         if (log) {
+            const uint32_t sum = speed_sum(dig);
+            const uint32_t fl = sum - sum_prev;   // this lane's share of F(t)
+            sum_prev = sum;
             const uint32_t total = wave_total(fl);
             if (lane == 0u) partials[(size_t)s * n_items + item] = total;
+            acc += s >= s_warm ? fl : 0u;
         }
-        acc += s >= s_warm ? fl : 0u;
     }
+    if (!log) acc = speed_sum(dig);   // only the steps past the warm-up were added
     if (R.flux_acc) {
         const uint32_t total = wave_total(acc);
         if (lane == 0u && total) atomicAdd(R.flux_acc, (unsigned long long)total);

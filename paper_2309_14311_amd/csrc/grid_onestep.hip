@@ -114,6 +114,7 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
     uint32_t fl = 0u;
     if constexpr (VMAX > 0) {
         if (run) {
+            uint32_t dig[4] = {0u, 0u, 0u, 0u};   // F(t) as binary digit counts
             // occupancy of the word after the lane's last one (lane 63's is the
             // halo word's, whose own results are not kept)
             const uint32_t occ_next = from_next_lane(T[0][0]);
@@ -149,12 +150,12 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
                 T3[0] = T[q][0];
 #pragma unroll
                 for (int m = 1; m <= VMAX; ++m)
-                    T3[m] = (T2[q][m] & ~S[q]) | (T2[q][m + 1] & S[q]);
+                    T3[m] = select_bits(S[q], T2[q][m + 1], T2[q][m]);
                 T3[VMAX + 1] = 0u;
+                add_speed_digits<VMAX, true>(T3, own[q], dig);
 #pragma unroll
-                for (int m = 1; m <= VMAX; ++m) fl += __popc(T3[m] & own[q]);
-#pragma unroll
-                for (int j = 0; j <= VMAX; ++j) Eq[q][j] = T3[j] & ~T3[j + 1];
+                for (int j = 1; j <= VMAX; ++j) Eq[q][j] = T3[j] & ~T3[j + 1];
+                Eq[q][0] = T3[1];   // the moving cars; the stopped ones are T3[0] & ~T3[1]
             }
             // rule 4: cars with v3 == j move j cells right (lane 0's incoming
             // cars are unknown: its word is the halo)
@@ -170,8 +171,10 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
                     accm |= __builtin_amdgcn_alignbit(Eq[q][j], prv, 32 - j);
                     T[q][j] = accm;
                 }
-                T[q][0] = accm | Eq[q][0];
+                // occupancy: the moved cars and the stopped ones, accm | (T3[0] & ~T3[1])
+                T[q][0] = __builtin_amdgcn_bitop3_b32(T[q][0], Eq[q][0], accm, 0xBA);
             }
+            fl = speed_sum(dig);
         }
     }
 
@@ -202,6 +205,7 @@ __device__ __forceinline__ void os_block(const RingDesc& R, uint32_t b, uint32_t
         RefineLds<Q>& rl = ref[wib];
 #pragma unroll
         for (int q = 0; q < Q; ++q) rl.slow[lane * Q + q] = 0u;
+        if (lane == 0u) rl.n = 0u;
         uint32_t d[Q][8];
         os_load<Q>(R, R.buf[par], tile, lane, d);
         fl = os_step<VMAX, Q>(R, R.buf[par ^ 1u], tile, t, run, lane, d, rl);

@@ -58,6 +58,21 @@ __device__ __forceinline__ uint32_t op(uint32_t a, uint32_t b, uint32_t c) {
         return (a & b) | (c & ~b);   // v_and_or_b32 (c & ~b is loop-invariant)
     } else if constexpr (OP == NASCH_PROBE_CNDMASK) {
         return c > 7u ? a : b;   // v_cndmask_b32 on a loop-invariant condition
+    } else if constexpr (OP == NASCH_PROBE_BFI) {
+        // the chain value selects between b and c (written out: the compiler
+        // turns the C form into v_bitop3_b32 here)
+        uint32_t r;
+        __asm__("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+        return r;
+    } else if constexpr (OP == NASCH_PROBE_OR) {
+        return a | b;
+    } else if constexpr (OP == NASCH_PROBE_AND) {
+        return a & b;
+    } else if constexpr (OP == NASCH_PROBE_ADD3) {
+        // written out: the compiler adds the loop-invariant b + c once
+        uint32_t r;
+        __asm__("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+        return r;
     } else {
         return a;
     }
@@ -146,6 +161,10 @@ hipError_t launch_op(uint32_t kind, uint32_t blocks, uint32_t* out, uint64_t* cl
         case NASCH_PROBE_SUB: return launch<NASCH_PROBE_SUB>(blocks, out, clocks, iters, seed, s);
         case NASCH_PROBE_CNDMASK: return launch<NASCH_PROBE_CNDMASK>(blocks, out, clocks, iters, seed, s);
         case NASCH_PROBE_AND_OR: return launch<NASCH_PROBE_AND_OR>(blocks, out, clocks, iters, seed, s);
+        case NASCH_PROBE_BFI: return launch<NASCH_PROBE_BFI>(blocks, out, clocks, iters, seed, s);
+        case NASCH_PROBE_OR: return launch<NASCH_PROBE_OR>(blocks, out, clocks, iters, seed, s);
+        case NASCH_PROBE_AND: return launch<NASCH_PROBE_AND>(blocks, out, clocks, iters, seed, s);
+        case NASCH_PROBE_ADD3: return launch<NASCH_PROBE_ADD3>(blocks, out, clocks, iters, seed, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -551,7 +551,8 @@ def grid_step_device_noalloc(d_in, d_out, L, vmax, p, seed, t, *, d_flux=None, r
 PROBE_PATH = os.path.join(_PKG, "libnasch_probe.so")
 PROBE_KINDS = {"bitop3": 0, "alignbit": 1, "bcnt": 2, "mul_lo": 3, "mul_hi": 4, "mad_u64": 5,
                "dpp": 6, "add": 7, "xor": 8, "shift": 9, "lshl_or": 10, "perm": 11,
-               "mul_u24": 12, "add_u64": 13, "min": 14, "sub": 15, "cndmask": 16, "and_or": 17}
+               "mul_u24": 12, "add_u64": 13, "min": 14, "sub": 15, "cndmask": 16, "and_or": 17,
+               "bfi": 18, "or": 19, "and": 20, "add3": 21}
 _probe = None
 
 

@@ -185,15 +185,28 @@ def test_agent_ring_shared_stream_whole_state(kernel):
 
 def test_ensemble_in_bench_configuration():
     """The 4096-replica ensemble as the benchmark runs it (graph replay, autotuned
-    (k, q), reset between passes): the smallest replicas, a median-size one and
-    the largest one against the oracle in full (the largest on the oracle's
-    all-core twin), a sample of the rest against the same replica run alone."""
+    (k, q), reset between passes): every replica's final road and flux sum
+    against the oracle's (by checksum, over two passes); the smallest replicas,
+    a median-size one and the largest one against the oracle in full (the
+    largest on the oracle's all-core twin), a sample of the rest against the
+    same replica run alone."""
     reps = workloads.ensemble(4096, seed=1, T=5000, warmup=1000)
+    g = GOLDEN["ensemble"]
+    assert (g["replicas"], g["seed"], g["T"], g["warmup"]) == (4096, 1, 5000, 1000)
+    assert g["cells"] == sum(r["L"] for r in reps)
     b = Batch(reps, use_graph=True)
     b.autotune()
-    b.reset()
-    b.step(5000)
-    sums = b.flux_sums()
+    for _ in range(2):
+        b.reset()
+        b.step(5000)
+        sums = b.flux_sums()
+        grids, t = b.snapshot_all()
+        assert t == 5000
+        assert f"{oracle.fnv1a64(grids):016x}" == g["grid_fnv1a64"], "final roads differ"
+        assert int(sums.astype(np.uint64).sum()) == g["flux_sums_total"]
+        assert f"{oracle.fnv1a64(sums.astype('<u8')):016x}" == g["flux_sums_fnv1a64"], \
+            "flux sums differ"
+        del grids
     order = np.argsort([r["L"] for r in reps])
     nthreads = min(16, oracle.num_threads_available())
     for i in list(order[:12]) + [order[len(order) // 2], order[-1]]:
