@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_2309_14311_amd import Sim, Writer
-from paper_2309_14311_amd.traffic import CLI
+from paper_2309_14311_amd.build import CLI
 
 pytestmark = pytest.mark.gpu
 
