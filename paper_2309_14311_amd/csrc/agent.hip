@@ -78,14 +78,30 @@ __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const uint32_t lo_thr = sp.thr & 0x0FFFFFFFu;
     uint32_t tie = 0;
+    // The table covers every car of the wave unless some car lies past it (a
+    // sparse road, or a wave going round a short ring): the common case reads
+    // it with no per-car test or clamp.  A slow car loses one unit of speed,
+    // none below 0 (a saturating subtraction); a tie counts only for a moving car.
+    uint32_t smax = slot[0];
 #pragma unroll
-    for (int q = 0; q < C; ++q) {
-        uint2 e = lds.blk[min(slot[q], kBlockSlots - 1u)];
-        if (slot[q] >= n) block_lt_eq(slow_hi_planes(x[q] >> 5, t, sp), th, e.x, e.y);
-        const uint32_t sh = x[q] & 31u;
-        const uint32_t moving = min(nv[q], 1u);
-        nv[q] -= ((e.x >> sh) & 1u) & moving;
-        if (lo_thr != 0u) tie |= (((e.y >> sh) & moving) & 1u) << q;
+    for (int q = 1; q < C; ++q) smax = max(smax, slot[q]);
+    if (__builtin_amdgcn_ballot_w64(smax >= n) == 0u) {
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const uint2 e = lds.blk[slot[q]];
+            const uint32_t sh = x[q] & 31u;
+            if (lo_thr != 0u) tie |= (__builtin_amdgcn_ubfe(e.y, sh, 1u) & min(nv[q], 1u)) << q;
+            nv[q] = __builtin_elementwise_sub_sat(nv[q], __builtin_amdgcn_ubfe(e.x, sh, 1u));
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            uint2 e = lds.blk[min(slot[q], kBlockSlots - 1u)];
+            if (slot[q] >= n) block_lt_eq(slow_hi_planes(x[q] >> 5, t, sp), th, e.x, e.y);
+            const uint32_t sh = x[q] & 31u;
+            if (lo_thr != 0u) tie |= (__builtin_amdgcn_ubfe(e.y, sh, 1u) & min(nv[q], 1u)) << q;
+            nv[q] = __builtin_elementwise_sub_sat(nv[q], __builtin_amdgcn_ubfe(e.x, sh, 1u));
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -191,11 +191,13 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
 
 // Step t of tile 4 b + wave of ring R (b: the block's tile group), from
 // R.buf[par] to R.buf[par ^ 1].  The block's F(t) goes to *partial (if not
-// null) and, from the warm-up on, into R.flux_acc.
+// null), to *whole (if not null: a launch of one block, whose F(t) is the
+// ring's) and, from the warm-up on, into R.flux_acc.
 template <int VMAX, int Q>
 __device__ __forceinline__ void os_block(const RingDesc& R, uint32_t b, uint32_t t, uint32_t par,
-                                         uint32_t* __restrict__ partial, RefineLds<Q>* ref,
-                                         uint32_t* s_flux) {
+                                         uint32_t* __restrict__ partial,
+                                         unsigned long long* __restrict__ whole,
+                                         RefineLds<Q>* ref, uint32_t* s_flux) {
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t tile = b * kOsWaves + wib;
@@ -218,6 +220,7 @@ __device__ __forceinline__ void os_block(const RingDesc& R, uint32_t b, uint32_t
 #pragma unroll
         for (uint32_t w = 0; w < kOsWaves; ++w) total += s_flux[w];
         if (partial) *partial = total;
+        if (whole) *whole = total;
         if (R.flux_acc && run && (uint64_t)t >= R.warmup && total)
             atomicAdd(R.flux_acc, (unsigned long long)total);
     }
@@ -237,18 +240,25 @@ __global__ __launch_bounds__(kOneStepThreads) void grid_onestep_kernel(
     const RingDesc& R = *ring;
     const uint32_t t = clk->t + R.t + s_off;
     const uint32_t par = (clk->parity + R.parity + launch_idx) & 1u;
-    os_block<VMAX, Q>(R, b, t, par, R.flux_log ? partials + b : nullptr, s_ref, s_flux);
+    // one block (a ring of at most 4 tiles) writes F(t) itself: no fold launch
+    const bool one = gridDim.x == 1u && R.flux_log;
+    os_block<VMAX, Q>(R, b, t, par, R.flux_log && !one ? partials + b : nullptr,
+                      one ? R.flux_log + ((uint64_t)t - R.log_t0) : nullptr, s_ref, s_flux);
 }
 
 // One step t of a ring described by value (buf[0] is read, buf[1] written):
 // the launch of the stateless device-buffer entry points.
 template <int VMAX, int Q>
 __global__ __launch_bounds__(kOneStepThreads) void grid_onestep_direct_kernel(
-    const RingDesc R, uint32_t* __restrict__ partials, uint32_t t) {
+    const RingDesc R, uint32_t* __restrict__ partials, uint32_t t,
+    unsigned long long* __restrict__ flux) {
     __shared__ RefineLds<Q> s_ref[kOsWaves];
     __shared__ uint32_t s_flux[kOsWaves];
     const uint32_t b = xcd_item(blockIdx.x, gridDim.x);
-    os_block<VMAX, Q>(R, b, t, 0u, partials + b, s_ref, s_flux);
+    // one block writes F(t) itself: no fold launch
+    const bool one = gridDim.x == 1u;
+    os_block<VMAX, Q>(R, b, t, 0u, one ? nullptr : partials + b, one ? flux : nullptr, s_ref,
+                      s_flux);
 }
 
 // F(t) = the sum of n uint32 partials, into *out or into the ring's flux log at
@@ -323,7 +333,7 @@ uint32_t os_blocks(uint32_t ntiles) { return std::max(1u, (ntiles + kOsWaves - 1
 // The counter has a fixed place so that it stays 0 between launches of any size.
 hipError_t fold(uint32_t* scratch, uint32_t n, unsigned long long* out, const RingDesc* ring,
                 const Clock* clk, uint32_t s_off, hipStream_t s) {
-    NASCH_LAUNCH(fold_partials_kernel, dim3(kFoldBlocks), dim3(256), 0, s,
+    NASCH_LAUNCH(fold_partials_kernel, dim3(std::min(kFoldBlocks, (n + 255u) / 256u)), dim3(256), 0, s,
                  scratch + kFoldScratchWords, n,
                  reinterpret_cast<unsigned long long*>(scratch + 2), scratch, out, ring, clk,
                  s_off);
@@ -342,7 +352,7 @@ hipError_t launch_grid_onestep(uint32_t vmax, uint32_t ntiles, const RingDesc* r
     NASCH_OS_VMAX_SWITCH(grid_onestep_kernel, kOneStepQ, dim3(nb), dim3(kOneStepThreads), 0, s,
                          ring, partials + kFoldScratchWords, clk, s_off, launch_idx)
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !log) return e;
+    if (e != hipSuccess || !log || nb == 1u) return e;   // one block wrote F(t) itself
     return fold(partials, nb, nullptr, ring, clk, s_off, s);
 }
 
@@ -352,9 +362,9 @@ hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t* partials, uin
     const uint32_t vmax = R.vmax;
     const uint32_t nb = os_blocks(R.ntiles);
     NASCH_OS_VMAX_SWITCH(grid_onestep_direct_kernel, kOneStepQ, dim3(nb), dim3(kOneStepThreads),
-                         0, s, R, partials + kFoldScratchWords, t)
+                         0, s, R, partials + kFoldScratchWords, t, flux)
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !flux) return e;
+    if (e != hipSuccess || !flux || nb == 1u) return e;   // one block wrote F(t) itself
     return fold(partials, nb, flux, nullptr, nullptr, 0u, s);
 }
 
