@@ -47,11 +47,20 @@ __device__ __forceinline__ Word4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     for (int r = 0; r < 10; ++r) {
         const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
-        // in round 0, n0 depends on counter words 1-2 and the key only, which
-        // are uniform at every call site: plain XORs let it stay scalar
-        const uint32_t n0 = r == 0 ? ((uint32_t)(m1 >> 32) ^ c1) ^ k0
-                                   : xor3((uint32_t)(m1 >> 32), c1, k0);
-        const uint32_t n2 = xor3((uint32_t)(m0 >> 32), c3, k1);
+        // With counter words 1-3 uniform (every call site), some operands of
+        // rounds 0-2 are uniform too; grouping those with plain XORs lets the
+        // scalar unit combine them, where a three-input vector XOR would need
+        // a move for its second scalar operand: round 0's n0 is uniform
+        // outright; in round 1, c1 (a product of uniform words) and hi(m0)
+        // (c0 is round 0's uniform n0) are; in round 2, c3 is (round 1's
+        // lo(m0)).
+        const uint32_t h0 = (uint32_t)(m0 >> 32), h1 = (uint32_t)(m1 >> 32);
+        const uint32_t n0 = r == 0 ? (h1 ^ c1) ^ k0
+                          : r == 1 ? h1 ^ (c1 ^ k0)
+                                   : xor3(h1, c1, k0);
+        const uint32_t n2 = r == 1 ? (h0 ^ k1) ^ c3
+                          : r == 2 ? h0 ^ (c3 ^ k1)
+                                   : xor3(h0, c3, k1);
         c1 = (uint32_t)m1;
         c3 = (uint32_t)m0;
         c0 = n0;
