@@ -260,8 +260,8 @@ int nasch_grid_step_device(const uint8_t* d_in, uint8_t* d_out, uint64_t L, uint
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * step as nasch_grid_step_device, same arguments, layout, ownership and
  * errors, but it allocates nothing.  Its scratch (one uint32 flux partial per
- * block of four 1984-cell tiles, and the fold's per-block sums and counter) is
- * a static device array of 270731 words (about 1 MiB) that each device the
+ * block of eight 1984-cell tiles, and the fold's per-block sums and counter) is
+ * a static device array of 135431 words (about 0.5 MiB) that each device the
  * library runs on holds until the process ends; every L the library accepts
  * fits it (a launch needing more would be NASCH_EINVAL).
  * All calls on one device share that array, so calls that overlap on one

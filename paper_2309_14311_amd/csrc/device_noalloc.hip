@@ -22,10 +22,12 @@ using namespace nasch;
 
 namespace {
 // The fold's counter and per-block sums, then one uint32 F(t) partial per block
-// of 4 tiles of 1984 cells, for the longest ring (L = 2^31 - 1): about 1 MiB.
+// of 8 tiles (one per wave) of 1984 cells, for the longest ring
+// (L = 2^31 - 1): about 0.5 MiB.
 constexpr uint32_t kTileCells = 32u * (64u * kOneStepQ - 2u);
-constexpr uint32_t kMaxBlocks =
-    (uint32_t)(((NASCH_MAX_L + kTileCells - 1u) / kTileCells + 3u) / 4u);
+constexpr uint32_t kTilesPerBlock = kOneStepThreads / 64u;
+constexpr uint32_t kMaxBlocks = (uint32_t)(((NASCH_MAX_L + kTileCells - 1u) / kTileCells +
+                                            kTilesPerBlock - 1u) / kTilesPerBlock);
 constexpr uint32_t kScratchWords = kFoldScratchWords + kMaxBlocks;
 }  // namespace
 

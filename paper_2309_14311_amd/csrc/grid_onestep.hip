@@ -19,10 +19,12 @@
 // Streaming.  One tile per wave and one launch over all tiles: on this GPU a
 // launch whose waves each move one tile and exit streams faster (5.8 TB/s for
 // the bare copy of this access pattern) than persistent waves that loop over
-// tiles (5.0 - 5.3 TB/s, with or without prefetching the next tile).  The 4
-// waves of a block take 4 consecutive tiles and add their F(t) into one
-// partial; blocks dealt to one XCD (the 8 XCDs take blocks in turn) take
-// consecutive tiles.  A fold kernel sums the partials.
+// tiles (5.0 - 5.3 TB/s, with or without prefetching the next tile), and two
+// tiles per wave measured slower too.  The 8 waves of a block take 8
+// consecutive tiles and add their F(t) into one partial (blocks of 1, 2, 4
+// and 16 waves measured 9, 4, 2 and 1 % slower); blocks dealt to one XCD (the
+// 8 XCDs take blocks in turn) take consecutive tiles.  A fold kernel sums the
+// partials.
 //
 // Segment cell i is ring cell (own_start - 32 + i) mod L.  A tile whose
 // segment lies inside [0, L) is the common case and takes aligned 16-byte
@@ -189,7 +191,7 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
     return fl;
 }
 
-// Step t of tile 4 b + wave of ring R (b: the block's tile group), from
+// Step t of tile 8 b + wave of ring R (b: the block's tile group), from
 // R.buf[par] to R.buf[par ^ 1].  The block's F(t) goes to *partial (if not
 // null), to *whole (if not null: a launch of one block, whose F(t) is the
 // ring's) and, from the warm-up on, into R.flux_acc.

@@ -77,7 +77,7 @@ hipError_t launch_grid_kstep_bytes(uint32_t vmax, bool open, uint32_t q, const R
 // ---- grid, one step per launch on the byte form (grid_onestep.hip) -----------
 // A wave handles a tile of 64 q words: a halo word at each end and the owned
 // words in between; blocks of kOneStepThreads lanes hold independent waves.
-constexpr uint32_t kOneStepThreads = 256;
+constexpr uint32_t kOneStepThreads = 512;
 // Words per lane of the one-step kernel.
 constexpr uint32_t kOneStepQ = 1;
 // The fold of a launch's F(t) partials: blocks, and the scratch words it needs
