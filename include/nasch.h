@@ -69,7 +69,11 @@ extern "C" {
 #define NASCH_ENOTFOUND (-7) /* no such replica / request                    */
 
 /* ---- limits ------------------------------------------------------------ */
-#define NASCH_MAX_VMAX  8u            /* kernels are specialised for vmax <= 8 */
+#define NASCH_MAX_VMAX  8u            /* the grid form's kernels (bit planes) are
+                                         specialised for vmax <= 8: grid handles,
+                                         batches, servers, device-buffer steps  */
+#define NASCH_MAX_VMAX_AGENT 254u     /* the agent form takes any vmax up to 254
+                                         (0xFF marks an empty cell)           */
 #define NASCH_MAX_L     0x7FFFFFFFull /* L < 2^31: positions are int32         */
 
 /* ---- option values ----------------------------------------------------- */
@@ -152,8 +156,10 @@ void nasch_default_opts(nasch_opts* opts);
 
 /*
  * Create a simulation of N cars on a ring of L cells, initialised as described
- * above (t = 0).  Requires 1 <= L < 2^31, N <= L, vmax <= 8, 0 <= p < 1 (the
- * range the paper gives for p, Handout bullet list on drawing r), p not NaN.
+ * above (t = 0).  Requires 1 <= L < 2^31, N <= L, 0 <= p < 1 (the range the
+ * paper gives for p, Handout bullet list on drawing r), p not NaN, and
+ * vmax <= 8 for the grid form (NASCH_MAX_VMAX) or vmax <= 254 for the agent
+ * form (NASCH_MAX_VMAX_AGENT; the paper leaves vmax free).
  * opts may be NULL (defaults).  On success *out is a new handle; on failure
  * *out is NULL and nothing is leaked.
  */

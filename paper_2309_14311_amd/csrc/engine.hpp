@@ -41,10 +41,11 @@ struct HipStatus {
 
 inline uint32_t threshold_of(double p) { return (uint32_t)std::floor(p * 4294967296.0); }
 
-inline int validate_params(uint64_t L, uint64_t N, uint32_t vmax, double p) {
+inline int validate_params(uint64_t L, uint64_t N, uint32_t vmax, double p,
+                           uint32_t max_vmax = NASCH_MAX_VMAX) {
     if (L < 1 || L > NASCH_MAX_L) return NASCH_EINVAL;
     if (N > L) return NASCH_EINVAL;
-    if (vmax > NASCH_MAX_VMAX) return NASCH_EINVAL;
+    if (vmax > max_vmax) return NASCH_EINVAL;
     if (!(p >= 0.0 && p < 1.0)) return NASCH_EINVAL;  // also rejects NaN
     return NASCH_OK;
 }

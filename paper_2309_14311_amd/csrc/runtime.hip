@@ -335,11 +335,13 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
                const nasch_opts* opts) {
     if (!out) return NASCH_EINVAL;
     *out = nullptr;
-    int rc = validate_params(L, N, vmax, p);
-    if (rc) return rc;
     nasch_opts o;
     nasch_default_opts(&o);
     if (opts) o = *opts;
+    // the agent form's kernels take any vmax up to 254, the grid form's up to 8
+    int rc = validate_params(L, N, vmax, p,
+                             o.rep == NASCH_REP_AGENT ? NASCH_MAX_VMAX_AGENT : NASCH_MAX_VMAX);
+    if (rc) return rc;
     if (o.rep > NASCH_REP_AGENT || o.init_v > NASCH_INIT_V_UNIFORM || o.kernel > NASCH_KERNEL_KSTEP ||
         o.rng > NASCH_RNG_STREAM)
         return NASCH_EINVAL;

@@ -365,3 +365,26 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(NaschError):
         s.set_tuning("kstep", k=10000, q=1)
     s.close()
+
+
+@pytest.mark.parametrize("vmax", [9, 31, 254])
+@pytest.mark.parametrize("L,N", [(20011, 200), (20011, 3001), (300, 7)])
+def test_agent_form_any_vmax(vmax, L, N):
+    """The agent form takes any vmax up to 254 (the paper leaves it free; only
+    0xFF is reserved for an empty cell): k-step and one-step against the
+    oracle on a sparse road (long gaps, speeds up to vmax), a denser one and a
+    short ring, with ties in the draws (p = 0.13) and without (p = 0.25)."""
+    for p in (0.13, 0.25):
+        _run_and_compare(L, N, vmax, p, 5, 60, rep="agent", kernel="kstep", init_v=1)
+        _run_and_compare(L, N, vmax, p, 5, 15, rep="agent", kernel="onestep", init_v=1)
+
+
+def test_grid_form_refuses_vmax_beyond_its_kernels():
+    """The grid form's bit planes stop at vmax = 8; 9 is an argument error there,
+    and 255 (the empty-cell code) in either form."""
+    with pytest.raises(NaschError):
+        Sim(1000, 100, 9, 0.1, 1)
+    with pytest.raises(NaschError):
+        Sim(1000, 100, 255, 0.1, 1, rep="agent")
+    Sim(1000, 100, 8, 0.1, 1).close()
+    Sim(1000, 100, 254, 0.1, 1, rep="agent").close()

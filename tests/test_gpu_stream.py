@@ -87,3 +87,19 @@ def test_stream_mode_far_into_the_stream(far_stream_case, kernel, k):
     np.testing.assert_array_equal(v, vo)
     np.testing.assert_array_equal(s.flux(c["t0"], c["T"]), fo)
     s.close()
+
+
+@pytest.mark.parametrize("vmax", [9, 254])
+@pytest.mark.parametrize("kernel,k", [("onestep", 0), ("kstep", 16)])
+def test_stream_mode_any_vmax(vmax, kernel, k):
+    """The shared stream with vmax beyond the grid form's 8 (the agent form
+    takes any vmax up to 254), against the serial oracle."""
+    L, N, p, seed, T = 20011, 400, 0.3, 9, 80
+    xo, vo, fo = _oracle(L, N, vmax, p, seed, T)
+    s = Sim(L, N, vmax, p, seed, rep="agent", rng="stream", init_v=1, kernel=kernel, k=k)
+    s.step(T)
+    x, v = s.agent_state()
+    np.testing.assert_array_equal(x, xo)
+    np.testing.assert_array_equal(v, vo)
+    np.testing.assert_array_equal(s.flux(0, T), fo)
+    s.close()
