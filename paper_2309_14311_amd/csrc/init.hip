@@ -307,8 +307,10 @@ hipError_t launch_agent_to_grid(const int32_t* x, const uint8_t* v, uint32_t N, 
 // The kernels leave F(t) per item and step in partials[s * n_items + item]; the
 // fold adds them up.  Block (r, s, c) sums chunk c (kFoldChunk items) of ring
 // log_rings[r] for step s and adds it to the ring's (zero-initialised) log
-// entry: a handful of atomics per step instead of one per item.
-constexpr uint32_t kFoldChunk = 4096;
+// entry: a handful of atomics per step instead of one per item.  Chunks of
+// 1024 items (4 per thread) keep a step's fold short: with 4096 it took 9 us of
+// the agent one-step's 127 us on the 2^28 ring.
+constexpr uint32_t kFoldChunk = 1024;
 
 __device__ __forceinline__ unsigned long long block_sum(const uint32_t* p, uint32_t n) {
     __shared__ unsigned long long part[4];
