@@ -35,6 +35,7 @@ struct nasch_batch {
     InitRing* d_init_rings = nullptr;     // placement of every replica, one launch
     InitChunk* d_init_chunks = nullptr;
     uint32_t n_init_chunks = 0;
+    uint32_t* d_init_tabs = nullptr;      // every replica's placement round-function table
     ConvJob* d_conv_jobs = nullptr;       // byte grid -> planes pl[0] of every replica
     ConvChunk* d_conv_chunks = nullptr;
     uint32_t n_conv_chunks = 0;
@@ -51,7 +52,7 @@ struct nasch_batch {
         graphs.clear();
         eng.release();
         void* ps[] = {arena, d_acc, d_log, d_clk, d_init_rings, d_init_chunks, d_conv_jobs,
-                      d_conv_chunks};
+                      d_conv_chunks, d_init_tabs};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -139,6 +140,12 @@ int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
     if (!b->ok(hipMemcpyAsync(b->d_clk, &c0, sizeof(Clock), hipMemcpyHostToDevice, b->stream)))
         return NASCH_EDEVICE;
     uint32_t vmax_all = 0;
+    // the placement tables (filled once: they depend on L, seed and replica only)
+    uint64_t tab_words = 0;
+    for (uint32_t r = 0; r < R; ++r) tab_words += init_tab_words(feistel_bits(reps[r].L));
+    if (!b->ok(dev_alloc(&b->d_init_tabs, tab_words))) return NASCH_ENOMEM;
+    uint64_t tab_off = 0;
+    std::vector<InitChunk> tab_chunks;
     std::vector<InitRing> init_rings;
     std::vector<InitChunk> init_chunks;
     std::vector<ConvJob> conv_jobs;
@@ -167,8 +174,11 @@ int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
         }
         b->eng.rings.push_back(d);
         vmax_all = std::max(vmax_all, p.vmax);
+        const uint32_t fb = feistel_bits(p.L);
         init_rings.push_back(InitRing{d.buf[0], (uint32_t)p.L, (uint32_t)p.N, p.vmax, p.init_v,
-                                      feistel_bits(p.L), 0u, d.sp});
+                                      fb, 0u, d.sp, b->d_init_tabs + tab_off});
+        for (uint64_t e = 0; e < init_tab_words(fb); e += 256) tab_chunks.push_back(InitChunk{r, (uint32_t)e});
+        tab_off += init_tab_words(fb);
         for (uint64_t c = 0; c < p.N; c += kInitChunk) init_chunks.push_back(InitChunk{r, (uint32_t)c});
         conv_jobs.push_back(ConvJob{d.buf[0], d.pl[0], d.L, d.nw, d.vmax, 0u});
         for (uint32_t w = 0; w < d.nw; w += kConvChunk) conv_chunks.push_back(ConvChunk{r, w});
@@ -191,6 +201,18 @@ int nasch_batch_init(nasch_batch** out, const nasch_replica* reps, uint32_t R,
          !b->ok(hipMemcpy(b->d_init_chunks, init_chunks.data(),
                           init_chunks.size() * sizeof(InitChunk), hipMemcpyHostToDevice))))
         return NASCH_EDEVICE;
+    {
+        InitChunk* d_tab_chunks = nullptr;
+        if (!b->ok(dev_alloc(&d_tab_chunks, tab_chunks.size()))) return NASCH_ENOMEM;
+        const bool filled =
+            b->ok(hipMemcpy(d_tab_chunks, tab_chunks.data(), tab_chunks.size() * sizeof(InitChunk),
+                            hipMemcpyHostToDevice)) &&
+            b->ok(launch_init_tables(b->d_init_rings, d_tab_chunks, (uint32_t)tab_chunks.size(),
+                                     b->stream)) &&
+            b->ok(hipStreamSynchronize(b->stream));
+        (void)hipFree(d_tab_chunks);
+        if (!filled) return NASCH_EDEVICE;
+    }
     if (!b->init_state()) return NASCH_EDEVICE;
     uint32_t q = o.q ? o.q : 4u;
     uint32_t k = o.k ? o.k : std::min(32u, std::max(1u, kstep_max_k(vmax_all, q)));

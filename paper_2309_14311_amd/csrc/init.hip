@@ -10,24 +10,37 @@ namespace nasch {
 // 64, so a lane whose car has landed takes the next car of the wave's range
 // instead of idling: the wave's work is the sum of the walks, not 64 times
 // their maximum.
-__global__ __launch_bounds__(256) void init_scatter_kernel(const InitRing* __restrict__ rings,
-                                                           const InitChunk* __restrict__ chunks,
-                                                           InitRing single) {
-    const InitChunk c = chunks ? chunks[blockIdx.x] : InitChunk{0u, blockIdx.x * kInitChunk};
-    const InitRing R = chunks ? rings[c.ring] : single;
-    constexpr uint32_t kPerWave = kInitChunk / 4;   // 256 threads: four waves
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t begin =
-        c.first + kPerWave * (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t end = min(begin + kPerWave, R.N);
-    if (begin >= end) return;   // uniform over the wave
-    const uint32_t half = R.b >> 1;
-    const uint32_t mask = (half >= 32) ? 0xFFFFFFFFu : ((1u << half) - 1u);
+//
+// A Feistel round sees only 2^(b/2) inputs, so when the ring has a table of
+// its round functions (InitRing::tab, filled by init_table_kernel) a walk is
+// four table reads instead of four Philox calls: the block copies a table of
+// at most kInitLdsTab words into LDS, a larger one is read from global memory
+// (L2).  Without a table the rounds are computed.
+constexpr uint32_t kInitLdsTab = 4096;   // 4 rounds x 1024 inputs: b <= 20, L <= 2^20
+
+// Table reads of the round function (an LDS or a global table).
+struct LdsRound {
+    const uint32_t* t;
+    uint32_t half;
+    __device__ uint32_t operator()(uint32_t r, uint32_t j) const { return t[(j << half) | r]; }
+};
+struct GlobalRound {
+    const uint32_t* t;
+    uint32_t half;
+    __device__ uint32_t operator()(uint32_t r, uint32_t j) const {
+        return *gmem(t + ((j << half) | r));
+    }
+};
+
+template <class Round>
+__device__ __forceinline__ void scatter_range(const InitRing& R, uint32_t begin, uint32_t end,
+                                              uint32_t lane, uint32_t half, uint32_t mask,
+                                              const Round& round) {
     uint32_t y = begin + lane;      // the lane's car, then its walk
     bool active = y < end;
     uint32_t next = begin + 64u;    // first car not yet taken (uniform)
     while (__builtin_amdgcn_ballot_w64(active) != 0u) {
-        y = feistel_fwd(y, half, mask, R.sp);
+        y = feistel_fwd_by(y, half, mask, round);
         const bool done = active && y < R.L;
         if (done) R.g[y] = (uint8_t)(R.init_v ? initial_velocity(y, R.vmax, R.sp) : 0u);
         const bool take = done || !active;
@@ -42,6 +55,44 @@ __global__ __launch_bounds__(256) void init_scatter_kernel(const InitRing* __res
     }
 }
 
+__global__ __launch_bounds__(256) void init_scatter_kernel(const InitRing* __restrict__ rings,
+                                                           const InitChunk* __restrict__ chunks,
+                                                           InitRing single) {
+    __shared__ uint32_t s_tab[kInitLdsTab];
+    const InitChunk c = chunks ? chunks[blockIdx.x] : InitChunk{0u, blockIdx.x * kInitChunk};
+    const InitRing R = chunks ? rings[c.ring] : single;
+    const uint32_t half = R.b >> 1;
+    const uint32_t mask = (half >= 32) ? 0xFFFFFFFFu : ((1u << half) - 1u);
+    const uint64_t ntab = init_tab_words(R.b);
+    const bool lds_tab = R.tab && ntab <= kInitLdsTab;   // uniform over the block
+    if (lds_tab) {
+        for (uint32_t e = threadIdx.x; e < (uint32_t)ntab; e += 256u) s_tab[e] = *gmem(R.tab + e);
+        __syncthreads();
+    }
+    constexpr uint32_t kPerWave = kInitChunk / 4;   // 256 threads: four waves
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t begin =
+        c.first + kPerWave * (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t end = min(begin + kPerWave, R.N);
+    if (begin >= end) return;   // uniform over the wave
+    if (lds_tab) scatter_range(R, begin, end, lane, half, mask, LdsRound{s_tab, half});
+    else if (R.tab) scatter_range(R, begin, end, lane, half, mask, GlobalRound{R.tab, half});
+    else scatter_range(R, begin, end, lane, half, mask, PhiloxRound{R.sp, mask});
+}
+
+// Round-function tables: entry e = j 2^half + r of a ring's table is F_j(r).
+__global__ __launch_bounds__(256) void init_table_kernel(const InitRing* __restrict__ rings,
+                                                         const InitChunk* __restrict__ chunks,
+                                                         InitRing single) {
+    const InitChunk c = chunks ? chunks[blockIdx.x] : InitChunk{0u, blockIdx.x * 256u};
+    const InitRing R = chunks ? rings[c.ring] : single;
+    const uint32_t half = R.b >> 1;
+    const uint32_t mask = (half >= 32) ? 0xFFFFFFFFu : ((1u << half) - 1u);
+    const uint32_t e = c.first + threadIdx.x;
+    if (!R.tab || (uint64_t)e >= init_tab_words(R.b)) return;
+    *gmem(R.tab + e) = feistel_round(e & mask, e >> half, mask, R.sp);
+}
+
 hipError_t launch_init_scatter(const InitRing* rings, const InitChunk* chunks, uint32_t n_chunks,
                                hipStream_t s) {
     if (n_chunks == 0) return hipSuccess;
@@ -49,11 +100,25 @@ hipError_t launch_init_scatter(const InitRing* rings, const InitChunk* chunks, u
     return hipGetLastError();
 }
 
+hipError_t launch_init_tables(const InitRing* rings, const InitChunk* chunks, uint32_t n_chunks,
+                              hipStream_t s) {
+    if (n_chunks == 0) return hipSuccess;
+    NASCH_LAUNCH(init_table_kernel, dim3(n_chunks), dim3(256), 0, s, rings, chunks, InitRing{});
+    return hipGetLastError();
+}
+
 hipError_t launch_init_grid(uint8_t* g, uint32_t L, uint32_t N, uint32_t vmax, uint32_t init_v,
-                            SlowParams sp, hipStream_t s) {
+                            SlowParams sp, hipStream_t s, uint32_t* tab) {
     hipError_t e = launch_fill_u8(g, L, (uint8_t)kEmpty, s);
     if (e != hipSuccess || N == 0) return e;
-    InitRing r{g, L, N, vmax, init_v, feistel_bits(L), 0u, sp};
+    InitRing r{g, L, N, vmax, init_v, feistel_bits(L), 0u, sp, tab};
+    if (tab) {
+        const uint64_t n = init_tab_words(r.b);
+        NASCH_LAUNCH(init_table_kernel, dim3((uint32_t)((n + 255u) / 256u)), dim3(256), 0, s,
+                     nullptr, nullptr, r);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const uint32_t chunks = (N + kInitChunk - 1) / kInitChunk;
     NASCH_LAUNCH(init_scatter_kernel, dim3(chunks), dim3(256), 0, s, nullptr, nullptr, r);
     return hipGetLastError();

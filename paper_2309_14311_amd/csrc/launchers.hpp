@@ -18,9 +18,14 @@ namespace nasch {
 
 // ---- init (init.hip) ----------------------------------------------------------
 // Grid at t = 0 for cells [0, L): EMPTY, or the initial velocity where the
-// placement puts a car.
+// placement puts a car.  `tab` (init_tab_words(feistel_bits(L)) words, or
+// null) receives the placement's round-function table on the way.
 hipError_t launch_init_grid(uint8_t* g, uint32_t L, uint32_t N, uint32_t vmax, uint32_t init_v,
-                            SlowParams sp, hipStream_t s);
+                            SlowParams sp, hipStream_t s, uint32_t* tab = nullptr);
+// Fill the round-function tables of the rings whose tab is set: chunk c fills
+// entries [chunks[c].first, +256) of ring chunks[c].ring's table.
+hipError_t launch_init_tables(const InitRing* rings, const InitChunk* chunks, uint32_t n_chunks,
+                              hipStream_t s);
 // Scatter the cars of many rings (grids must already be EMPTY): one thread per
 // car, chunk c places cars [chunks[c].first, +kInitChunk) of ring chunks[c].ring.
 hipError_t launch_init_scatter(const InitRing* rings, const InitChunk* chunks, uint32_t n_chunks,

@@ -153,6 +153,12 @@ __host__ __device__ inline uint32_t feistel_bits(uint64_t L) {
     return b < 2 ? 2 : b;
 }
 
+// Round function j of the placement permutation: F_j(r), r < 2^half.
+__device__ __forceinline__ uint32_t feistel_round(uint32_t r, uint32_t j, uint32_t mask,
+                                                  const SlowParams& sp) {
+    return philox(r, j, sp.replica, kTagPlace, sp.k0, sp.k1).w0 & mask;
+}
+
 // Inverse of the 4-round Feistel permutation on b bits: forward round j maps
 // (l, r) to (r, l ^ F_j(r)); undo rounds 3..0.
 __device__ __forceinline__ uint32_t feistel_inv(uint32_t y, uint32_t half, uint32_t mask,
@@ -160,7 +166,7 @@ __device__ __forceinline__ uint32_t feistel_inv(uint32_t y, uint32_t half, uint3
     uint32_t l = (y >> half) & mask, r = y & mask;
 #pragma unroll
     for (int j = 3; j >= 0; --j) {
-        const uint32_t f = philox(l, (uint32_t)j, sp.replica, kTagPlace, sp.k0, sp.k1).w0 & mask;
+        const uint32_t f = feistel_round(l, (uint32_t)j, mask, sp);
         const uint32_t pr = l;
         l = r ^ f;
         r = pr;
@@ -169,18 +175,33 @@ __device__ __forceinline__ uint32_t feistel_inv(uint32_t y, uint32_t half, uint3
 }
 
 // Forward 4-round Feistel permutation on b bits: round j maps (l, r) to
-// (r, l ^ F_j(r)).
-__device__ __forceinline__ uint32_t feistel_fwd(uint32_t i, uint32_t half, uint32_t mask,
-                                                const SlowParams& sp) {
+// (r, l ^ F_j(r)), with F_j(r) = round(r, j) (feistel_round, or a table of its
+// values: a round sees only 2^half inputs).
+template <class Round>
+__device__ __forceinline__ uint32_t feistel_fwd_by(uint32_t i, uint32_t half, uint32_t mask,
+                                                   const Round& round) {
     uint32_t l = (i >> half) & mask, r = i & mask;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const uint32_t f = philox(r, (uint32_t)j, sp.replica, kTagPlace, sp.k0, sp.k1).w0 & mask;
+        const uint32_t f = round(r, (uint32_t)j);
         const uint32_t nl = r;
         r = l ^ f;
         l = nl;
     }
     return (l << half) | r;
+}
+
+struct PhiloxRound {
+    SlowParams sp;
+    uint32_t mask;
+    __device__ uint32_t operator()(uint32_t r, uint32_t j) const {
+        return feistel_round(r, j, mask, sp);
+    }
+};
+
+__device__ __forceinline__ uint32_t feistel_fwd(uint32_t i, uint32_t half, uint32_t mask,
+                                                const SlowParams& sp) {
+    return feistel_fwd_by(i, half, mask, PhiloxRound{sp, mask});
 }
 
 // Cell of car i: the Feistel permutation cycle-walked until it lands in [0, L).
@@ -266,7 +287,11 @@ struct InitRing {
     uint32_t b;              // Feistel width
     uint32_t pad;
     SlowParams sp;
+    uint32_t* tab;           // the placement's round-function table (init_tab_words(b)
+                             // words, filled by launch_init_tables), or null: computed
 };
+// Words of a ring's placement table: 4 rounds x 2^(b/2) inputs.
+__host__ __device__ inline uint64_t init_tab_words(uint32_t b) { return 4ull << (b >> 1); }
 // kInitChunk consecutive cars of one ring.
 struct InitChunk {
     uint32_t ring;

@@ -377,8 +377,16 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
     uint8_t* g0 = nullptr;
     if (!h->ok(dev_alloc(&h->grid[0], L))) return NASCH_ENOMEM;
     g0 = h->grid[0];
-    if (!h->ok(launch_init_grid(g0, (uint32_t)L, (uint32_t)N, vmax, o.init_v, sp, h->stream)))
-        return NASCH_EDEVICE;
+    {
+        // the placement's round-function table, for the init only (stream-ordered)
+        uint32_t* tab = nullptr;
+        const size_t tb = init_tab_words(feistel_bits(L)) * sizeof(uint32_t);
+        if (!h->ok(hipMallocAsync((void**)&tab, tb, h->stream))) return NASCH_ENOMEM;
+        const bool placed =
+            h->ok(launch_init_grid(g0, (uint32_t)L, (uint32_t)N, vmax, o.init_v, sp, h->stream, tab));
+        const bool freed = h->ok(hipFreeAsync(tab, h->stream));
+        if (!placed || !freed) return NASCH_EDEVICE;
+    }
     h->dev_bytes += L;
 
     if (o.rep == NASCH_REP_GRID) {

@@ -140,6 +140,7 @@ struct nasch_server {
     uint8_t* arena_base = nullptr;
     Arena arena;
     Clock* d_clk = nullptr;   // stays {0, 0}: each slot carries its own t and parity
+    uint32_t* d_init_tab = nullptr;   // placement round-function table of an admission
     GridEngine eng;           // the large rings
     GridEngine eng_s;         // the small rings
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -180,7 +181,8 @@ nasch_server::Admit nasch_server::admit_one(Job& j) {
     const SlowParams sp = slow_params(r.seed, r.replica, r.p);
     const ConvJob job{base, reinterpret_cast<uint32_t*>(base + grid_bytes(r)), (uint32_t)r.L,
                       plane_words(r.L), r.vmax, 0u};
-    if (!st.ok(launch_init_grid(base, (uint32_t)r.L, (uint32_t)r.N, r.vmax, r.init_v, sp, stream)) ||
+    if (!st.ok(launch_init_grid(base, (uint32_t)r.L, (uint32_t)r.N, r.vmax, r.init_v, sp, stream,
+                                d_init_tab)) ||
         !st.ok(launch_bytes_to_planes_one(job, stream)) ||
         !st.ok(launch_fill_u64(reinterpret_cast<unsigned long long*>(base + log_offset(r)), r.T,
                                stream))) {
@@ -479,6 +481,9 @@ int nasch_server_create(nasch_server** out, const nasch_server_opts* opts) {
     if (!s->st.ok(dev_alloc(&s->arena_base, o.hbm_budget))) return NASCH_ENOMEM;
     s->arena.reset(o.hbm_budget);
     if (!s->st.ok(dev_alloc(&s->d_clk, 1))) return NASCH_ENOMEM;
+    // one placement table serves every admission (they run in order on one stream)
+    if (!s->st.ok(dev_alloc(&s->d_init_tab, init_tab_words(feistel_bits(NASCH_MAX_L)))))
+        return NASCH_ENOMEM;
     const Clock c0{0u, 0u};
     if (!s->st.ok(hipMemcpy(s->d_clk, &c0, sizeof(Clock), hipMemcpyHostToDevice))) return NASCH_EDEVICE;
     int dev = 0;
@@ -580,6 +585,7 @@ void nasch_server_destroy(nasch_server* s) {
     s->eng_s.release();
     if (s->arena_base) (void)hipFree(s->arena_base);
     if (s->d_clk) (void)hipFree(s->d_clk);
+    if (s->d_init_tab) (void)hipFree(s->d_init_tab);
     if (s->ev_admit) (void)hipEventDestroy(s->ev_admit);
     if (s->ev_small) (void)hipEventDestroy(s->ev_small);
     if (s->stream_s) (void)hipStreamDestroy(s->stream_s);
