@@ -20,8 +20,9 @@
 // wave reads it with two loads of 16 bytes per lane (each 1 KiB contiguous, the
 // fastest form measured here) and regroups the bytes into the lanes' 32-byte
 // words through 2 KiB of LDS per wave, and writes a whole tile back the same way
-// (its halo words' chunks masked off).  Loading each lane's own 32 bytes
-// directly (two 16-byte loads 32 bytes apart) measured 4 % slower.
+// (its halo words' chunks masked off) with non-temporal stores (1 % faster
+// than plain ones here).  Loading each lane's own 32 bytes directly (two
+// 16-byte loads 32 bytes apart) measured 4 % slower.
 //
 // Streaming.  One tile per wave and one launch over all tiles: on this GPU a
 // launch whose waves each move one tile and exit streams faster (5.8 TB/s for
@@ -222,8 +223,8 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
         const u32x4 a = *reinterpret_cast<const u32x4*>(stage + 4u * lane);
         const u32x4 b = *reinterpret_cast<const u32x4*>(stage + 256u + 4u * lane);
         uint8_t* base = dst + g.s0;
-        if (lane >= 2u) *gmem(reinterpret_cast<u32x4*>(base + 16u * lane)) = a;
-        if (lane < 62u) *gmem(reinterpret_cast<u32x4*>(base + 1024u + 16u * lane)) = b;
+        if (lane >= 2u) __builtin_nontemporal_store(a, reinterpret_cast<u32x4*>(base + 16u * lane));
+        if (lane < 62u) __builtin_nontemporal_store(b, reinterpret_cast<u32x4*>(base + 1024u + 16u * lane));
         return fl;
     }
 #pragma unroll
