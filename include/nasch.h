@@ -266,10 +266,10 @@ int nasch_grid_step_device(const uint8_t* d_in, uint8_t* d_out, uint64_t L, uint
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * step as nasch_grid_step_device, same arguments, layout, ownership and
  * errors, but it allocates nothing.  Its scratch (one uint32 flux partial per
- * block of eight 1984-cell tiles, and the fold's per-block sums and counter) is
- * a static device array of 135431 words (about 0.5 MiB) that each device the
- * library runs on holds until the process ends; every L the library accepts
- * fits it (a launch needing more would be NASCH_EINVAL).
+ * block of eight 1984-cell tiles) is a static device array of 135301 words
+ * (about 0.5 MiB) that each device the library runs on holds until the
+ * process ends; every L the library accepts fits it (a launch needing more
+ * would be NASCH_EINVAL).
  * All calls on one device share that array, so calls that overlap on one
  * device (different streams, or threads without ordering) race and must not
  * be issued; calls ordered on one stream are safe.  The array's contents

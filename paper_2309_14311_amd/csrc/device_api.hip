@@ -3,7 +3,7 @@
 // in the library.  A caller that keeps its roads in its own buffers (torch
 // tensors, an arena of its own) steps them in place of nasch_init /
 // nasch_step_n.  The step is the one-step kernel (grid_onestep.hip) launched
-// on a ring described by value; F(t) is folded from per-wave partials into the
+// on a ring described by value; F(t) is folded from per-block sums into the
 // caller's uint64.
 #include <hip/hip_runtime.h>
 
@@ -67,11 +67,8 @@ int nasch_grid_step_device(const uint8_t* d_in, uint8_t* d_out, uint64_t L, uint
         thread_last_hip_error() = (int)e;
         return NASCH_ENOMEM;
     }
-    // the fold's counter, the scratch's first word, starts at 0
-    e = launch_fill_u8(reinterpret_cast<uint8_t*>(partials), sizeof(uint32_t), 0u, s);
-    if (e == hipSuccess)
-        e = launch_grid_onestep_direct(R, partials, (uint32_t)t,
-                                       reinterpret_cast<unsigned long long*>(d_flux), s);
+    e = launch_grid_onestep_direct(R, partials, (uint32_t)t,
+                                   reinterpret_cast<unsigned long long*>(d_flux), s);
     const hipError_t ef = hipFreeAsync(partials, s);
     if (e != hipSuccess) return device_error(e);
     if (ef != hipSuccess) return device_error(ef);

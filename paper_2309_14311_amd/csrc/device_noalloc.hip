@@ -1,8 +1,7 @@
 // device_noalloc.hip -- nasch_grid_step_device_noalloc: the device-buffer step
 // of device_api.hip for callers that must not allocate (code under HIP graph
 // capture, tight serving loops, harnesses that forbid hipMalloc).  Its only
-// scratch, the per-block F(t) partials and the fold's stage and counter, lives
-// in a file-scope device array
+// scratch, the per-block F(t) partials, lives in a file-scope device array
 // instead of a stream-ordered allocation; the call itself allocates nothing.
 //
 // In host code `scratch` names a host-side stand-in, not device memory: its
@@ -21,18 +20,16 @@
 using namespace nasch;
 
 namespace {
-// The fold's counter and per-block sums, then one uint32 F(t) partial per block
-// of 8 tiles (one per wave) of 1984 cells, for the longest ring
-// (L = 2^31 - 1): about 0.5 MiB.
+// One uint32 F(t) partial per block of 8 tiles (one per wave) of 1984 cells,
+// for the longest ring (L = 2^31 - 1): about 0.5 MiB.
 constexpr uint32_t kTileCells = 32u * (64u * kOneStepQ - 2u);
 constexpr uint32_t kTilesPerBlock = kOneStepThreads / 64u;
-constexpr uint32_t kMaxBlocks = (uint32_t)(((NASCH_MAX_L + kTileCells - 1u) / kTileCells +
-                                            kTilesPerBlock - 1u) / kTilesPerBlock);
-constexpr uint32_t kScratchWords = kFoldScratchWords + kMaxBlocks;
+constexpr uint32_t kScratchWords = (uint32_t)(((NASCH_MAX_L + kTileCells - 1u) / kTileCells +
+                                               kTilesPerBlock - 1u) / kTilesPerBlock);
 }  // namespace
 
-// The scratch of every call on a device: F(t) partials and the fold's counter,
-// which static storage starts at 0 and every fold leaves at 0.
+// The scratch of every call on a device: the F(t) partials of the step's
+// blocks, each written before the fold reads it.
 static __device__ __align__(256) uint32_t scratch[kScratchWords];
 
 namespace {

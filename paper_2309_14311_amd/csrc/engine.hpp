@@ -211,7 +211,8 @@ struct GridEngine {
         hipError_t e = upload_rings(s);
         if (e != hipSuccess) return e;
         size_t np = items.size() * (size_t)kk;
-        if (onestep && !rings.empty()) np = std::max<size_t>(np, onestep_partials(rings[0].ntiles));
+        if (onestep && !rings.empty())
+            np = std::max<size_t>(np, 2u * (size_t)onestep_partials(rings[0].ntiles));
         if (np > partials_cap) {
             if (d_partials) (void)hipFree(d_partials);
             d_partials = nullptr;
@@ -219,7 +220,7 @@ struct GridEngine {
             e = dev_alloc(&d_partials, np);
             if (e != hipSuccess) return e;
             partials_cap = np;
-            // the one-step fold's counter (and everything else) starts at 0
+            // start from zeros
             e = launch_fill_u8(reinterpret_cast<uint8_t*>(d_partials), np * sizeof(uint32_t), 0u,
                                s);
             if (e != hipSuccess) return e;
@@ -285,9 +286,10 @@ struct GridEngine {
         for (uint32_t i = 0; i < n; ++i) {
             const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
             if (onestep) {
-                // one ring; F(t) folded by the launch itself
+                // one ring; F(t) of each launch folded by the next one
                 hipError_t e = launch_grid_onestep(launch_vmax, rings[0].ntiles, d_rings,
-                                                   d_partials, n_log_rings != 0, d_clk, i, i, s);
+                                                   d_partials, n_log_rings != 0, d_clk, i, i,
+                                                   i == 0, i + 1 == n, s);
                 if (e != hipSuccess) return e;
                 continue;
             }

@@ -31,8 +31,13 @@
 // tiles per wave measured slower too.  The 8 waves of a block take 8
 // consecutive tiles and add their F(t) into one partial (blocks of 1, 2, 4
 // and 16 waves measured 9, 4, 2 and 1 % slower); blocks dealt to one XCD (the
-// 8 XCDs take blocks in turn) take consecutive tiles.  A fold kernel sums the
-// partials.
+// 8 XCDs take blocks in turn) take consecutive tiles.
+//
+// F(t).  Each block stores its sum as one partial; the first waves of the
+// first 64 blocks of the next launch add the partials up in 64 chunks, each
+// into the log entry with one atomic add (a launch of their own after the
+// last step).  Consecutive launches alternate between two sets of partials.
+// A fold kernel of its own after every step cost 7 us of each step.
 //
 // Segment cell i is ring cell (own_start - 32 + i) mod L.  A tile whose
 // segment lies inside [0, L) is the common case and takes aligned 16-byte
@@ -240,7 +245,7 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
 // Step t of tile 8 b + wave of ring R (b: the block's tile group), from
 // R.buf[par] to R.buf[par ^ 1].  The block's F(t) goes to *partial (if not
 // null), to *whole (if not null: a launch of one block, whose F(t) is the
-// ring's) and, from the warm-up on, into R.flux_acc.
+// ring's) and, from the warm-up on, is added into R.flux_acc.
 template <int VMAX, int Q>
 __device__ __forceinline__ void os_block(const RingDesc& R, uint32_t b, uint32_t t, uint32_t par,
                                          uint32_t* __restrict__ partial,
@@ -275,29 +280,55 @@ __device__ __forceinline__ void os_block(const RingDesc& R, uint32_t b, uint32_t
     }
 }
 
+// Chunk c of m (m <= 64 chunks) of a launch's n partials, added by one wave
+// (all 64 lanes active).  A partial is below 2^17 (8 tiles of 1984 cells at
+// speed <= 8) and a chunk holds at most 2^12 of them, so 32 bits suffice.
+__device__ __forceinline__ uint32_t chunk_sum(const uint32_t* __restrict__ partials, uint32_t n,
+                                              uint32_t c, uint32_t m, uint32_t lane) {
+    const uint32_t per = (n + m - 1u) / m;
+    const uint32_t lo = min(c * per, n), hi = min(lo + per, n);
+    uint32_t acc = 0u;
+    for (uint32_t i = lo + lane; i < hi; i += 64u) acc += partials[i];
+    return wave_total(acc);
+}
+
 }  // namespace
 
 // One step of a ring (RingDesc at `ring`, step and buffer parity from the
-// device clock), F(t) partials of every block in partials[block].
+// device clock).  With a flux log and more than one block, every block stores
+// its F(t) in partial set launch_idx of `scratch` (sets of gridDim.x words),
+// and (fold_prev) the first wave of each of the first 64 blocks first adds a
+// chunk of the previous launch's set into its log entry.
 template <int VMAX, int Q>
 __global__ __launch_bounds__(kOneStepThreads) void grid_onestep_kernel(
-    const RingDesc* __restrict__ ring, uint32_t* __restrict__ partials,
-    const Clock* __restrict__ clk, uint32_t s_off, uint32_t launch_idx) {
+    const RingDesc* __restrict__ ring, uint32_t* __restrict__ scratch,
+    const Clock* __restrict__ clk, uint32_t s_off, uint32_t launch_idx, uint32_t fold_prev) {
     __shared__ RefineLds<Q> s_ref[kOsWaves];
     __shared__ uint32_t s_flux[kOsWaves];
     __shared__ uint32_t s_stage[kOsWaves * 512];
-    const uint32_t b = xcd_item(blockIdx.x, gridDim.x);
     const RingDesc& R = *ring;
     const uint32_t t = clk->t + R.t + s_off;
+    const uint32_t nb = gridDim.x;
+    const uint32_t m = min(kFoldBlocks, nb);
+    if (fold_prev && blockIdx.x < m && threadIdx.x < 64u) {
+        const uint32_t f = chunk_sum(scratch + (size_t)((launch_idx + 1u) & 1u) * nb, nb,
+                                     blockIdx.x, m, threadIdx.x);
+        if (threadIdx.x == 0u && f)
+            atomicAdd(&R.flux_log[(uint64_t)t - 1u - R.log_t0], (unsigned long long)f);
+    }
+    const uint32_t b = xcd_item(blockIdx.x, nb);
     const uint32_t par = (clk->parity + R.parity + launch_idx) & 1u;
-    // one block (a ring of at most 4 tiles) writes F(t) itself: no fold launch
-    const bool one = gridDim.x == 1u && R.flux_log;
-    os_block<VMAX, Q>(R, b, t, par, R.flux_log && !one ? partials + b : nullptr,
+    // one block (a ring of at most 8 tiles) writes F(t) itself
+    const bool one = nb == 1u && R.flux_log;
+    os_block<VMAX, Q>(R, b, t, par,
+                      R.flux_log && !one ? scratch + (size_t)(launch_idx & 1u) * nb + blockIdx.x
+                                         : nullptr,
                       one ? R.flux_log + ((uint64_t)t - R.log_t0) : nullptr, s_ref, s_flux, s_stage);
 }
 
 // One step t of a ring described by value (buf[0] is read, buf[1] written):
-// the launch of the stateless device-buffer entry points.
+// the launch of the stateless device-buffer entry points.  With flux and more
+// than one block, *flux is cleared here and the fold adds the partials to it.
 template <int VMAX, int Q>
 __global__ __launch_bounds__(kOneStepThreads) void grid_onestep_direct_kernel(
     const RingDesc R, uint32_t* __restrict__ partials, uint32_t t,
@@ -306,67 +337,28 @@ __global__ __launch_bounds__(kOneStepThreads) void grid_onestep_direct_kernel(
     __shared__ uint32_t s_flux[kOsWaves];
     __shared__ uint32_t s_stage[kOsWaves * 512];
     const uint32_t b = xcd_item(blockIdx.x, gridDim.x);
-    // one block writes F(t) itself: no fold launch
+    // one block writes F(t) itself
     const bool one = gridDim.x == 1u;
-    os_block<VMAX, Q>(R, b, t, 0u, one ? nullptr : partials + b, one ? flux : nullptr, s_ref,
-                      s_flux, s_stage);
+    if (flux && !one && blockIdx.x == 0u && threadIdx.x == 0u) *flux = 0ull;
+    os_block<VMAX, Q>(R, b, t, 0u, flux && !one ? partials + blockIdx.x : nullptr,
+                      one ? flux : nullptr, s_ref, s_flux, s_stage);
 }
 
-// F(t) = the sum of n uint32 partials, into *out or into the ring's flux log at
-// the launch's step (when ring is given).  kFoldBlocks blocks each add a
-// contiguous range and store their sum in stage[block]; the last block to
-// finish (a device-scope counter) adds the stage, one block's sum per lane,
-// writes F(t) and resets the counter for the next launch.  (Adding the stage
-// in one thread, 64 dependent loads, took 14 us of a 0.41 ms step on the 2^30
-// ring.)
-__global__ __launch_bounds__(256) void fold_partials_kernel(const uint32_t* __restrict__ partials,
-                                                            uint32_t n,
-                                                            unsigned long long* __restrict__ stage,
-                                                            uint32_t* __restrict__ counter,
-                                                            unsigned long long* __restrict__ out,
-                                                            const RingDesc* __restrict__ ring,
-                                                            const Clock* __restrict__ clk,
-                                                            uint32_t s_off) {
-    __shared__ unsigned long long s[4];
-    __shared__ bool last;
-    const uint32_t per = (n + gridDim.x - 1u) / gridDim.x;
-    const uint32_t lo = min(blockIdx.x * per, n), hi = min(lo + per, n);
-    unsigned long long acc = 0;
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256u) acc += partials[i];
-    // a block's range sums to below 2^32 only per lane; add the low 16 bits and
-    // the rest of each lane's sum separately across the wave
-    const uint32_t wl = wave_total((uint32_t)(acc & 0xFFFFu));
-    const uint32_t wh = wave_total((uint32_t)(acc >> 16));
-    if ((threadIdx.x & 63u) == 0u)
-        s[threadIdx.x >> 6] = (unsigned long long)wl + ((unsigned long long)wh << 16);
-    __syncthreads();
-    if (threadIdx.x == 0u) {
-        stage[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
-        __threadfence();
-        last = atomicAdd(counter, 1u) == gridDim.x - 1u;
+// Adds a launch's n partials into *out, or into the ring's flux log at step
+// s_off of the run (when ring is given): block c adds chunk c of gridDim.x.
+__global__ __launch_bounds__(64) void fold_partials_kernel(const uint32_t* __restrict__ partials,
+                                                           uint32_t n,
+                                                           unsigned long long* __restrict__ out,
+                                                           const RingDesc* __restrict__ ring,
+                                                           const Clock* __restrict__ clk,
+                                                           uint32_t s_off) {
+    const uint32_t f = chunk_sum(partials, n, blockIdx.x, gridDim.x, threadIdx.x);
+    if (threadIdx.x != 0u || !f) return;
+    if (ring) {
+        const uint64_t t = (uint64_t)clk->t + ring->t + s_off;
+        out = ring->flux_log + (t - ring->log_t0);
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (threadIdx.x >= 64u) return;
-    // the first wave adds the stage, one block's sum per lane (gridDim.x <= 64;
-    // a sum is below 2^35, so its bits past the low 16 add up below 2^32)
-    const unsigned long long v =
-        threadIdx.x < gridDim.x
-            ? __hip_atomic_load(&stage[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-            : 0ull;
-    const uint32_t tl = wave_total((uint32_t)(v & 0xFFFFu));
-    const uint32_t th = wave_total((uint32_t)(v >> 16));
-    if (threadIdx.x == 0u) {
-        const unsigned long long total = (unsigned long long)tl + ((unsigned long long)th << 16);
-        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (ring) {
-            const uint64_t t = (uint64_t)clk->t + ring->t + s_off;
-            ring->flux_log[t - ring->log_t0] = total;
-        } else {
-            *out = total;
-        }
-    }
+    atomicAdd(out, (unsigned long long)f);
 }
 
 namespace {
@@ -388,44 +380,40 @@ uint32_t os_blocks(uint32_t ntiles) { return std::max(1u, (ntiles + kOsWaves - 1
         default: return hipErrorInvalidValue;                                                  \
     }
 
-// The scratch of a one-step launch: word 0 the fold's counter, words 2 ..
-// 2 kFoldBlocks + 1 its per-block sums, then one partial per block of tiles.
-// The counter has a fixed place so that it stays 0 between launches of any size.
-hipError_t fold(uint32_t* scratch, uint32_t n, unsigned long long* out, const RingDesc* ring,
-                const Clock* clk, uint32_t s_off, hipStream_t s) {
-    NASCH_LAUNCH(fold_partials_kernel, dim3(std::min(kFoldBlocks, (n + 255u) / 256u)), dim3(256), 0, s,
-                 scratch + kFoldScratchWords, n,
-                 reinterpret_cast<unsigned long long*>(scratch + 2), scratch, out, ring, clk,
-                 s_off);
+hipError_t fold(const uint32_t* partials, uint32_t n, unsigned long long* out,
+                const RingDesc* ring, const Clock* clk, uint32_t s_off, hipStream_t s) {
+    NASCH_LAUNCH(fold_partials_kernel, dim3(std::min(kFoldBlocks, n)), dim3(64), 0, s, partials,
+                 n, out, ring, clk, s_off);
     return hipGetLastError();
 }
 
 }  // namespace
 
-uint32_t onestep_partials(uint32_t ntiles) { return kFoldScratchWords + os_blocks(ntiles); }
+uint32_t onestep_partials(uint32_t ntiles) { return os_blocks(ntiles); }
 
 hipError_t launch_grid_onestep(uint32_t vmax, uint32_t ntiles, const RingDesc* ring,
-                               uint32_t* partials, bool log, const Clock* clk, uint32_t s_off,
-                               uint32_t launch_idx, hipStream_t s) {
+                               uint32_t* scratch, bool log, const Clock* clk, uint32_t s_off,
+                               uint32_t launch_idx, bool first, bool last, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
     const uint32_t nb = os_blocks(ntiles);
+    const bool fold_log = log && nb > 1u;   // one block writes F(t) itself
     NASCH_OS_VMAX_SWITCH(grid_onestep_kernel, kOneStepQ, dim3(nb), dim3(kOneStepThreads), 0, s,
-                         ring, partials + kFoldScratchWords, clk, s_off, launch_idx)
+                         ring, scratch, clk, s_off, launch_idx, (fold_log && !first) ? 1u : 0u)
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !log || nb == 1u) return e;   // one block wrote F(t) itself
-    return fold(partials, nb, nullptr, ring, clk, s_off, s);
+    if (e != hipSuccess || !fold_log || !last) return e;
+    return fold(scratch + (size_t)(launch_idx & 1u) * nb, nb, nullptr, ring, clk, s_off, s);
 }
 
-hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t* partials, uint32_t t,
+hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t* scratch, uint32_t t,
                                       unsigned long long* flux, hipStream_t s) {
     if (R.ntiles == 0) return hipSuccess;
     const uint32_t vmax = R.vmax;
     const uint32_t nb = os_blocks(R.ntiles);
     NASCH_OS_VMAX_SWITCH(grid_onestep_direct_kernel, kOneStepQ, dim3(nb), dim3(kOneStepThreads),
-                         0, s, R, partials + kFoldScratchWords, t, flux)
+                         0, s, R, scratch, t, flux)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !flux || nb == 1u) return e;   // one block wrote F(t) itself
-    return fold(partials, nb, flux, nullptr, nullptr, 0u, s);
+    return fold(scratch, nb, flux, nullptr, nullptr, 0u, s);
 }
 
 #undef NASCH_OS_VMAX_SWITCH

@@ -85,10 +85,10 @@ hipError_t launch_grid_kstep_bytes(uint32_t vmax, bool open, uint32_t q, const R
 constexpr uint32_t kOneStepThreads = 512;
 // Words per lane of the one-step kernel.
 constexpr uint32_t kOneStepQ = 1;
-// The fold of a launch's F(t) partials: blocks, and the scratch words it needs
-// ahead of the partials (a counter that must start at 0, and a uint64 per block).
+// F(t) of a one-step launch: every block stores its sum as one uint32 partial,
+// and kFoldBlocks waves add the partials up in chunks (atomic adds into the
+// zero-initialised log entry).
 constexpr uint32_t kFoldBlocks = 64;
-constexpr uint32_t kFoldScratchWords = 2u + 2u * kFoldBlocks;
 // Tile geometry of the one-step kernel: owned cells per tile (a ring that fits
 // one tile is one tile owning all L cells), the one-word halo, tile count.
 inline void onestep_geometry(uint32_t L, uint32_t q, uint32_t* own, uint32_t* halo,
@@ -103,22 +103,24 @@ inline void onestep_geometry(uint32_t L, uint32_t q, uint32_t* own, uint32_t* ha
     }
     *halo = 32u;
 }
-// Scratch words of a one-step launch over ntiles tiles: the fold's counter
-// (word 0, which must be 0 when the scratch is first used; every fold leaves
-// it 0) and per-block sums, then one F(t) partial per block of tiles.
+// F(t) partials of a one-step launch over ntiles tiles (one uint32 per block).
 uint32_t onestep_partials(uint32_t ntiles);
 // One step of the ring at `ring` (geometry from onestep_geometry with q =
 // kOneStepQ, ntiles tiles): reads ring.buf[parity], writes the other buffer;
-// with `log`, F(t) goes to the ring's flux log (scratch `partials` of
-// onestep_partials(ntiles) words in between).  Ring roads only.
+// with `log`, F(t) is added into the ring's flux log entry (which must be 0),
+// through `scratch` (2 onestep_partials(ntiles) words: a launch folds the
+// previous launch's partials while storing its own).  A run of launches
+// s_off = 0, 1, ... folds launch i's partials in launch i + 1 (first: the
+// run's first launch, whose predecessor's partials are folded already) and
+// after the last one (last: in a launch of their own).  Ring roads only.
 hipError_t launch_grid_onestep(uint32_t vmax, uint32_t ntiles, const RingDesc* ring,
-                               uint32_t* partials, bool log, const Clock* clk, uint32_t s_off,
-                               uint32_t launch_idx, hipStream_t s);
+                               uint32_t* scratch, bool log, const Clock* clk, uint32_t s_off,
+                               uint32_t launch_idx, bool first, bool last, hipStream_t s);
 // One step t of a single ring given by value: reads R.buf[0], writes R.buf[1]
 // (R.own and R.ntiles from onestep_geometry, R.flux_acc null), with scratch
-// `partials` of onestep_partials(R.ntiles) words; *flux = F(t) when flux is not
-// null.
-hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t* partials, uint32_t t,
+// `scratch` of onestep_partials(R.ntiles) words; *flux = F(t) when flux is
+// not null.
+hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t* scratch, uint32_t t,
                                       unsigned long long* flux, hipStream_t s);
 
 // ---- agent (agent.hip) --------------------------------------------------------
