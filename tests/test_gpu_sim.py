@@ -116,11 +116,11 @@ def test_rule3_draws_at_the_ring_end(q, vmax):
 @pytest.mark.parametrize("vmax,p", [(1, 0.13), (5, 0.13), (8, 0.13), (5, 0.25), (3, 0.0)])
 def test_onestep_tile_edges(vmax, p):
     """The one-step kernel's tiles: a wave's 64 words, a halo word at each end
-    and 1984 owned cells, each wave walking a run of tiles.  Rings just below,
+    and 1984 owned cells, one tile per wave and 8 per block.  Rings just below,
     at and above one and several tiles; last tiles that end inside the ring's
     last word; a tile whose segment ends exactly at the ring's end (4000 =
-    1984 + 2016) or one cell past it; whole multiples of the tile; and rings
-    of more tiles than a launch has waves (each wave takes several)."""
+    1984 + 2016) or one cell past it; whole multiples of the tile; and a ring
+    of 9001 tiles (1126 blocks, whose F(t) partials are folded in 64 chunks)."""
     own = 32 * (64 - 2)
     lengths = [own - 1, own, own + 1, own + 31, own + 32, own + 33, 2047, 2048, 2049,
                2 * own, 2 * own + 5, 3999, 4000, 4001, 3 * own, 3 * own + 2017, 5 * own + 77,
@@ -128,6 +128,40 @@ def test_onestep_tile_edges(vmax, p):
     for i, L in enumerate(lengths):
         _run_and_compare(L, L // 4 + i, vmax, p, 300 + i, 25 if L < 10**6 else 5,
                          kernel="onestep", init_v=1, replica=i % 3)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_onestep_flux_folded_across_calls(use_graph):
+    """The one-step kernel folds each step's per-block F(t) partials in the next
+    step's launch, and a run's last step in a launch of its own: runs of
+    different lengths back to back (one step alone among them), a restore to
+    an earlier step in between (the log is cleared), and rings of fewer and of
+    more blocks than the fold's 64 chunks."""
+    vmax, p, seed = 5, 0.13, 12
+    for L in (300007, 2000003):
+        N = L // 5
+        g0 = oracle.init_grid(L, N, vmax, seed, init_v=1)
+        s = Sim(L, N, vmax, p, seed, kernel="onestep", init_v=1, use_graph=use_graph)
+        try:
+            runs = [7, 1, 12, 7]
+            for T in runs:
+                s.step(T)
+            t = sum(runs)
+            want, want_flux = oracle.run_grid(g0, vmax, p, seed, t)
+            g, tt = s.snapshot()
+            assert tt == t
+            np.testing.assert_array_equal(g, want)
+            np.testing.assert_array_equal(s.flux(0, t), want_flux)
+            mid, _ = oracle.run_grid(g0, vmax, p, seed, 8)
+            s.restore(mid, 8)
+            s.step(1)
+            s.step(11)
+            np.testing.assert_array_equal(s.flux(8, 12), want_flux[8:20])
+            g, tt = s.snapshot()
+            assert tt == 20
+            np.testing.assert_array_equal(g, oracle.run_grid(mid, vmax, p, seed, 12, t0=8)[0])
+        finally:
+            s.close()
 
 
 @pytest.mark.parametrize("L", [1, 2, 3, 5, 8, 31, 32, 33, 63, 64, 100, 1023, 2047, 2048, 2049])
