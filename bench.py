@@ -178,6 +178,12 @@ def _median_of_chunks(advance, cells, warm_s, chunk_s, repeats=3):
     return float(np.median(rates)), rates, warm, chunk
 
 
+def _ordinal(m):
+    """1st, 2nd, 3rd, 4th, ..., 11th, 12th, 13th, ..., 21st, ..."""
+    suffix = "th" if m % 100 in (11, 12, 13) else {1: "st", 2: "nd", 3: "rd"}.get(m % 10, "th")
+    return f"{m}{suffix}"
+
+
 def _stratified(reps, target_cells):
     """Every m-th replica in order of L (all sizes represented), m chosen so the
     sample holds about target_cells cells."""
@@ -190,9 +196,9 @@ def _stratified(reps, target_cells):
 def cpu_baseline_ensemble(reps, T, budget_s=15.0):
     """The oracle on a bounded, L-stratified sample of the ensemble: the all-core
     OpenMP twin on one thread per physical core (OMP_PLACES=cores,
-    OMP_PROC_BIND=spread), 10 warm-up steps, then the median of 3 chunks of 20
-    timed steps (the reported value); the serial oracle the same way on a
-    smaller sample.  The sample's rate stands for the whole workload, whose
+    OMP_PROC_BIND=spread), warm-up steps for about a fifth of the time budget,
+    then the median rate of 3 timed chunks of steps, each about a quarter of it
+    (the reported value); the serial oracle the same way on a smaller sample.  The sample's rate stands for the whole workload, whose
     time is extrapolated from it (labelled as such)."""
     import oracle
     threads = _cpu_threads()
@@ -225,7 +231,7 @@ def cpu_baseline_ensemble(reps, T, budget_s=15.0):
     (s_value, s_rates, s_warm, s_chunk), s_cells = run(s_sample, 1, budget_s / 10, budget_s / 8)
 
     def desc(mm, smp, c, w, ch, rr):
-        return (f"every {mm}th of {len(reps)} replicas in order of L ({len(smp)}, {c:.3g} "
+        return (f"every {_ordinal(mm)} of {len(reps)} replicas in order of L ({len(smp)}, {c:.3g} "
                 f"cells): {w} warm-up steps, then median of 3 chunks of {ch} steps "
                 f"(chunk rates {', '.join(f'{x:.3g}' for x in rr)})")
     return {"value": value, "unit": "cell-updates/s", "cores": nthreads, "kind": "oracle",
@@ -383,7 +389,7 @@ def bench_ensemble(args):
         plain_ms = e0.elapsed_time(e1)
         plain_cells = sum(r["L"] for r in sample) * args.plain_T
         extra["plain_cups"] = plain_cells / (plain_ms * 1e-3)
-        extra["plain_sample"] = f"every {args.plain_stride}th replica ({len(sample)}), " \
+        extra["plain_sample"] = f"every {_ordinal(args.plain_stride)} replica ({len(sample)}), " \
                                 f"{args.plain_T} steps each"
         extra["batched_over_plain"] = extra["batched_kernel_cups"] / extra["plain_cups"]
         for s in sims:
