@@ -37,7 +37,8 @@
 // first 64 blocks of the next launch add the partials up in 64 chunks, each
 // into the log entry with one atomic add (a launch of their own after the
 // last step).  Consecutive launches alternate between two sets of partials.
-// A fold kernel of its own after every step cost 7 us of each step.
+// A fold kernel of its own after every step measured about 1 % slower (381.4
+// against 378.2 - 378.7 ms for 1000 steps of the 2^30-cell ring).
 //
 // Segment cell i is ring cell (own_start - 32 + i) mod L.  A tile whose
 // segment lies inside [0, L) is the common case and takes aligned 16-byte
