@@ -150,11 +150,15 @@ __device__ __forceinline__ void agent_rule3(uint32_t (&nv)[C], const uint32_t (&
 // Wave w holds cars [w own, w own + 64 CPL) and writes back the first own of
 // them; F(t) of each wave and step goes to partials[s * ntiles + wave].  own is
 // a multiple of 8 (agent_geometry), so for CPL = 4 and 8 a lane's x and v are
-// aligned for vector loads and stores.
+// aligned for vector loads and stores.  With `prev` (launches of one step
+// each), the first wave of each of the first kFoldBlocks blocks first adds a
+// chunk of the previous launch's partials, prev[0 .. ntiles), into its step's
+// log entry: no fold launch between steps.
 template <int CPL>
 __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __restrict__ A,
                                                           uint32_t own, uint32_t ntiles,
                                                           uint32_t* __restrict__ partials,
+                                                          const uint32_t* __restrict__ prev,
                                                           uint32_t k,
                                                           const Clock* __restrict__ clk,
                                                           uint32_t s_off, uint32_t launch_idx) {
@@ -162,6 +166,12 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t wave = blockIdx.x * 4u + wib;
+    if (prev && wib == 0u && blockIdx.x < kFoldBlocks && A->flux_log) {
+        const unsigned long long f =
+            chunk_sum(prev, ntiles, blockIdx.x, min(kFoldBlocks, gridDim.x), lane);
+        const uint64_t t_prev = (uint64_t)clk->t + A->t + s_off - 1u;
+        if (lane == 0u && f) atomicAdd(&A->flux_log[t_prev - A->log_t0], f);
+    }
     if (wave >= ntiles) return;
     AgentLds& lds = s_lds[wib];
     if (lane == 0u) lds.n = 0u;
@@ -319,14 +329,16 @@ __global__ __launch_bounds__(256) void agent_kstep_kernel(const AgentDesc* __res
 }
 
 hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t cpl, uint32_t own, uint32_t ntiles,
-                              uint32_t* partials, uint32_t k, const Clock* clk, uint32_t s_off,
-                              uint32_t launch_idx, hipStream_t s) {
+                              uint32_t* partials, const uint32_t* prev, uint32_t k,
+                              const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                              hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
+    if (prev && (k != 1u || s_off == 0u)) return hipErrorInvalidValue;
     const dim3 grid((ntiles + 3) / 4);
 #define NASCH_AGENT_CASE(C)                                                                   \
     case C:                                                                                   \
-        NASCH_LAUNCH(agent_kstep_kernel<C>, grid, dim3(256), 0, s, a, own, ntiles, partials, k, \
-                     clk, s_off, launch_idx);                                                 \
+        NASCH_LAUNCH(agent_kstep_kernel<C>, grid, dim3(256), 0, s, a, own, ntiles, partials,    \
+                     prev, k, clk, s_off, launch_idx);                                        \
         break;
     switch (cpl) {
         NASCH_AGENT_CASE(4)

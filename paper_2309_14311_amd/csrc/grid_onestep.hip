@@ -281,18 +281,6 @@ __device__ __forceinline__ void os_block(const RingDesc& R, uint32_t b, uint32_t
     }
 }
 
-// Chunk c of m (m <= 64 chunks) of a launch's n partials, added by one wave
-// (all 64 lanes active).  A partial is below 2^17 (8 tiles of 1984 cells at
-// speed <= 8) and a chunk holds at most 2^12 of them, so 32 bits suffice.
-__device__ __forceinline__ uint32_t chunk_sum(const uint32_t* __restrict__ partials, uint32_t n,
-                                              uint32_t c, uint32_t m, uint32_t lane) {
-    const uint32_t per = (n + m - 1u) / m;
-    const uint32_t lo = min(c * per, n), hi = min(lo + per, n);
-    uint32_t acc = 0u;
-    for (uint32_t i = lo + lane; i < hi; i += 64u) acc += partials[i];
-    return wave_total(acc);
-}
-
 }  // namespace
 
 // One step of a ring (RingDesc at `ring`, step and buffer parity from the
@@ -312,10 +300,9 @@ __global__ __launch_bounds__(kOneStepThreads) void grid_onestep_kernel(
     const uint32_t nb = gridDim.x;
     const uint32_t m = min(kFoldBlocks, nb);
     if (fold_prev && blockIdx.x < m && threadIdx.x < 64u) {
-        const uint32_t f = chunk_sum(scratch + (size_t)((launch_idx + 1u) & 1u) * nb, nb,
-                                     blockIdx.x, m, threadIdx.x);
-        if (threadIdx.x == 0u && f)
-            atomicAdd(&R.flux_log[(uint64_t)t - 1u - R.log_t0], (unsigned long long)f);
+        const unsigned long long f = chunk_sum(scratch + (size_t)((launch_idx + 1u) & 1u) * nb,
+                                               nb, blockIdx.x, m, threadIdx.x);
+        if (threadIdx.x == 0u && f) atomicAdd(&R.flux_log[(uint64_t)t - 1u - R.log_t0], f);
     }
     const uint32_t b = xcd_item(blockIdx.x, nb);
     const uint32_t par = (clk->parity + R.parity + launch_idx) & 1u;
@@ -353,13 +340,13 @@ __global__ __launch_bounds__(64) void fold_partials_kernel(const uint32_t* __res
                                                            const RingDesc* __restrict__ ring,
                                                            const Clock* __restrict__ clk,
                                                            uint32_t s_off) {
-    const uint32_t f = chunk_sum(partials, n, blockIdx.x, gridDim.x, threadIdx.x);
+    const unsigned long long f = chunk_sum(partials, n, blockIdx.x, gridDim.x, threadIdx.x);
     if (threadIdx.x != 0u || !f) return;
     if (ring) {
         const uint64_t t = (uint64_t)clk->t + ring->t + s_off;
         out = ring->flux_log + (t - ring->log_t0);
     }
-    atomicAdd(out, (unsigned long long)f);
+    atomicAdd(out, f);
 }
 
 namespace {

@@ -127,11 +127,16 @@ hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t* scratch, uint
 // k steps per launch: each wave holds 64 * cpl consecutive cars (cpl cars per
 // lane, kAgentMinCarsPerLane to kAgentMaxCarsPerLane) and writes back the first
 // own of them, own <= 64 cpl - k (fewer steps than the tiling's k are correct
-// too; one step per launch is the one-step kernel).
+// too; one step per launch is the one-step kernel).  F(t) of wave w and step s
+// goes to partials[s ntiles + w].  A run of one-step launches (k = 1, s_off =
+// 0, 1, ...) may pass `prev`, the previous launch's partials (s_off >= 1): the
+// launch then adds them into their log entry itself, and only the run's last
+// launch needs launch_fold_agent_flux.
 constexpr uint32_t kAgentMinCarsPerLane = 4;
 constexpr uint32_t kAgentMaxCarsPerLane = 8;
 hipError_t launch_agent_kstep(const AgentDesc* a, uint32_t cpl, uint32_t own, uint32_t ntiles,
-                              uint32_t* partials, uint32_t k, const Clock* clk, uint32_t s_off,
-                              uint32_t launch_idx, hipStream_t s);
+                              uint32_t* partials, const uint32_t* prev, uint32_t k,
+                              const Clock* clk, uint32_t s_off, uint32_t launch_idx,
+                              hipStream_t s);
 
 }  // namespace nasch

@@ -220,13 +220,19 @@ int nasch_sim::enqueue_steps(uint64_t T) {
         } else {
             if (kernel == NASCH_KERNEL_ONESTEP) {
                 // one step per launch: the k-step kernel with one step, on the
-                // one-step tiling
+                // one-step tiling.  The partials of consecutive launches
+                // alternate between two sets; each launch folds the previous
+                // one's, and a fold launch the last one's.
+                const auto set = [&](uint64_t i) {
+                    return os_partials + (size_t)(i & 1u) * agent_ntiles1;
+                };
                 for (uint64_t i = 0; i < T; ++i) {
                     hipError_t e = launch_agent_kstep(d_agent, kAgentMaxCarsPerLane, agent_own1,
-                                                      agent_ntiles1, os_partials, 1u, d_clk,
+                                                      agent_ntiles1, set(i),
+                                                      i ? set(i - 1u) : nullptr, 1u, d_clk,
                                                       (uint32_t)i, (uint32_t)i, stream);
-                    if (e == hipSuccess)
-                        e = launch_fold_agent_flux(d_agent, os_partials, agent_ntiles1, 1u, d_clk,
+                    if (e == hipSuccess && i + 1u == T)
+                        e = launch_fold_agent_flux(d_agent, set(i), agent_ntiles1, 1u, d_clk,
                                                    (uint32_t)i, stream);
                     if (e != hipSuccess) return e;
                 }
@@ -236,8 +242,8 @@ int nasch_sim::enqueue_steps(uint64_t T) {
                 for (uint32_t i = 0; i < nl; ++i) {
                     const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
                     hipError_t e = launch_agent_kstep(d_agent, agent_cpl, agent_own,
-                                                      agent_ntiles, os_partials, ki, d_clk,
-                                                      i * k, i, stream);
+                                                      agent_ntiles, os_partials, nullptr, ki,
+                                                      d_clk, i * k, i, stream);
                     if (e == hipSuccess)
                         e = launch_fold_agent_flux(d_agent, os_partials, agent_ntiles, ki, d_clk,
                                                    i * k, stream);
@@ -484,7 +490,7 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
             return NASCH_EINVAL;
         h->agent_cpl = cpl;
         rc = h->ensure_os_partials(
-            std::max((size_t)h->agent_ntiles * kk, (size_t)h->agent_ntiles1));
+            std::max((size_t)h->agent_ntiles * kk, 2u * (size_t)h->agent_ntiles1));
         if (rc) return rc;
         h->k = kk;
         h->q = cpl;
