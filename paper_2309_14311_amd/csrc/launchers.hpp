@@ -89,6 +89,23 @@ constexpr uint32_t kOneStepQ = 1;
 // and kFoldBlocks waves add the partials up in chunks (atomic adds into the
 // zero-initialised log entry).
 constexpr uint32_t kFoldBlocks = 64;
+
+// Chunk c of m (m <= 64 chunks) of n uint32 F(t) partials, added by one wave
+// (all 64 lanes active) and returned to every lane.  A partial is below 2^20
+// and a chunk holds at most 2^16 of them, so a lane's sum stays below 2^30:
+// its low 16 bits and the rest are added across the wave separately.
+__device__ __forceinline__ unsigned long long chunk_sum(const uint32_t* __restrict__ partials,
+                                                        uint32_t n, uint32_t c, uint32_t m,
+                                                        uint32_t lane) {
+    const uint32_t per = (n + m - 1u) / m;
+    const uint32_t lo = min(c * per, n), hi = min(lo + per, n);
+    uint32_t acc = 0u;
+    for (uint32_t i = lo + lane; i < hi; i += 64u) acc += partials[i];
+    const uint32_t tl = wave_total(acc & 0xFFFFu);
+    const uint32_t th = wave_total(acc >> 16);
+    return (unsigned long long)tl + ((unsigned long long)th << 16);
+}
+
 // Tile geometry of the one-step kernel: owned cells per tile (a ring that fits
 // one tile is one tile owning all L cells), the one-word halo, tile count.
 inline void onestep_geometry(uint32_t L, uint32_t q, uint32_t* own, uint32_t* halo,

@@ -406,20 +406,4 @@ __device__ __forceinline__ uint32_t wave_total(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Chunk c of m (m <= 64 chunks) of n uint32 F(t) partials, added by one wave
-// (all 64 lanes active) and returned to every lane.  A partial is below 2^20
-// and a chunk holds at most 2^16 of them, so a lane's sum stays below 2^30:
-// its low 16 bits and the rest are added across the wave separately.
-__device__ __forceinline__ unsigned long long chunk_sum(const uint32_t* __restrict__ partials,
-                                                        uint32_t n, uint32_t c, uint32_t m,
-                                                        uint32_t lane) {
-    const uint32_t per = (n + m - 1u) / m;
-    const uint32_t lo = min(c * per, n), hi = min(lo + per, n);
-    uint32_t acc = 0u;
-    for (uint32_t i = lo + lane; i < hi; i += 64u) acc += partials[i];
-    const uint32_t tl = wave_total(acc & 0xFFFFu);
-    const uint32_t th = wave_total(acc >> 16);
-    return (unsigned long long)tl + ((unsigned long long)th << 16);
-}
-
 }  // namespace nasch
