@@ -100,7 +100,8 @@ __device__ __forceinline__ unsigned long long chunk_sum(const uint32_t* __restri
     const uint32_t per = (n + m - 1u) / m;
     const uint32_t lo = min(c * per, n), hi = min(lo + per, n);
     uint32_t acc = 0u;
-    for (uint32_t i = lo + lane; i < hi; i += 64u) acc += partials[i];
+#pragma unroll 8
+    for (uint32_t i = lo + lane; i < hi; i += 64u) acc += partials[i];   // 8 loads in flight
     const uint32_t tl = wave_total(acc & 0xFFFFu);
     const uint32_t th = wave_total(acc >> 16);
     return (unsigned long long)tl + ((unsigned long long)th << 16);
