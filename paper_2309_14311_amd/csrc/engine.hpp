@@ -140,8 +140,7 @@ struct GridEngine {
     uint32_t k = 0, q = 0;
     uint32_t launch_vmax = kMixedVmax;  // single specialisation when all rings agree
     bool launch_open = false;           // the rings are open roads (all or none)
-    bool io_bytes = false;              // kernels read and write the byte form (one vmax)
-    bool onestep = false;               // the dedicated one-step kernel (bytes, k = 1, rings)
+    bool onestep = false;               // the dedicated one-step kernel (bytes, k = 1, one road)
     uint32_t version = 0;               // bumped whenever d_items / geometry change
     // per-launch F(t) partials of every item and step, and the rings that keep a log
     uint32_t* d_partials = nullptr;
@@ -287,17 +286,13 @@ struct GridEngine {
             const uint32_t ki = (uint32_t)std::min<uint64_t>(k, T - (uint64_t)i * k);
             if (onestep) {
                 // one ring; F(t) of each launch folded by the next one
-                hipError_t e = launch_grid_onestep(launch_vmax, rings[0].ntiles, d_rings,
-                                                   d_partials, n_log_rings != 0, d_clk, i, i,
-                                                   i == 0, i + 1 == n, s);
+                hipError_t e = launch_grid_onestep(launch_vmax, launch_open, rings[0].ntiles,
+                                                   d_rings, d_partials, n_log_rings != 0, d_clk,
+                                                   i, i, i == 0, i + 1 == n, s);
                 if (e != hipSuccess) return e;
                 continue;
             }
-            hipError_t e =
-                io_bytes ? launch_grid_kstep_bytes(launch_vmax, launch_open, q, d_rings, d_items,
-                                                   (uint32_t)items.size(), d_partials, ki, d_clk,
-                                                   i * k, i, s)
-                         : launch_grid_kstep(launch_vmax, launch_open, q, d_rings, d_items,
+            hipError_t e = launch_grid_kstep(launch_vmax, launch_open, q, d_rings, d_items,
                                              (uint32_t)items.size(), d_partials, ki, d_clk, i * k,
                                              i, s);
             if (e == hipSuccess && n_log_rings)

@@ -292,8 +292,8 @@ __device__ __forceinline__ void gather_ring(const uint32_t* __restrict__ src, ui
     }
 }
 
-// ---- the byte form (BYTES = true): the road is read and written as one byte
-// per cell and converted to and from bit planes in registers.
+// ---- the byte form (the one-step kernel): the road is read and written as one
+// byte per cell and converted to and from bit planes in registers.
 
 // The 32 bytes of an aligned 32-cell word (16-byte loads).
 __device__ __forceinline__ void load_bytes32(const uint8_t* __restrict__ p, uint32_t (&d)[8]) {

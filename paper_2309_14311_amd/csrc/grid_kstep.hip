@@ -15,10 +15,8 @@
 //   rule 4   the cars with v3 == j are shifted j cells to the right, and the
 //            new thermometer is the suffix-OR of the shifted classes.
 // The road is stored in HBM in the same planes (RingDesc), so a launch loads
-// and stores VMAX + 1 words per 32 cells and converts nothing.  The BYTES
-// instantiations read and write the road's byte form instead and convert each
-// word in registers (bitplanes.hpp); launched with k = 1 they are the one-step
-// kernel.
+// and stores VMAX + 1 words per 32 cells and converts nothing (the one-step
+// kernel, grid_onestep.hip, works on the byte form instead).
 // Neighbouring words come from the same lane or, at lane edges, from lane +-1
 // by cross-lane shuffles.  The segment is the tile's owned cells plus a halo
 // of H >= k*vmax cells on each side (read modulo L, so short rings repeat
@@ -50,7 +48,7 @@ using namespace grid;
 // One wave advances one tile item by up to k steps.  F(t) of a ring with a
 // flux log goes to partials[s * n_items + item] (summed per ring and step by
 // the fold kernel); flux_acc gets one atomic per wave.
-template <int VMAX, int Q, bool OPEN, bool BYTES>
+template <int VMAX, int Q, bool OPEN>
 __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it, uint32_t item,
                                            uint32_t n_items, uint32_t* __restrict__ partials,
                                            uint32_t lane, uint32_t k,
@@ -121,28 +119,7 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
         // [0, L) on an open road
         const uint32_t valid = j0 + 32u <= seg_len ? 0xFFFFFFFFu
                                : (j0 < seg_len ? (1u << (seg_len - j0)) - 1u : 0u);
-        if constexpr (BYTES) {
-            const uint8_t* __restrict__ bsrc = R.buf[par];
-            uint32_t d[8];
-            bool inside = true;
-            if constexpr (OPEN) {
-                if (p0 >= 0 && p0 < (int64_t)L) load_bytes_open(bsrc, L, (uint32_t)p0, d);
-                else inside = false;
-            } else if (aligned[q]) {
-                load_bytes32(bsrc + x0, d);
-            } else {
-                gather_bytes_ring(bsrc, L, x0, d);
-            }
-            if (inside) {
-                bytes_to_thermo<VMAX>(d, T[q]);
-                const uint32_t v = OPEN ? valid & keep[q] : valid;
-#pragma unroll
-                for (int m = 0; m <= VMAX; ++m) T[q][m] &= v;
-            } else {
-#pragma unroll
-                for (int m = 0; m <= VMAX; ++m) T[q][m] = 0u;
-            }
-        } else if constexpr (OPEN) {
+        if constexpr (OPEN) {
             if (p0 >= 0 && p0 < (int64_t)L) {
                 const uint32_t v = valid & keep[q];
                 const uint32_t w = (uint32_t)p0 >> 5;
@@ -304,20 +281,13 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
         if (own[q] == 0u) continue;
         const uint32_t j0 = 32u * (lane * Q + q);
         const uint32_t w = (own_start + (j0 - H)) >> 5;
-        if constexpr (BYTES) {
-            uint32_t d[8];
-            thermo_to_bytes<VMAX>(T[q], d);
-            store_bytes(R.buf[par ^ 1u], 32u * w, own[q], d);
-        } else {
 #pragma unroll
-            for (int m = 0; m <= VMAX; ++m) *gmem(dst + (size_t)m * nw + w) = T[q][m] & own[q];
-        }
+        for (int m = 0; m <= VMAX; ++m) *gmem(dst + (size_t)m * nw + w) = T[q][m] & own[q];
     }
 }
 
 // All items of a launch share vmax (and the boundary): one specialisation.
-// BYTES: the road is read and written in its byte form (the one-step kernel).
-template <int VMAX, int Q, bool OPEN, bool BYTES>
+template <int VMAX, int Q, bool OPEN>
 __global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restrict__ rings,
                                                          const TileItem* __restrict__ items,
                                                          uint32_t n_items, uint32_t* partials,
@@ -328,8 +298,8 @@ __global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restr
     const uint32_t wave = blockIdx.x * 4u + wib;
     if (wave >= n_items) return;
     const TileItem it = items[wave];
-    kstep_tile<VMAX, Q, OPEN, BYTES>(rings[it.ring], it, wave, n_items, partials,
-                                     threadIdx.x & 63u, k, clk, s_off, launch_idx, s_ref[wib]);
+    kstep_tile<VMAX, Q, OPEN>(rings[it.ring], it, wave, n_items, partials, threadIdx.x & 63u, k,
+                              clk, s_off, launch_idx, s_ref[wib]);
 }
 
 // Items of different vmax in one launch: the branch on the ring's vmax is
@@ -351,15 +321,15 @@ __global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* _
     const uint32_t lane = threadIdx.x & 63u;
     RefineLds<Q>& rl = s_ref[wib];
     switch (R.vmax) {
-        case 0: kstep_tile<0, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 1: kstep_tile<1, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 2: kstep_tile<2, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 3: kstep_tile<3, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 4: kstep_tile<4, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 5: kstep_tile<5, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 6: kstep_tile<6, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 7: kstep_tile<7, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
-        case 8: kstep_tile<8, Q, OPEN, false>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 0: kstep_tile<0, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 1: kstep_tile<1, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 2: kstep_tile<2, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 3: kstep_tile<3, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 4: kstep_tile<4, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 5: kstep_tile<5, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 6: kstep_tile<6, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 7: kstep_tile<7, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
+        case 8: kstep_tile<8, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
         default: break;
     }
 }
@@ -372,10 +342,10 @@ hipError_t launch_q(uint32_t vmax, bool open, dim3 grid, hipStream_t s, const Ri
 #define NASCH_KSTEP_CASE(V)                                                                      \
     case V:                                                                                      \
         if (open)                                                                                \
-            NASCH_LAUNCH((grid_kstep_kernel<V, Q, true, false>), grid, dim3(256), 0, s, rings,   \
+            NASCH_LAUNCH((grid_kstep_kernel<V, Q, true>), grid, dim3(256), 0, s, rings,          \
                          items, n_items, partials, k, clk, s_off, launch_idx);                   \
         else                                                                                     \
-            NASCH_LAUNCH((grid_kstep_kernel<V, Q, false, false>), grid, dim3(256), 0, s, rings,  \
+            NASCH_LAUNCH((grid_kstep_kernel<V, Q, false>), grid, dim3(256), 0, s, rings,         \
                          items, n_items, partials, k, clk, s_off, launch_idx);                   \
         break;
     switch (vmax) {
@@ -415,51 +385,6 @@ hipError_t launch_grid_kstep(uint32_t vmax, bool open, uint32_t q, const RingDes
         case 2: return launch_q<2>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         case 3: return launch_q<3>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         case 4: return launch_q<4>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-namespace {
-template <int Q>
-hipError_t launch_bytes_q(uint32_t vmax, bool open, dim3 grid, hipStream_t s,
-                          const RingDesc* rings, const TileItem* items, uint32_t n_items,
-                          uint32_t* partials, uint32_t k, const Clock* clk, uint32_t s_off,
-                          uint32_t launch_idx) {
-#define NASCH_KSTEP_BYTES_CASE(V)                                                                \
-    case V:                                                                                      \
-        if (open)                                                                                \
-            NASCH_LAUNCH((grid_kstep_kernel<V, Q, true, true>), grid, dim3(256), 0, s, rings,    \
-                         items, n_items, partials, k, clk, s_off, launch_idx);                   \
-        else                                                                                     \
-            NASCH_LAUNCH((grid_kstep_kernel<V, Q, false, true>), grid, dim3(256), 0, s, rings,   \
-                         items, n_items, partials, k, clk, s_off, launch_idx);                   \
-        break;
-    switch (vmax) {
-        NASCH_KSTEP_BYTES_CASE(0)
-        NASCH_KSTEP_BYTES_CASE(1)
-        NASCH_KSTEP_BYTES_CASE(2)
-        NASCH_KSTEP_BYTES_CASE(3)
-        NASCH_KSTEP_BYTES_CASE(4)
-        NASCH_KSTEP_BYTES_CASE(5)
-        NASCH_KSTEP_BYTES_CASE(6)
-        NASCH_KSTEP_BYTES_CASE(7)
-        NASCH_KSTEP_BYTES_CASE(8)
-        default:
-            return hipErrorInvalidValue;
-    }
-#undef NASCH_KSTEP_BYTES_CASE
-    return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_grid_kstep_bytes(uint32_t vmax, bool open, uint32_t q, const RingDesc* rings,
-                                   const TileItem* items, uint32_t n_items, uint32_t* partials,
-                                   uint32_t k, const Clock* clk, uint32_t s_off,
-                                   uint32_t launch_idx, hipStream_t s) {
-    if (n_items == 0) return hipSuccess;
-    const dim3 grid((n_items + 3u) / 4u);
-    switch (q) {
-        case 1: return launch_bytes_q<1>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         default: return hipErrorInvalidValue;
     }
 }

@@ -47,6 +47,14 @@
 // segment cell by cell where it crosses the end (the periodic images of a
 // short ring are exact by periodicity) and draw rule 3 across block edges.
 // The branch is uniform over the wave.
+//
+// Open road (OPEN = true).  Segment cell i is road cell own_start - 32 + i;
+// cells before 0 and from L on load as empty, and words stay aligned to the
+// road's 32-cell blocks.  Tiles inside the road run the ring code.  A segment
+// that holds cell L puts a stopped car there when the step's gate keeps the
+// exit closed (the tile before a last tile of fewer than 8 cells holds it
+// too), and the first tile adds the entering car (v = 0) to cell 0 after rule
+// 4 if the gate lets one in and the cell was empty at the start of the step.
 #include "grid_common.hpp"
 #include "launchers.hpp"
 
@@ -91,13 +99,20 @@ __device__ __forceinline__ uint32_t os_word_cell(const OsTile& g, uint32_t j, ui
     return g.inside ? x0 : x0 % L;
 }
 
-// The bytes of the lane's Q words of a tile.
-template <int Q>
+// Open road: road cell of the first cell of segment word j (negative before
+// the road's start).
+__device__ __forceinline__ int64_t os_road_cell(const OsTile& g, uint32_t j) {
+    return (int64_t)g.own_start - 32 + 32 * (int64_t)j;
+}
+
+// The bytes of the lane's Q words of a tile (OPEN: a tile of an open road
+// that holds cell 0 or cells from L on).
+template <int Q, bool OPEN>
 __device__ __forceinline__ void os_load(const RingDesc& R, const uint8_t* __restrict__ src,
                                         uint32_t tile, uint32_t lane, uint32_t (&d)[Q][8],
                                         uint32_t* stage) {
     const OsTile g = os_tile<Q>(R, tile);
-    if (Q == 1 && g.inside) {
+    if (!OPEN && Q == 1 && g.inside) {
         // two contiguous 1 KiB loads (16 bytes per lane), regrouped into the
         // lanes' 32-byte words through LDS
         const uint8_t* base = src + g.s0;
@@ -118,15 +133,26 @@ __device__ __forceinline__ void os_load(const RingDesc& R, const uint8_t* __rest
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const uint32_t x0 = os_word_cell(g, lane * Q + q, R.L);
-        if (g.inside || ((x0 & 31u) == 0u && x0 + 32u <= R.L)) load_bytes32(src + x0, d[q]);
-        else gather_bytes_ring(src, R.L, x0, d[q]);
+        if constexpr (OPEN) {
+            const int64_t p0 = os_road_cell(g, lane * Q + q);
+            if (p0 >= 0 && p0 < (int64_t)R.L) {
+                load_bytes_open(src, R.L, (uint32_t)p0, d[q]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) d[q][i] = 0xFFFFFFFFu;   // off the road: empty
+            }
+        } else {
+            const uint32_t x0 = os_word_cell(g, lane * Q + q, R.L);
+            if (g.inside || ((x0 & 31u) == 0u && x0 + 32u <= R.L)) load_bytes32(src + x0, d[q]);
+            else gather_bytes_ring(src, R.L, x0, d[q]);
+        }
     }
 }
 
 // Step t of one tile from the bytes d of the lane's words: writes the owned
-// cells to dst and returns the lane's share of F(t) (owned cars only).
-template <int VMAX, int Q>
+// cells to dst and returns the lane's share of F(t) (owned cars only).  OPEN:
+// a tile of an open road that holds cell 0 or cells from L on.
+template <int VMAX, int Q, bool OPEN>
 __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restrict__ dst,
                                             uint32_t tile, uint32_t t, bool run, uint32_t lane,
                                             const uint32_t (&d)[Q][8], RefineLds<Q>& rl,
@@ -138,14 +164,37 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
     uint32_t xw[Q];     // ring cell of each word's first cell
     bool aligned[Q];    // the word is one aligned 32-cell block of the ring
     uint32_t own[Q];    // owned cells of each word
+    uint32_t obst[Q];   // open road: cell L
+    uint32_t inj[Q];    // open road: cell 0
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const uint32_t j = lane * Q + q;
-        xw[q] = os_word_cell(g, j, L);
-        aligned[q] = g.inside || ((xw[q] & 31u) == 0u && xw[q] + 32u <= L);
+        if constexpr (OPEN) {
+            // words before cell 0 hold no car; their draws are never used
+            const int64_t p0 = os_road_cell(g, j);
+            xw[q] = p0 < 0 ? 0u : (uint32_t)p0;
+            aligned[q] = true;
+            obst[q] = (p0 <= (int64_t)L && (int64_t)L < p0 + 32) ? 1u << (uint32_t)(L - p0) : 0u;
+            inj[q] = p0 == 0 ? 1u : 0u;
+        } else {
+            xw[q] = os_word_cell(g, j, L);
+            aligned[q] = g.inside || ((xw[q] & 31u) == 0u && xw[q] + 32u <= L);
+            obst[q] = inj[q] = 0u;
+        }
         bytes_to_thermo<VMAX>(d[q], T[q]);
         const uint32_t lo = max(32u, 32u * j), hi = min(32u + g.own_len, 32u * j + 32u);
         own[q] = lo < hi ? bit_range(lo - 32u * j, hi - 32u * j) : 0u;
+    }
+    bool enter = false;
+    uint32_t empty0[Q];   // open road: cell 0, if it is empty at the start of the step
+    if (OPEN && run) {
+        bool exit_open;
+        gate_draw(t, sp, R.thr_in, R.thr_out, enter, exit_open);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (!exit_open) T[q][0] |= obst[q];   // stopped car in cell L, v = 0
+            empty0[q] = inj[q] & ~T[q][0];
+        }
     }
 
     uint32_t fl = 0u;
@@ -175,11 +224,14 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
             // rule 3: the top nibble of R of 32 cars per Philox call, then the
             // wave's tied cars
             if (sp.thr != 0u) {
-                slow_hi<Q>(moving, xw, aligned, g.inside ? kDrawAligned : kDrawGeneric, t, L, sp,
-                           S, U);
+                slow_hi<Q>(moving, xw, aligned,
+                           (OPEN || g.inside) ? kDrawAligned : kDrawGeneric, t, L, sp, S, U);
             }
+            // a queued car's ring cell: segment cell + s0 (an open road's
+            // segment cell 0 is road cell own_start - 32, taken modulo 2^32)
             if ((sp.thr & 0x0FFFFFFFu) != 0u)
-                slow_lo_wave<Q>(S, U, xw, L, g.s0, g.inside ? kXNone : kXMod, t, sp, rl, lane);
+                slow_lo_wave<Q>(S, U, xw, L, OPEN ? g.own_start - 32u : g.s0,
+                                (OPEN || g.inside) ? kXNone : kXMod, t, sp, rl, lane);
             uint32_t Eq[Q][VMAX + 1];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
@@ -214,6 +266,10 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
             fl = speed_sum(dig);
         }
     }
+    if (OPEN && run && enter) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) T[q][0] |= empty0[q];   // entering car in cell 0, v = 0
+    }
 
     // store the owned cells (they lie in [0, L) and start on a word boundary)
     if (Q == 1 && g.inside && g.own_len == 32u * (64u * Q - 2u)) {
@@ -247,7 +303,7 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
 // R.buf[par] to R.buf[par ^ 1].  The block's F(t) goes to *partial (if not
 // null), to *whole (if not null: a launch of one block, whose F(t) is the
 // ring's) and, from the warm-up on, is added into R.flux_acc.
-template <int VMAX, int Q>
+template <int VMAX, int Q, bool OPEN>
 __device__ __forceinline__ void os_block(const RingDesc& R, uint32_t b, uint32_t t, uint32_t par,
                                          uint32_t* __restrict__ partial,
                                          unsigned long long* __restrict__ whole,
@@ -264,8 +320,15 @@ __device__ __forceinline__ void os_block(const RingDesc& R, uint32_t b, uint32_t
         if (lane == 0u) rl.n = 0u;
         uint32_t d[Q][8];
         uint32_t* stage = s_stage + 512u * wib;
-        os_load<Q>(R, R.buf[par], tile, lane, d, stage);
-        fl = os_step<VMAX, Q>(R, R.buf[par ^ 1u], tile, t, run, lane, d, rl, stage);
+        // an open road's tiles that hold cell 0 or cells from L on take the
+        // open-road code; the others run the ring code (wave-uniform)
+        if (OPEN && !os_tile<Q>(R, tile).inside) {
+            os_load<Q, true>(R, R.buf[par], tile, lane, d, stage);
+            fl = os_step<VMAX, Q, true>(R, R.buf[par ^ 1u], tile, t, run, lane, d, rl, stage);
+        } else {
+            os_load<Q, false>(R, R.buf[par], tile, lane, d, stage);
+            fl = os_step<VMAX, Q, false>(R, R.buf[par ^ 1u], tile, t, run, lane, d, rl, stage);
+        }
     }
     const uint32_t wtot = wave_total(fl);
     if (lane == 0u) s_flux[wib] = wtot;
@@ -288,7 +351,7 @@ __device__ __forceinline__ void os_block(const RingDesc& R, uint32_t b, uint32_t
 // its F(t) in partial set launch_idx of `scratch` (sets of gridDim.x words),
 // and (fold_prev) the first wave of each of the first 64 blocks first adds a
 // chunk of the previous launch's set into its log entry.
-template <int VMAX, int Q>
+template <int VMAX, int Q, bool OPEN>
 __global__ __launch_bounds__(kOneStepThreads) void grid_onestep_kernel(
     const RingDesc* __restrict__ ring, uint32_t* __restrict__ scratch,
     const Clock* __restrict__ clk, uint32_t s_off, uint32_t launch_idx, uint32_t fold_prev) {
@@ -308,10 +371,10 @@ __global__ __launch_bounds__(kOneStepThreads) void grid_onestep_kernel(
     const uint32_t par = (clk->parity + R.parity + launch_idx) & 1u;
     // one block (a ring of at most 8 tiles) writes F(t) itself
     const bool one = nb == 1u && R.flux_log;
-    os_block<VMAX, Q>(R, b, t, par,
-                      R.flux_log && !one ? scratch + (size_t)(launch_idx & 1u) * nb + blockIdx.x
-                                         : nullptr,
-                      one ? R.flux_log + ((uint64_t)t - R.log_t0) : nullptr, s_ref, s_flux, s_stage);
+    os_block<VMAX, Q, OPEN>(
+        R, b, t, par,
+        R.flux_log && !one ? scratch + (size_t)(launch_idx & 1u) * nb + blockIdx.x : nullptr,
+        one ? R.flux_log + ((uint64_t)t - R.log_t0) : nullptr, s_ref, s_flux, s_stage);
 }
 
 // One step t of a ring described by value (buf[0] is read, buf[1] written):
@@ -328,8 +391,8 @@ __global__ __launch_bounds__(kOneStepThreads) void grid_onestep_direct_kernel(
     // one block writes F(t) itself
     const bool one = gridDim.x == 1u;
     if (flux && !one && blockIdx.x == 0u && threadIdx.x == 0u) *flux = 0ull;
-    os_block<VMAX, Q>(R, b, t, 0u, flux && !one ? partials + blockIdx.x : nullptr,
-                      one ? flux : nullptr, s_ref, s_flux, s_stage);
+    os_block<VMAX, Q, false>(R, b, t, 0u, flux && !one ? partials + blockIdx.x : nullptr,
+                             one ? flux : nullptr, s_ref, s_flux, s_stage);
 }
 
 // Adds a launch's n partials into *out, or into the ring's flux log at step
@@ -354,17 +417,19 @@ namespace {
 // Blocks of a one-step launch: one tile per wave.
 uint32_t os_blocks(uint32_t ntiles) { return std::max(1u, (ntiles + kOsWaves - 1u) / kOsWaves); }
 
-#define NASCH_OS_VMAX_SWITCH(KERNEL, Q, ...)                                                   \
+// KERNEL<vmax, TARGS...> for the launch's vmax; TARGS is a parenthesised list.
+#define NASCH_OS_UNPAREN(...) __VA_ARGS__
+#define NASCH_OS_VMAX_SWITCH(KERNEL, TARGS, ...)                                               \
     switch (vmax) {                                                                            \
-        case 0: NASCH_LAUNCH((KERNEL<0, Q>), __VA_ARGS__); break;                               \
-        case 1: NASCH_LAUNCH((KERNEL<1, Q>), __VA_ARGS__); break;                               \
-        case 2: NASCH_LAUNCH((KERNEL<2, Q>), __VA_ARGS__); break;                               \
-        case 3: NASCH_LAUNCH((KERNEL<3, Q>), __VA_ARGS__); break;                               \
-        case 4: NASCH_LAUNCH((KERNEL<4, Q>), __VA_ARGS__); break;                               \
-        case 5: NASCH_LAUNCH((KERNEL<5, Q>), __VA_ARGS__); break;                               \
-        case 6: NASCH_LAUNCH((KERNEL<6, Q>), __VA_ARGS__); break;                               \
-        case 7: NASCH_LAUNCH((KERNEL<7, Q>), __VA_ARGS__); break;                               \
-        case 8: NASCH_LAUNCH((KERNEL<8, Q>), __VA_ARGS__); break;                               \
+        case 0: NASCH_LAUNCH((KERNEL<0, NASCH_OS_UNPAREN TARGS>), __VA_ARGS__); break;          \
+        case 1: NASCH_LAUNCH((KERNEL<1, NASCH_OS_UNPAREN TARGS>), __VA_ARGS__); break;          \
+        case 2: NASCH_LAUNCH((KERNEL<2, NASCH_OS_UNPAREN TARGS>), __VA_ARGS__); break;          \
+        case 3: NASCH_LAUNCH((KERNEL<3, NASCH_OS_UNPAREN TARGS>), __VA_ARGS__); break;          \
+        case 4: NASCH_LAUNCH((KERNEL<4, NASCH_OS_UNPAREN TARGS>), __VA_ARGS__); break;          \
+        case 5: NASCH_LAUNCH((KERNEL<5, NASCH_OS_UNPAREN TARGS>), __VA_ARGS__); break;          \
+        case 6: NASCH_LAUNCH((KERNEL<6, NASCH_OS_UNPAREN TARGS>), __VA_ARGS__); break;          \
+        case 7: NASCH_LAUNCH((KERNEL<7, NASCH_OS_UNPAREN TARGS>), __VA_ARGS__); break;          \
+        case 8: NASCH_LAUNCH((KERNEL<8, NASCH_OS_UNPAREN TARGS>), __VA_ARGS__); break;          \
         default: return hipErrorInvalidValue;                                                  \
     }
 
@@ -379,14 +444,22 @@ hipError_t fold(const uint32_t* partials, uint32_t n, unsigned long long* out,
 
 uint32_t onestep_partials(uint32_t ntiles) { return os_blocks(ntiles); }
 
-hipError_t launch_grid_onestep(uint32_t vmax, uint32_t ntiles, const RingDesc* ring,
+hipError_t launch_grid_onestep(uint32_t vmax, bool open, uint32_t ntiles, const RingDesc* ring,
                                uint32_t* scratch, bool log, const Clock* clk, uint32_t s_off,
                                uint32_t launch_idx, bool first, bool last, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
     const uint32_t nb = os_blocks(ntiles);
     const bool fold_log = log && nb > 1u;   // one block writes F(t) itself
-    NASCH_OS_VMAX_SWITCH(grid_onestep_kernel, kOneStepQ, dim3(nb), dim3(kOneStepThreads), 0, s,
-                         ring, scratch, clk, s_off, launch_idx, (fold_log && !first) ? 1u : 0u)
+    const uint32_t fold_prev = (fold_log && !first) ? 1u : 0u;
+    if (open) {
+        NASCH_OS_VMAX_SWITCH(grid_onestep_kernel, (kOneStepQ, true), dim3(nb),
+                             dim3(kOneStepThreads), 0, s, ring, scratch, clk, s_off, launch_idx,
+                             fold_prev)
+    } else {
+        NASCH_OS_VMAX_SWITCH(grid_onestep_kernel, (kOneStepQ, false), dim3(nb),
+                             dim3(kOneStepThreads), 0, s, ring, scratch, clk, s_off, launch_idx,
+                             fold_prev)
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !fold_log || !last) return e;
     return fold(scratch + (size_t)(launch_idx & 1u) * nb, nb, nullptr, ring, clk, s_off, s);
@@ -397,13 +470,14 @@ hipError_t launch_grid_onestep_direct(const RingDesc& R, uint32_t* scratch, uint
     if (R.ntiles == 0) return hipSuccess;
     const uint32_t vmax = R.vmax;
     const uint32_t nb = os_blocks(R.ntiles);
-    NASCH_OS_VMAX_SWITCH(grid_onestep_direct_kernel, kOneStepQ, dim3(nb), dim3(kOneStepThreads),
-                         0, s, R, scratch, t, flux)
+    NASCH_OS_VMAX_SWITCH(grid_onestep_direct_kernel, (kOneStepQ), dim3(nb),
+                         dim3(kOneStepThreads), 0, s, R, scratch, t, flux)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !flux || nb == 1u) return e;   // one block wrote F(t) itself
     return fold(scratch, nb, flux, nullptr, nullptr, 0u, s);
 }
 
 #undef NASCH_OS_VMAX_SWITCH
+#undef NASCH_OS_UNPAREN
 
 }  // namespace nasch

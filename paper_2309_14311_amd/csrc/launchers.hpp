@@ -71,13 +71,6 @@ hipError_t launch_grid_kstep(uint32_t vmax, bool open, uint32_t q, const RingDes
                              const TileItem* items, uint32_t n_items, uint32_t* partials,
                              uint32_t k, const Clock* clk, uint32_t s_off, uint32_t launch_idx,
                              hipStream_t s);
-// The same kernel reading and writing the road's byte form (ring.buf) instead
-// of its bit planes; one vmax per launch (no kMixedVmax), q = 1 only.  With
-// k = 1 it is the one-step kernel.
-hipError_t launch_grid_kstep_bytes(uint32_t vmax, bool open, uint32_t q, const RingDesc* rings,
-                                   const TileItem* items, uint32_t n_items, uint32_t* partials,
-                                   uint32_t k, const Clock* clk, uint32_t s_off,
-                                   uint32_t launch_idx, hipStream_t s);
 
 // ---- grid, one step per launch on the byte form (grid_onestep.hip) -----------
 // A wave handles a tile of 64 q words: a halo word at each end and the owned
@@ -130,8 +123,9 @@ uint32_t onestep_partials(uint32_t ntiles);
 // previous launch's partials while storing its own).  A run of launches
 // s_off = 0, 1, ... folds launch i's partials in launch i + 1 (first: the
 // run's first launch, whose predecessor's partials are folded already) and
-// after the last one (last: in a launch of their own).  Ring roads only.
-hipError_t launch_grid_onestep(uint32_t vmax, uint32_t ntiles, const RingDesc* ring,
+// after the last one (last: in a launch of their own).  open: the ring is an
+// open road.
+hipError_t launch_grid_onestep(uint32_t vmax, bool open, uint32_t ntiles, const RingDesc* ring,
                                uint32_t* scratch, bool log, const Clock* clk, uint32_t s_off,
                                uint32_t launch_idx, bool first, bool last, hipStream_t s);
 // One step t of a single ring given by value: reads R.buf[0], writes R.buf[1]

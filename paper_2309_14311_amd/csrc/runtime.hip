@@ -420,8 +420,7 @@ int nasch_init(nasch_sim** out, uint64_t L, uint64_t N, uint32_t vmax, double p,
         }
         h->eng.rings.push_back(r);
         h->eng1.rings.push_back(r);
-        h->eng1.io_bytes = true;
-        h->eng1.onestep = !open;   // open roads: the k-step kernel on bytes at k = 1
+        h->eng1.onestep = true;
         if (!h->ok(h->eng1.set_geometry(1, kOneStepQ, h->stream))) return NASCH_EDEVICE;
         uint32_t kk = o.k, qq = o.q;
         uint32_t dk, dq;
