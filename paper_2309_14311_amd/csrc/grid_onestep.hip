@@ -55,6 +55,9 @@
 // exit closed (the tile before a last tile of fewer than 8 cells holds it
 // too), and the first tile adds the entering car (v = 0) to cell 0 after rule
 // 4 if the gate lets one in and the cell was empty at the start of the step.
+// The tile code is compiled once per kind of tile (inside, ring edge, open
+// road edge): with the open road's branches in the interior tiles' code those
+// ran 2 % slower.
 #include "grid_common.hpp"
 #include "launchers.hpp"
 
@@ -93,10 +96,16 @@ __device__ __forceinline__ OsTile os_tile(const RingDesc& R, uint32_t tile) {
     return g;
 }
 
+// The tile code is compiled once per kind of tile, so that the interior
+// tiles' code holds no branch of the edge tiles': a tile whose segment lies
+// inside [0, L), a ring's other tiles, and an open road's other tiles.
+enum : int { kTileInside = 0, kTileRingEdge = 1, kTileOpenEdge = 2 };
+
 // Ring cell of the first cell of segment word j (< 64 Q).
+template <int MODE>
 __device__ __forceinline__ uint32_t os_word_cell(const OsTile& g, uint32_t j, uint32_t L) {
     const uint32_t x0 = g.s0 + 32u * j;   // s0 < 2^31, 32 j < 2^14: no overflow
-    return g.inside ? x0 : x0 % L;
+    return MODE == kTileInside ? x0 : x0 % L;
 }
 
 // Open road: road cell of the first cell of segment word j (negative before
@@ -105,14 +114,13 @@ __device__ __forceinline__ int64_t os_road_cell(const OsTile& g, uint32_t j) {
     return (int64_t)g.own_start - 32 + 32 * (int64_t)j;
 }
 
-// The bytes of the lane's Q words of a tile (OPEN: a tile of an open road
-// that holds cell 0 or cells from L on).
-template <int Q, bool OPEN>
+// The bytes of the lane's Q words of a tile of kind MODE.
+template <int Q, int MODE>
 __device__ __forceinline__ void os_load(const RingDesc& R, const uint8_t* __restrict__ src,
                                         uint32_t tile, uint32_t lane, uint32_t (&d)[Q][8],
                                         uint32_t* stage) {
     const OsTile g = os_tile<Q>(R, tile);
-    if (!OPEN && Q == 1 && g.inside) {
+    if (MODE == kTileInside && Q == 1) {
         // two contiguous 1 KiB loads (16 bytes per lane), regrouped into the
         // lanes' 32-byte words through LDS
         const uint8_t* base = src + g.s0;
@@ -133,7 +141,7 @@ __device__ __forceinline__ void os_load(const RingDesc& R, const uint8_t* __rest
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        if constexpr (OPEN) {
+        if constexpr (MODE == kTileOpenEdge) {
             const int64_t p0 = os_road_cell(g, lane * Q + q);
             if (p0 >= 0 && p0 < (int64_t)R.L) {
                 load_bytes_open(src, R.L, (uint32_t)p0, d[q]);
@@ -142,23 +150,27 @@ __device__ __forceinline__ void os_load(const RingDesc& R, const uint8_t* __rest
                 for (int i = 0; i < 8; ++i) d[q][i] = 0xFFFFFFFFu;   // off the road: empty
             }
         } else {
-            const uint32_t x0 = os_word_cell(g, lane * Q + q, R.L);
-            if (g.inside || ((x0 & 31u) == 0u && x0 + 32u <= R.L)) load_bytes32(src + x0, d[q]);
-            else gather_bytes_ring(src, R.L, x0, d[q]);
+            const uint32_t x0 = os_word_cell<MODE>(g, lane * Q + q, R.L);
+            if (MODE == kTileInside || ((x0 & 31u) == 0u && x0 + 32u <= R.L))
+                load_bytes32(src + x0, d[q]);
+            else
+                gather_bytes_ring(src, R.L, x0, d[q]);
         }
     }
 }
 
-// Step t of one tile from the bytes d of the lane's words: writes the owned
-// cells to dst and returns the lane's share of F(t) (owned cars only).  OPEN:
-// a tile of an open road that holds cell 0 or cells from L on.
-template <int VMAX, int Q, bool OPEN>
+// Step t of one tile of kind MODE from the bytes d of the lane's words:
+// writes the owned cells to dst and returns the lane's share of F(t) (owned
+// cars only).
+template <int VMAX, int Q, int MODE>
 __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restrict__ dst,
                                             uint32_t tile, uint32_t t, bool run, uint32_t lane,
                                             const uint32_t (&d)[Q][8], RefineLds<Q>& rl,
                                             uint32_t* stage) {
     const uint32_t L = R.L;
     const SlowParams sp = R.sp;
+    constexpr bool OPEN = MODE == kTileOpenEdge;
+    constexpr bool inside = MODE == kTileInside;
     const OsTile g = os_tile<Q>(R, tile);
     uint32_t T[Q][VMAX + 1];
     uint32_t xw[Q];     // ring cell of each word's first cell
@@ -177,8 +189,8 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
             obst[q] = (p0 <= (int64_t)L && (int64_t)L < p0 + 32) ? 1u << (uint32_t)(L - p0) : 0u;
             inj[q] = p0 == 0 ? 1u : 0u;
         } else {
-            xw[q] = os_word_cell(g, j, L);
-            aligned[q] = g.inside || ((xw[q] & 31u) == 0u && xw[q] + 32u <= L);
+            xw[q] = os_word_cell<MODE>(g, j, L);
+            aligned[q] = inside || ((xw[q] & 31u) == 0u && xw[q] + 32u <= L);
             obst[q] = inj[q] = 0u;
         }
         bytes_to_thermo<VMAX>(d[q], T[q]);
@@ -225,13 +237,13 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
             // wave's tied cars
             if (sp.thr != 0u) {
                 slow_hi<Q>(moving, xw, aligned,
-                           (OPEN || g.inside) ? kDrawAligned : kDrawGeneric, t, L, sp, S, U);
+                           (OPEN || inside) ? kDrawAligned : kDrawGeneric, t, L, sp, S, U);
             }
             // a queued car's ring cell: segment cell + s0 (an open road's
             // segment cell 0 is road cell own_start - 32, taken modulo 2^32)
             if ((sp.thr & 0x0FFFFFFFu) != 0u)
                 slow_lo_wave<Q>(S, U, xw, L, OPEN ? g.own_start - 32u : g.s0,
-                                (OPEN || g.inside) ? kXNone : kXMod, t, sp, rl, lane);
+                                (OPEN || inside) ? kXNone : kXMod, t, sp, rl, lane);
             uint32_t Eq[Q][VMAX + 1];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
@@ -272,7 +284,7 @@ __device__ __forceinline__ uint32_t os_step(const RingDesc& R, uint8_t* __restri
     }
 
     // store the owned cells (they lie in [0, L) and start on a word boundary)
-    if (Q == 1 && g.inside && g.own_len == 32u * (64u * Q - 2u)) {
+    if (Q == 1 && inside && g.own_len == 32u * (64u * Q - 2u)) {
         // a whole tile: regroup through LDS into two contiguous 1 KiB stores,
         // without the halo words (chunks 0, 1 and 126, 127)
         uint32_t dd[8];
@@ -320,14 +332,18 @@ __device__ __forceinline__ void os_block(const RingDesc& R, uint32_t b, uint32_t
         if (lane == 0u) rl.n = 0u;
         uint32_t d[Q][8];
         uint32_t* stage = s_stage + 512u * wib;
-        // an open road's tiles that hold cell 0 or cells from L on take the
-        // open-road code; the others run the ring code (wave-uniform)
-        if (OPEN && !os_tile<Q>(R, tile).inside) {
-            os_load<Q, true>(R, R.buf[par], tile, lane, d, stage);
-            fl = os_step<VMAX, Q, true>(R, R.buf[par ^ 1u], tile, t, run, lane, d, rl, stage);
+        // the code of the tile's kind (wave-uniform): an open road's tiles
+        // inside [0, L) run the ring's code
+        uint8_t* __restrict__ dst = R.buf[par ^ 1u];
+        if (os_tile<Q>(R, tile).inside) {
+            os_load<Q, kTileInside>(R, R.buf[par], tile, lane, d, stage);
+            fl = os_step<VMAX, Q, kTileInside>(R, dst, tile, t, run, lane, d, rl, stage);
+        } else if constexpr (OPEN) {
+            os_load<Q, kTileOpenEdge>(R, R.buf[par], tile, lane, d, stage);
+            fl = os_step<VMAX, Q, kTileOpenEdge>(R, dst, tile, t, run, lane, d, rl, stage);
         } else {
-            os_load<Q, false>(R, R.buf[par], tile, lane, d, stage);
-            fl = os_step<VMAX, Q, false>(R, R.buf[par ^ 1u], tile, t, run, lane, d, rl, stage);
+            os_load<Q, kTileRingEdge>(R, R.buf[par], tile, lane, d, stage);
+            fl = os_step<VMAX, Q, kTileRingEdge>(R, dst, tile, t, run, lane, d, rl, stage);
         }
     }
     const uint32_t wtot = wave_total(fl);
