@@ -1,6 +1,7 @@
 """GPU parity of the open road (entry at cell 0, exit after cell L-1) against the
-CPU oracle, element by element: every kernel (byte-wise one-step, bit-sliced
-k-step for every (k, q)), tiny and ragged roads, every vmax, the gate
+CPU oracle, element by element: every kernel (byte-wise one-step and its
+tiles at the road's end, bit-sliced k-step for every (k, q)), tiny and ragged
+roads, every vmax, the gate
 extremes (alpha, beta in {0, 1}), flux logs, snapshots, split launch
 sequences, graph replay, checkpoint restore, and windows of a 2^30-cell road.
 Integer work: the bar is bit-exact equality."""
@@ -46,6 +47,23 @@ def test_tiny_and_ragged_roads(L):
     for alpha, beta in GATES:
         for kernel in ("kstep", "onestep"):
             _run_and_compare(L, L // 3, 5, 0.3, L + 5, 50, alpha, beta, kernel=kernel)
+
+
+@pytest.mark.parametrize("vmax", [5, 8])
+def test_onestep_tile_edges(vmax):
+    """The one-step kernel's tiles of 1984 owned cells on open roads: a tile's
+    segment reaches 32 cells past it, so when the last tile owns fewer than
+    vmax cells the tile before it also holds cell L, where a closed exit puts
+    a stopped car its front cars can reach.  Roads of one tile and a few cells
+    more, segments that end just before, at and past L, and a closed, an open
+    and a random exit."""
+    own = 32 * (64 - 2)
+    lengths = [own, own + 1, own + 3, own + 7, own + 8, own + 31, own + 32, own + 33,
+               2 * own, 2 * own + 1, 2 * own + 7, 2 * own + 32, 3 * own + 5]
+    for i, L in enumerate(lengths):
+        for alpha, beta in ((0.5, 0.5), (1.0, 0.0), (0.7, 1.0)):
+            _run_and_compare(L, L // 4 + i, vmax, 0.13, 60 + i, 40, alpha, beta,
+                             kernel="onestep")
 
 
 @pytest.mark.parametrize("vmax", range(0, 9))
