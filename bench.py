@@ -644,13 +644,12 @@ def bench_single(args, cfg, rep, kernels):
         ops = kstep_ops_per_cell_update(cfg["vmax"], cfg["p"]) * value
         line["roofline"] = {"bound": "alu", "achieved": ops / 1e12, "peak": VALU_PEAK / 1e12,
                             "unit": "TOP/s", "frac": ops / VALU_PEAK, "traffic": None,
-                            "kernel": f"grid_kstep_kernel<{cfg['vmax']}, {info['q']}, false, "
-                                      f"false>"}
+                            "kernel": f"grid_kstep_kernel<{cfg['vmax']}, {info['q']}, false>"}
         if "onestep" in res:
             line["roofline_onestep"] = {
                 "bound": "hbm", "achieved": res["onestep"] * bpcu / 1e9, "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": res["onestep"] * bpcu / HBM_PEAK, "traffic": None,
-                "kernel": f"grid_onestep_kernel<{cfg['vmax']}, 1>"}
+                "kernel": f"grid_onestep_kernel<{cfg['vmax']}, 1, false>"}
     if not args.no_cpu:
         line["cpu_baseline"] = _cpu_baseline(dict(kind="single", cfg=cfg, T=T,
                                                   budget=args.cpu_budget, rng=rng))
