@@ -43,6 +43,12 @@ def test_stratified_sample_spans_every_size():
     assert len(sample) == 1
 
 
+def test_sample_descriptions_use_ordinals():
+    assert [bench._ordinal(m) for m in (1, 2, 3, 4, 11, 12, 13, 21, 22, 23, 64, 101, 111)] == [
+        "1st", "2nd", "3rd", "4th", "11th", "12th", "13th", "21st", "22nd", "23rd", "64th",
+        "101st", "111th"]
+
+
 def test_median_of_chunks_times_only_after_the_warm_up():
     calls = []
 
