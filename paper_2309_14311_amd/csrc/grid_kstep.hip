@@ -286,40 +286,43 @@ __device__ __forceinline__ void kstep_tile(const RingDesc& R, const TileItem it,
     }
 }
 
+// Blocks of one wave: a wave's slot frees as soon as its tile is done, which
+// matters where the tiles' work differs (an ensemble's rings differ in vmax,
+// p and density).  Blocks of 2, 4 and 8 waves measured 0.5, 2 and 3.5 % slower
+// on the ensemble (the same on one large ring).
+//
 // All items of a launch share vmax (and the boundary): one specialisation.
 template <int VMAX, int Q, bool OPEN>
-__global__ __launch_bounds__(256) void grid_kstep_kernel(const RingDesc* __restrict__ rings,
-                                                         const TileItem* __restrict__ items,
-                                                         uint32_t n_items, uint32_t* partials,
-                                                         uint32_t k, const Clock* __restrict__ clk,
-                                                         uint32_t s_off, uint32_t launch_idx) {
-    __shared__ RefineLds<Q> s_ref[4];
-    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t wave = blockIdx.x * 4u + wib;
+__global__ __launch_bounds__(64) void grid_kstep_kernel(const RingDesc* __restrict__ rings,
+                                                        const TileItem* __restrict__ items,
+                                                        uint32_t n_items, uint32_t* partials,
+                                                        uint32_t k, const Clock* __restrict__ clk,
+                                                        uint32_t s_off, uint32_t launch_idx) {
+    __shared__ RefineLds<Q> s_ref;
+    const uint32_t wave = blockIdx.x;
     if (wave >= n_items) return;
     const TileItem it = items[wave];
-    kstep_tile<VMAX, Q, OPEN>(rings[it.ring], it, wave, n_items, partials, threadIdx.x & 63u, k,
-                              clk, s_off, launch_idx, s_ref[wib]);
+    kstep_tile<VMAX, Q, OPEN>(rings[it.ring], it, wave, n_items, partials, threadIdx.x, k, clk,
+                              s_off, launch_idx, s_ref);
 }
 
 // Items of different vmax in one launch: the branch on the ring's vmax is
 // uniform over the wave.  OPEN: every ring of the launch is an open road.
 template <int Q, bool OPEN>
-__global__ __launch_bounds__(256) void grid_kstep_mixed_kernel(const RingDesc* __restrict__ rings,
-                                                               const TileItem* __restrict__ items,
-                                                               uint32_t n_items, uint32_t* partials,
-                                                               uint32_t k,
-                                                               const Clock* __restrict__ clk,
-                                                               uint32_t s_off,
-                                                               uint32_t launch_idx) {
-    __shared__ RefineLds<Q> s_ref[4];
-    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t wave = blockIdx.x * 4u + wib;
+__global__ __launch_bounds__(64) void grid_kstep_mixed_kernel(const RingDesc* __restrict__ rings,
+                                                              const TileItem* __restrict__ items,
+                                                              uint32_t n_items, uint32_t* partials,
+                                                              uint32_t k,
+                                                              const Clock* __restrict__ clk,
+                                                              uint32_t s_off,
+                                                              uint32_t launch_idx) {
+    __shared__ RefineLds<Q> s_ref;
+    const uint32_t wave = blockIdx.x;
     if (wave >= n_items) return;
     const TileItem it = items[wave];
     const RingDesc& R = rings[it.ring];
-    const uint32_t lane = threadIdx.x & 63u;
-    RefineLds<Q>& rl = s_ref[wib];
+    const uint32_t lane = threadIdx.x;
+    RefineLds<Q>& rl = s_ref;
     switch (R.vmax) {
         case 0: kstep_tile<0, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
         case 1: kstep_tile<1, Q, OPEN>(R, it, wave, n_items, partials, lane, k, clk, s_off, launch_idx, rl); break;
@@ -342,10 +345,10 @@ hipError_t launch_q(uint32_t vmax, bool open, dim3 grid, hipStream_t s, const Ri
 #define NASCH_KSTEP_CASE(V)                                                                      \
     case V:                                                                                      \
         if (open)                                                                                \
-            NASCH_LAUNCH((grid_kstep_kernel<V, Q, true>), grid, dim3(256), 0, s, rings,          \
+            NASCH_LAUNCH((grid_kstep_kernel<V, Q, true>), grid, dim3(64), 0, s, rings,          \
                          items, n_items, partials, k, clk, s_off, launch_idx);                   \
         else                                                                                     \
-            NASCH_LAUNCH((grid_kstep_kernel<V, Q, false>), grid, dim3(256), 0, s, rings,         \
+            NASCH_LAUNCH((grid_kstep_kernel<V, Q, false>), grid, dim3(64), 0, s, rings,         \
                          items, n_items, partials, k, clk, s_off, launch_idx);                   \
         break;
     switch (vmax) {
@@ -360,10 +363,10 @@ hipError_t launch_q(uint32_t vmax, bool open, dim3 grid, hipStream_t s, const Ri
         NASCH_KSTEP_CASE(8)
         case kMixedVmax:
             if (open)
-                NASCH_LAUNCH((grid_kstep_mixed_kernel<Q, true>), grid, dim3(256), 0, s, rings,
+                NASCH_LAUNCH((grid_kstep_mixed_kernel<Q, true>), grid, dim3(64), 0, s, rings,
                              items, n_items, partials, k, clk, s_off, launch_idx);
             else
-                NASCH_LAUNCH((grid_kstep_mixed_kernel<Q, false>), grid, dim3(256), 0, s, rings,
+                NASCH_LAUNCH((grid_kstep_mixed_kernel<Q, false>), grid, dim3(64), 0, s, rings,
                              items, n_items, partials, k, clk, s_off, launch_idx);
             break;
         default:
@@ -379,7 +382,7 @@ hipError_t launch_grid_kstep(uint32_t vmax, bool open, uint32_t q, const RingDes
                              uint32_t k, const Clock* clk, uint32_t s_off, uint32_t launch_idx,
                              hipStream_t s) {
     if (n_items == 0) return hipSuccess;
-    const dim3 grid((n_items + 3u) / 4u);
+    const dim3 grid(n_items);
     switch (q) {
         case 1: return launch_q<1>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
         case 2: return launch_q<2>(vmax, open, grid, s, rings, items, n_items, partials, k, clk, s_off, launch_idx);
