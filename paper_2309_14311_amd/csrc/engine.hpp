@@ -395,16 +395,27 @@ inline hipError_t autotune_grid(const std::vector<RingDesc>& rings, uint32_t t_n
         bytes += 2 * plane_bytes(r);
         cells += r.L;
     }
+    // a ring that keeps a flux log is timed with one (a scratch log of the
+    // timed steps): F(t) of every step costs each wave a sum and a store per
+    // step, and a launch a fold, which favours fewer, longer segments
+    const auto candidates = kstep_candidates(rings);
+    uint32_t kmax = 1;
+    for (auto kq : candidates) kmax = std::max(kmax, kq.first);
+    const uint64_t log_len = (uint64_t)std::max(steps, kmax) + kmax;
+    uint64_t n_logs = 0;
+    for (const RingDesc& r : rings) n_logs += r.flux_log ? 1u : 0u;
     uint8_t* arena = nullptr;
+    unsigned long long* logs = nullptr;
     Clock* d_clk = nullptr;
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = dev_alloc(&arena, bytes);
+    if (e == hipSuccess && n_logs) e = dev_alloc(&logs, n_logs * log_len);
     if (e == hipSuccess) e = dev_alloc(&d_clk, 1);
     if (e == hipSuccess) e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     GridEngine scratch;
     if (e == hipSuccess) {
-        uint64_t off = 0;
+        uint64_t off = 0, ilog = 0;
         for (const RingDesc& r : rings) {
             RingDesc c = r;
             const uint64_t sz = plane_bytes(r);
@@ -412,7 +423,8 @@ inline hipError_t autotune_grid(const std::vector<RingDesc>& rings, uint32_t t_n
             c.pl[0] = reinterpret_cast<uint32_t*>(arena + off);
             c.pl[1] = reinterpret_cast<uint32_t*>(arena + off + sz);
             off += 2 * sz;
-            c.flux_log = nullptr;
+            c.flux_log = r.flux_log ? logs + (ilog++) * log_len : nullptr;
+            c.log_t0 = t_now;   // the clock stays at t_now: entries 0 .. T - 1
             c.flux_acc = nullptr;
             c.t = 0;
             c.parity = 0;
@@ -427,7 +439,7 @@ inline hipError_t autotune_grid(const std::vector<RingDesc>& rings, uint32_t t_n
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_clk, &c0, sizeof(Clock), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    for (auto kq : kstep_candidates(rings)) {
+    for (auto kq : candidates) {
         if (e != hipSuccess) break;
         if (!scratch.geometry_ok(kq.first, kq.second)) continue;
         e = scratch.set_geometry(kq.first, kq.second, s);
@@ -462,6 +474,7 @@ inline hipError_t autotune_grid(const std::vector<RingDesc>& rings, uint32_t t_n
     if (b) (void)hipEventDestroy(b);
     scratch.release();
     if (d_clk) (void)hipFree(d_clk);
+    if (logs) (void)hipFree(logs);
     if (arena) (void)hipFree(arena);
     return e;
 }
