@@ -199,29 +199,9 @@ struct GridEngine {
         }
         if (n_open != 0 && n_open != rings.size()) return hipErrorInvalidValue;   // all or none
         launch_open = n_open != 0;
-        bool any_log = false;
         for (uint32_t ri : order) {
             rings[ri].first_item = (uint32_t)items.size();
             for (uint32_t t = 0; t < rings[ri].ntiles; ++t) items.push_back(TileItem{ri, t});
-            any_log = any_log || rings[ri].flux_log != nullptr;
-        }
-        if (!onestep && !any_log) {
-            // no fold reads the partials ring by ring, so a ring's tiles need
-            // not be adjacent: every tile by its own work, a tile whose words
-            // draw across 32-cell block edges (the ends of a ring whose length
-            // is not a multiple of 32, and every tile of a ring shorter than a
-            // segment) weighing more
-            const uint32_t seg = kstep_segment(qq);
-            auto tile_cost = [&](const TileItem& it) {
-                const RingDesc& r = rings[it.ring];
-                const bool edge = (r.L & 31u) != 0u && (it.tile == 0u || it.tile + 1u == r.ntiles);
-                const uint32_t w = r.L < seg ? 5u : (edge ? 3u : 2u);
-                return (uint64_t)word_step_cost(r) * w;
-            };
-            std::stable_sort(items.begin(), items.end(),
-                             [&](const TileItem& a, const TileItem& b) {
-                                 return tile_cost(a) > tile_cost(b);
-                             });
         }
         launch_vmax = (vmin == vmaxx) ? vmin : kMixedVmax;
         k = kk;
